@@ -1,0 +1,217 @@
+/*
+ * sdfdock.h - C ABI of the MI355X (gfx950) shape-complementarity scoring
+ * library: skeletal density functions (SDFs) of two solids and the
+ * cross-correlation score over rigid placements, after Behandish & Ilies,
+ * "Shape Complementarity Analysis for Objects of Arbitrary Shape"
+ * (tech. report CDL-TR-14-01, 2014; arXiv 1712.00238).
+ *
+ * The paper poses the problem as: given a fixed solid S1 and a moving solid
+ * S2, score every relative placement tau in SE(3) by
+ *     f(tau) = integral rho_1(p) rho_2(tau^-1 p) dv                 (eq. 8)
+ * where rho is the skeletal density function of eq. 13 / 15 / 16c / 17t,
+ * and return the placements with the highest scores (Formulation section).
+ * Rigid motions are split into a rotation set times all grid translations,
+ * and each rotation's translations are scored at once through FFTs
+ * (Implementation section).
+ *
+ * Conventions used by every call
+ * ------------------------------
+ *  - Memory: every array argument is a caller-owned DEVICE pointer unless
+ *    marked (host).  The library never frees or retains caller memory.
+ *    Device arrays must be 16-byte aligned (any allocation from hipMalloc or
+ *    PyTorch qualifies).
+ *  - Precision: a context has a dtype.  SDF_F32 contexts take and return
+ *    float (real) / float2 (complex) arrays, SDF_F64 contexts double /
+ *    double2.  "real" and "complex" below mean the context's type.  Rotation
+ *    matrices, sub-voxel offsets and pose gradients are computed in FP64 in
+ *    both precisions.
+ *  - Complex arrays are interleaved (re, im).
+ *  - Grids: sdf_grid.n = (nx, ny, nz) nodes, node (i, j, k) at world
+ *    origin + h * (i, j, k); arrays are [k][j][i] with i fastest, flat index
+ *    (k * ny + j) * nx + i.  Planar (2D) work uses nz = 1, samples with
+ *    z = 0 and in-plane normals, rotations about +z.
+ *  - Moving body box: a grid of N_M^3 (or N_M^2 x 1) nodes whose node k sits
+ *    at body position x_k = h (k - N_M / 2) relative to the body origin;
+ *    g_moving.origin is the world position of node 0 in the moving part's
+ *    own frame (body origin - h N_M / 2).
+ *  - Pose (R, t): the body point x goes to R x + o_F + h t, with o_F the
+ *    fixed grid origin and t in grid units.  Scores of integer t are
+ *        f(R, t) = Re sum_p rho_F(p) M_R((p - t) mod N),
+ *        M_R(u)  = sum_k c_k B3(u - R x_k / h),  c_k = w_k rho_M(x_k),
+ *    B3 the tensor cubic B-spline (the grid is periodic).
+ *  - Quaternions are (w, x, y, z), Hamilton convention, R = R(q / |q|).
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = the null
+ *    stream).  A context is not thread-safe: use one per thread / stream.
+ *  - Return value: SDF_OK (0) or a negative error code.  On error nothing
+ *    was enqueued, inputs are untouched, outputs are unspecified and
+ *    sdf_last_error() holds a message.  Faults inside kernels surface at the
+ *    caller's next synchronisation.  No C++ exception crosses the ABI.
+ */
+#ifndef SDFDOCK_H
+#define SDFDOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sdf_ctx_s *sdf_ctx;
+typedef void *sdf_stream; /* a hipStream_t */
+
+typedef enum { SDF_F32 = 0, SDF_F64 = 1 } sdf_dtype;
+
+enum {
+    SDF_OK = 0,
+    SDF_EINVAL = -1,       /* null pointer, bad size / shape, non-finite parameter, zero quaternion */
+    SDF_EUNSUPPORTED = -2, /* FFT size outside {8, 16, 32, 64, 96, 128}, dtype / device mismatch */
+    SDF_EHIP = -3,         /* HIP runtime error while enqueueing */
+    SDF_ENOMEM = -4        /* workspace would exceed the context's cap, or allocation failed */
+};
+
+typedef struct {
+    int32_t n[3];      /* nodes per axis (x, y, z); n[2] = 1 for planar work */
+    double origin[3];  /* world position of node (0, 0, 0) */
+    double h;          /* node spacing (> 0); both parts of a pair use the same h */
+} sdf_grid;
+
+/* Affinity parameters (eq. 15 / 16c / 17t): lambda1 > 0 weights exterior
+ * points, lambda2 > 0 interior points, sigma > 0 is the thickness factor,
+ * eps >= 0 the truncation factor of the contact region, xi_floor >= 0 the
+ * distance below which a node counts as on the boundary (rho := 0 there).
+ * The planar validation runs use lambda1 = 1, lambda2 = 3, sigma = 0.5,
+ * eps = 1.5. */
+typedef struct {
+    double lambda1, lambda2, sigma, eps, xi_floor;
+} sdf_params;
+
+/* ------------------------------------------------------------------ context */
+
+/* Create a context on HIP device `device`.  `workspace_cap_bytes` bounds the
+ * device workspace the context may hold (0 = no cap).  Workspace grows
+ * lazily on the first call that needs it and is reused afterwards.
+ * Errors: SDF_EINVAL (out == NULL, bad dtype), SDF_EHIP (no such device). */
+int sdf_ctx_create(sdf_ctx *out, int device, sdf_dtype dtype, size_t workspace_cap_bytes);
+
+/* Release the workspace, cached plans and graphs.  Synchronises the device
+ * first.  NULL is ignored. */
+void sdf_ctx_destroy(sdf_ctx ctx);
+
+/* Message of the last failing call on `ctx` (or of the last failing call
+ * on this thread when ctx is NULL).  Valid until the next call. */
+const char *sdf_last_error(sdf_ctx ctx);
+
+/* Tuning options (integers):
+ *   "path"          0 auto, 1 plain multi-pass kernels, 2 fused kernels (F32 only)
+ *   "batch"         rotations per fused launch sequence (even, 2..256; default 64)
+ *   "graph"         1: capture each batch's launch sequence in a hipGraph and replay it
+ *   "pencil_group"  rotations sharing one spectrum tile in the fused pencil pass (2 or 4)
+ * Errors: SDF_EINVAL for an unknown key or out-of-range value. */
+int sdf_ctx_set_option(sdf_ctx ctx, const char *key, int64_t value);
+int sdf_ctx_get_option(sdf_ctx ctx, const char *key, int64_t *value);
+
+/* ------------------------------------------------------- skeletal density */
+
+/* Skeletal density function of one solid on a grid (eq. 10A, 11, 12a, 13,
+ * 15, 16c, 17t), by point quadrature over oriented boundary samples:
+ *   xi_abs = min_j |p - q_j|, j* its lowest-index minimiser,
+ *   pmc    = sign((p - q_j*) . n_j*),
+ *   rho(p) = 0 if pmc = 0 or xi_abs < xi_floor, else
+ *            lambda / (2 pi sigma xi_abs^2) *
+ *            sum_{j : |p - q_j| <= (1 + eps) xi_abs} w_j cos(theta_j) G(r_j) P(r_j) / (1 + r_j^2)^2
+ *   with r = |p - q| / xi_abs, cos(theta) = (p - q) . n / |p - q|,
+ *   G(r) = exp(-(r - 1)^2 / (2 sigma^2)), exterior (pmc > 0): lambda = lambda1,
+ *   P = (1 - i r)^2; interior: lambda = -lambda2, P = (1 + i r)^2
+ *   (this is eq. 13 with the kernel of eq. 15 and zeta = xi + i eta).
+ * q, nrm: n x 3 real (positions, outward unit normals); w: n real weights
+ * (area elements; arc lengths in 2D).  rho_out: complex, g->n[0]*n[1]*n[2].
+ * g, p: host structs.  Any grid shape is accepted.
+ * Errors: SDF_EINVAL (null pointer, n <= 0, bad grid, invalid params). */
+int sdf_build(sdf_ctx ctx, const void *q, const void *nrm, const void *w, int64_t n,
+              const sdf_grid *g, const sdf_params *p, void *rho_out, sdf_stream stream);
+
+/* Spectrum of the fixed part for the correlation (eq. 8):
+ * spec_out(k) = N^-3 * sum_p rho_fixed(p) exp(-2 pi i k.p / N)  (N^-2 in 2D),
+ * complex, same layout as the grid.  The grid must be N^3 or N^2 x 1 with N
+ * in {8, 16, 32, 64, 96, 128}.  rho_fixed and spec_out may not alias.
+ * Errors: SDF_EINVAL, SDF_EUNSUPPORTED. */
+int sdf_spectrum(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g, void *spec_out, sdf_stream stream);
+
+/* ------------------------------------------------------------ the search */
+
+/* Score every integer translation of every rotation and reduce each rotation
+ * to its peak (the search of the Formulation section; per-rotation FFT
+ * correlation of the Implementation section).
+ *   spec_fixed: output of sdf_spectrum for g_fixed.
+ *   rho_moving: complex N_M^3 (or N_M^2 x 1) SDF of the moving part on its body
+ *               box; w_moving: real, same size, per-node volume weights (h^3,
+ *               h^2 in 2D, for the plain quadrature of eq. 8).
+ *   quats (host): n_rot x 4 FP64 quaternions (non-zero, finite).
+ * Outputs per rotation r (device):
+ *   peak_score[r]   real, s = max_t Re f(R, t)
+ *   peak_t[3r..]    int32 (tx, ty, tz) of the lowest flat index attaining s
+ *   peak_nbhd[27r..] real, Re f at t* + (dx, dy, dz), offsets in {-1, 0, 1},
+ *                   dz slowest, dx fastest, periodic (may be NULL)
+ *   refined_t[3r..] FP64, t* + per-axis parabola vertex offset clamped to
+ *                   [-1/2, 1/2], 0 where the curvature is not negative (may be NULL)
+ * Constraints: h equal for both grids; the rotated body box plus its
+ * stencil fits the periodic grid: ceil(sqrt(3) N_M) + 4 <= N in 3D,
+ * ceil(sqrt(2) N_M) + 4 <= N in 2D.
+ * Errors: SDF_EINVAL, SDF_EUNSUPPORTED, SDF_EHIP, SDF_ENOMEM. */
+int score_rotations(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
+                    const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
+                    const double *quats, int64_t n_rot,
+                    void *peak_score, int32_t *peak_t, void *peak_nbhd, double *refined_t,
+                    sdf_stream stream);
+
+/* Full score volumes Re f(R, t) for every t of each rotation: vol_out is
+ * real, n_rot x (grid size), same layout as the grid.  Same inputs and
+ * constraints as score_rotations. */
+int score_volume(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
+                 const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
+                 const double *quats, int64_t n_rot, void *vol_out, sdf_stream stream);
+
+/* The rotated spread M_R on the fixed grid (complex, n_rot x grid size),
+ * samples at +R x_k / h (not reflected).  Same constraints. */
+int sdf_spread(sdf_ctx ctx, const sdf_grid *g_fixed, const void *rho_moving, const void *w_moving,
+               const sdf_grid *g_moving, const double *quats, int64_t n_rot, void *grid_out,
+               sdf_stream stream);
+
+/* Unnormalised 3D (or 2D when nz = 1) DFT of a complex grid, out of place:
+ * direction -1: out(k) = sum_p in(p) exp(-2 pi i k.p / N); +1: exp(+...).
+ * Grid N^3 or N^2 x 1, N in {8, 16, 32, 64, 96, 128}. */
+int sdf_fft(sdf_ctx ctx, const void *in, void *out, const sdf_grid *g, int direction, sdf_stream stream);
+
+/* Top-k rotations by score: indices (int32, k) ordered by score descending,
+ * ties by lower index.  scores: real, n.  1 <= k <= n. */
+int sdf_topk(sdf_ctx ctx, const void *scores, int64_t n, int64_t k, int32_t *idx_out, sdf_stream stream);
+
+/* ------------------------------------------------------------ refinement */
+
+/* Pose value and gradients for gradient-based refinement (the validation
+ * section's CG search over the score):
+ *   f(t, q) = Re sum_k c_k Phi(R x_k / h + t),  Phi(y) = sum_p rho_F(p) B3(p - y),
+ * which equals score_rotations' f(R, t) at integer t.
+ *   rho_fixed: the fixed part's spatial SDF grid (not its spectrum).
+ *   poses: B x 7 FP64 (t[3] in grid units, q[4] quaternion), device.
+ *   score: real, B (required).
+ *   grad_pose: FP64 B x 7 (df/dt, df/dq through R(q/|q|)), accumulated in FP64
+ *              (may be NULL).
+ *   grad_w: real N_M^3, sum over poses b of grad_scale[b] * Re(rho_M(x_k) Phi_b(y_k))
+ *           (may be NULL).  grad_scale: FP64 B, device, NULL = all ones.
+ * The B-spline stencil is recomputed, never stored.  Non-finite poses give
+ * non-finite outputs for that pose.  Grid constraints as score_rotations
+ * except that any N >= 4 works.
+ * Errors: SDF_EINVAL, SDF_EHIP, SDF_ENOMEM. */
+int score_grad(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
+               const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
+               const double *poses, int64_t B,
+               void *score, double *grad_pose, void *grad_w, const double *grad_scale,
+               sdf_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SDFDOCK_H */

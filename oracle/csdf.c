@@ -47,14 +47,15 @@ void oracle_sdf_points(const double *q, const double *nrm, const double *w, long
 #pragma omp parallel for schedule(dynamic, 16)
     for (long a = 0; a < npts; ++a) {
         const double px = pts[3 * a], py = pts[3 * a + 1], pz = pts[3 * a + 2];
-        /* pass 1: nearest sample */
-        double best = INFINITY;
+        /* pass 1: nearest sample (squared distances share the minimiser) */
+        double best2 = INFINITY;
         long jbest = -1;
         for (long j = 0; j < ns; ++j) {
             double dx = px - q[3 * j], dy = py - q[3 * j + 1], dz = pz - q[3 * j + 2];
-            double d = sqrt(dx * dx + dy * dy + dz * dz);
-            if (d < best) { best = d; jbest = j; }
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (d2 < best2) { best2 = d2; jbest = j; }
         }
+        double best = sqrt(best2);
         double dot = (px - q[3 * jbest]) * nrm[3 * jbest] + (py - q[3 * jbest + 1]) * nrm[3 * jbest + 1] +
                      (pz - q[3 * jbest + 2]) * nrm[3 * jbest + 2];
         int pmc = dot > 0.0 ? 1 : (dot < 0.0 ? -1 : 0);
@@ -80,11 +81,18 @@ void oracle_sdf_points(const double *q, const double *nrm, const double *w, long
         if (pmc != 0 && xi_abs >= xi_floor) {
             double lam = pmc > 0 ? lambda1 : -lambda2;
             double radius = (1.0 + eps) * xi_abs;
+            /* samples farther than the band around the contact sphere can
+               neither contribute nor matter to the diagnostics */
+            double reach = radius * (1.0 + band_rel) + 1e-300;
+            double reach2 = reach * reach;
             for (long j = 0; j < ns; ++j) {
                 double dx = px - q[3 * j], dy = py - q[3 * j + 1], dz = pz - q[3 * j + 2];
-                double eta = sqrt(dx * dx + dy * dy + dz * dz);
+                double d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 > reach2 && !out_trunc_margin) continue;
+                double eta = sqrt(d2);
                 double m = fabs(eta - radius) / xi_abs;
                 if (m < margin) margin = m;
+                if (eta > radius && m > band_rel) continue;
                 double complex zeta = xi + I * eta;
                 double tan_abs = eta / xi_abs; /* |tan arg zeta| = |Im / Re| */
                 double x = tan_abs - 1.0;

@@ -1,0 +1,185 @@
+"""Python binding of the sdfdock C ABI: argument marshalling only.
+
+Every computation runs in the HIP library; these wrappers allocate output
+tensors with PyTorch, pass raw device pointers and the current HIP stream,
+and raise on any non-zero return code.  Grids and parameters are any
+objects with the fields of ``workloads.configs.GridSpec`` / ``SDFParams``.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+
+_REAL = {"f32": torch.float32, "f64": torch.float64}
+_CPLX = {"f32": torch.complex64, "f64": torch.complex128}
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Context:
+    """An sdfdock context on one GPU.  dtype "f32" or "f64"."""
+
+    def __init__(self, device: int = 0, dtype: str = "f32", workspace_cap: int = 0):
+        if dtype not in _REAL:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        self.lib = _lib.load()
+        self.dtype = dtype
+        self.device = torch.device("cuda", device)
+        h = ctypes.c_void_p()
+        _lib.check(self.lib.sdf_ctx_create(ctypes.byref(h), device, _lib.SDF_F64 if dtype == "f64" else _lib.SDF_F32,
+                                           workspace_cap))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.sdf_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def real(self):
+        return _REAL[self.dtype]
+
+    @property
+    def cplx(self):
+        return _CPLX[self.dtype]
+
+    def _check(self, rc):
+        _lib.check(rc, self.handle)
+
+    def set_option(self, key: str, value: int):
+        self._check(self.lib.sdf_ctx_set_option(self.handle, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = ctypes.c_int64()
+        self._check(self.lib.sdf_ctx_get_option(self.handle, key.encode(), ctypes.byref(v)))
+        return v.value
+
+    def _dev(self, a, dtype):
+        if isinstance(a, np.ndarray):
+            a = torch.from_numpy(a)
+        return a.to(device=self.device, dtype=dtype).contiguous()
+
+    # ------------------------------------------------------------------ SDF
+    def sdf_build(self, q, n, w, grid, params, out=None):
+        """Skeletal density function of one solid on ``grid`` -> complex (nz, ny, nx)."""
+        q = self._dev(q, self.real)
+        n = self._dev(n, self.real)
+        w = self._dev(w, self.real)
+        nx, ny, nz = grid.n
+        if out is None:
+            out = torch.empty((nz, ny, nx), dtype=self.cplx, device=self.device)
+        g = _lib.make_grid(grid)
+        p = _lib.make_params(params)
+        self._check(self.lib.sdf_build(self.handle, _ptr(q), _ptr(n), _ptr(w), int(w.numel()), ctypes.byref(g),
+                                       ctypes.byref(p), _ptr(out), _stream(self.device)))
+        return out
+
+    def spectrum(self, rho_fixed, grid, out=None):
+        rho_fixed = self._dev(rho_fixed, self.cplx)
+        if out is None:
+            out = torch.empty_like(rho_fixed)
+        g = _lib.make_grid(grid)
+        self._check(self.lib.sdf_spectrum(self.handle, _ptr(rho_fixed), ctypes.byref(g), _ptr(out),
+                                          _stream(self.device)))
+        return out
+
+    # ------------------------------------------------------------------ search
+    def score_rotations(self, spec, g_fixed, rho_moving, w_moving, g_moving, quats, nbhd=True, refined=True,
+                        out=None):
+        """Per-rotation peaks.  Returns dict(score, t, nbhd, refined)."""
+        q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+        n_rot = len(q)
+        spec = self._dev(spec, self.cplx)
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        if out is None:
+            out = {"score": torch.empty(n_rot, dtype=self.real, device=self.device),
+                   "t": torch.empty((n_rot, 3), dtype=torch.int32, device=self.device),
+                   "nbhd": torch.empty((n_rot, 27), dtype=self.real, device=self.device) if nbhd else None,
+                   "refined": torch.empty((n_rot, 3), dtype=torch.float64, device=self.device) if refined else None}
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.score_rotations(self.handle, _ptr(spec), ctypes.byref(gf), _ptr(rm), _ptr(wm),
+                                             ctypes.byref(gm), q.ctypes.data_as(ctypes.c_void_p), n_rot,
+                                             _ptr(out["score"]), _ptr(out["t"]), _ptr(out["nbhd"]),
+                                             _ptr(out["refined"]), _stream(self.device)))
+        return out
+
+    def score_volume(self, spec, g_fixed, rho_moving, w_moving, g_moving, quats):
+        q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+        spec = self._dev(spec, self.cplx)
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        nx, ny, nz = g_fixed.n
+        out = torch.empty((len(q), nz, ny, nx), dtype=self.real, device=self.device)
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.score_volume(self.handle, _ptr(spec), ctypes.byref(gf), _ptr(rm), _ptr(wm),
+                                          ctypes.byref(gm), q.ctypes.data_as(ctypes.c_void_p), len(q), _ptr(out),
+                                          _stream(self.device)))
+        return out
+
+    def spread(self, g_fixed, rho_moving, w_moving, g_moving, quats):
+        q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        nx, ny, nz = g_fixed.n
+        out = torch.empty((len(q), nz, ny, nx), dtype=self.cplx, device=self.device)
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.sdf_spread(self.handle, ctypes.byref(gf), _ptr(rm), _ptr(wm), ctypes.byref(gm),
+                                        q.ctypes.data_as(ctypes.c_void_p), len(q), _ptr(out), _stream(self.device)))
+        return out
+
+    def fft(self, x, grid, direction: int = -1):
+        x = self._dev(x, self.cplx)
+        out = torch.empty_like(x)
+        g = _lib.make_grid(grid)
+        self._check(self.lib.sdf_fft(self.handle, _ptr(x), _ptr(out), ctypes.byref(g), int(direction),
+                                     _stream(self.device)))
+        return out
+
+    def topk(self, scores, k: int):
+        scores = self._dev(scores, self.real)
+        out = torch.empty(k, dtype=torch.int32, device=self.device)
+        self._check(self.lib.sdf_topk(self.handle, _ptr(scores), int(scores.numel()), int(k), _ptr(out),
+                                      _stream(self.device)))
+        return out
+
+    # ------------------------------------------------------------------ refinement
+    def score_grad(self, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, want_pose=True,
+                   want_w=False, grad_scale=None):
+        poses = self._dev(poses, torch.float64).reshape(-1, 7)
+        B = poses.shape[0]
+        rf = self._dev(rho_fixed, self.cplx)
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        score = torch.empty(B, dtype=self.real, device=self.device)
+        gp = torch.empty((B, 7), dtype=torch.float64, device=self.device) if want_pose else None
+        gw = torch.empty(wm.shape, dtype=self.real, device=self.device) if want_w else None
+        gs = None if grad_scale is None else self._dev(grad_scale, torch.float64)
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.score_grad(self.handle, _ptr(rf), ctypes.byref(gf), _ptr(rm), _ptr(wm), ctypes.byref(gm),
+                                        _ptr(poses), B, _ptr(score), _ptr(gp), _ptr(gw), _ptr(gs),
+                                        _stream(self.device)))
+        return score, gp, gw

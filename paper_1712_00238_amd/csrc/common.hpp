@@ -1,0 +1,83 @@
+// Shared device-side helpers of the sdfdock kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace sdf {
+
+template <typename T>
+struct __align__(2 * sizeof(T)) cplx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ __forceinline__ cplx<T> mk(T r, T i) {
+    cplx<T> c;
+    c.re = r;
+    c.im = i;
+    return c;
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> operator+(cplx<T> a, cplx<T> b) { return mk(a.re + b.re, a.im + b.im); }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator-(cplx<T> a, cplx<T> b) { return mk(a.re - b.re, a.im - b.im); }
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(cplx<T> a, cplx<T> b) {
+    return mk(a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re);
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> operator*(cplx<T> a, T s) { return mk(a.re * s, a.im * s); }
+template <typename T>
+__device__ __forceinline__ cplx<T> conj(cplx<T> a) { return mk(a.re, -a.im); }
+// multiply by +i (s = +1) or -i (s = -1)
+template <typename T, int S>
+__device__ __forceinline__ cplx<T> mul_i(cplx<T> a) {
+    return S > 0 ? mk(-a.im, a.re) : mk(a.im, -a.re);
+}
+
+// Cubic B-spline beta(s) and its derivative, piecewise cubic.
+template <typename T>
+__device__ __forceinline__ T bspline3(T s) {
+    T a = s < T(0) ? -s : s;
+    if (a < T(1)) return T(2) / T(3) - a * a + T(0.5) * a * a * a;
+    if (a < T(2)) {
+        T b = T(2) - a;
+        return b * b * b / T(6);
+    }
+    return T(0);
+}
+// Weights of the 4 stencil nodes floor(y)-1+i, i = 0..3, at fractional part f in [0, 1).
+template <typename T>
+__device__ __forceinline__ void bspline3_weights(T f, T w[4]) {
+    T g = T(1) - f;
+    T f2 = f * f, f3 = f2 * f;
+    w[0] = g * g * g / T(6);                               // beta(1 + f)
+    w[1] = T(2) / T(3) - f2 + T(0.5) * f3;                 // beta(f)
+    w[2] = T(2) / T(3) - g * g + T(0.5) * g * g * g;        // beta(1 - f)
+    w[3] = f3 / T(6);                                      // beta(2 - f)
+}
+// d/dy of beta(node - y) for the same 4 nodes: -beta'(node - y).
+template <typename T>
+__device__ __forceinline__ void bspline3_dweights(T f, T d[4]) {
+    T g = T(1) - f;
+    d[0] = -T(0.5) * g * g;            // node - y = -(1 + f): -beta'(-(1+f)) = -(1/2)(1-f)^2
+    d[1] = -T(2) * f + T(1.5) * f * f;  // node - y = -f
+    d[2] = T(2) * g - T(1.5) * g * g;   // node - y = 1 - f
+    d[3] = T(0.5) * f * f;              // node - y = 2 - f
+}
+
+__device__ __forceinline__ int wrap(int i, int n) {
+    int r = i % n;
+    return r < 0 ? r + n : r;
+}
+
+template <typename T>
+__device__ __forceinline__ T dev_floor(T x);
+template <>
+__device__ __forceinline__ float dev_floor<float>(float x) { return floorf(x); }
+template <>
+__device__ __forceinline__ double dev_floor<double>(double x) { return floor(x); }
+
+}  // namespace sdf

@@ -1,0 +1,290 @@
+"""GPU parity of each stage against the FP64 oracle, through the C ABI, at
+sizes the oracle finishes in seconds (several tiles, ragged tails)."""
+
+import numpy as np
+import pytest
+
+from helpers import flush_print, oracle_fields, score_rel_err, sdf_compare
+from oracle import correlate as oc
+from oracle import grad as og
+from oracle import peak as op
+from oracle import spread as osp
+from workloads import configs as C
+from workloads import rotations as wr
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    import torch  # noqa: F401
+    from paper_1712_00238_amd.api import Context
+    c32, c64 = Context(0, "f32"), Context(0, "f64")
+    yield {"f32": c32, "f64": c64}
+    c32.close()
+    c64.close()
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def upload_samples(ctx, s):
+    return s.q, s.n, s.w
+
+
+# ----------------------------------------------------------------------------- sdf_build
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sdf_build_planar_pair(ctxs, dtype):
+    pair = C.peg_in_hole_2d(seed=0)
+    ctx = ctxs[dtype]
+    for part in (pair.fixed, pair.moving):
+        flush_print("sdf_build planar", dtype, part.grid.n, part.samples.count)
+        rho = to_np(ctx.sdf_build(part.samples.q, part.samples.n, part.samples.w, part.grid, pair.params))
+        rel, band = (1e-10, 1e-10) if dtype == "f64" else (2e-5, 2e-5)
+        rep = sdf_compare(rho, part.samples, part.grid, pair.params, rel, band)
+        flush_print(rep)
+        assert rep["ok"], rep
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sdf_build_small_3d_ragged(ctxs, dtype):
+    pair = C.small_3d(seed=1, n=16, n_m=6)
+    ctx = ctxs[dtype]
+    # a ragged grid (not cubic, not a multiple of the block) and a ragged sample count
+    grid = C.GridSpec((15, 13, 11), (-7.3, -6.1, -5.2), 1.0)
+    s = pair.fixed.samples
+    flush_print("sdf_build 3d", dtype, grid.n, s.count)
+    rho = to_np(ctx.sdf_build(s.q, s.n, s.w, grid, pair.params))
+    rel, band = (1e-10, 1e-10) if dtype == "f64" else (2e-5, 2e-5)
+    rep = sdf_compare(rho, s, grid, pair.params, rel, band)
+    flush_print(rep)
+    assert rep["ok"], rep
+
+
+# ----------------------------------------------------------------------------- FFT
+
+@pytest.mark.parametrize("n,planar", [(8, False), (16, False), (32, False), (64, False), (96, False), (128, False),
+                                      (128, True), (96, True), (16, True)])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fft_matches_numpy_and_parseval(ctxs, n, planar, dtype):
+    ctx = ctxs[dtype]
+    rng = np.random.default_rng(n + (1000 if planar else 0))
+    shape = (1 if planar else n, n, n)
+    x = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    grid = C.GridSpec((n, n, shape[0]), (0.0, 0.0, 0.0), 1.0)
+    flush_print("fft", dtype, shape)
+    big = to_np(ctx.fft(x, grid, -1))
+    ref = np.fft.fftn(x)
+    tol = 1e-12 if dtype == "f64" else 2e-6
+    assert np.max(np.abs(big - ref)) <= tol * np.max(np.abs(ref)) * np.log2(x.size)
+    # Parseval and inverse round trip
+    assert abs((np.abs(big) ** 2).sum() / x.size - (np.abs(x) ** 2).sum()) <= 10 * tol * (np.abs(x) ** 2).sum()
+    back = to_np(ctx.fft(big, grid, +1)) / x.size
+    assert np.max(np.abs(back - x)) <= tol * np.log2(x.size) * np.max(np.abs(x)) * 4
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_spectrum_normalisation(ctxs, dtype):
+    ctx = ctxs[dtype]
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=(32, 32, 32)) + 1j * rng.normal(size=(32, 32, 32))
+    grid = C.GridSpec((32, 32, 32), (0, 0, 0), 1.0)
+    s = to_np(ctx.spectrum(x, grid))
+    ref = np.fft.fftn(x) / x.size
+    tol = 1e-12 if dtype == "f64" else 3e-6
+    assert np.max(np.abs(s - ref)) <= tol * np.max(np.abs(ref)) * 15
+
+
+# ----------------------------------------------------------------------------- spread
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["3d", "planar"])
+def test_spread_matches_oracle(ctxs, dtype, case):
+    ctx = ctxs[dtype]
+    rng = np.random.default_rng(21)
+    if case == "3d":
+        n, nm, planar = 32, 14, False
+        gf = C.GridSpec((n, n, n), (0, 0, 0), 1.0)
+        gm = C.GridSpec((nm, nm, nm), (0, 0, 0), 1.0)
+        shape = (nm, nm, nm)
+    else:
+        n, nm, planar = 32, 19, True
+        gf = C.GridSpec((n, n, 1), (0, 0, 0), 1.0)
+        gm = C.GridSpec((nm, nm, 1), (0, 0, 0), 1.0)
+        shape = (1, nm, nm)
+    rho_m = rng.normal(size=shape) + 1j * rng.normal(size=shape)
+    w = rng.uniform(0.5, 1.5, size=shape)
+    quats = wr.uniform_quaternions(3, 8) if not planar else wr.planar_rotations(37.0, 3)
+    flush_print("spread", case, dtype)
+    got = to_np(ctx.spread(gf, rho_m, w, gm, quats))
+    c = oc.moving_coefficients(rho_m, w)
+    for r, q in enumerate(quats):
+        ref = oc.rotated_spread(c, q, nm, got.shape[1:], planar)
+        tol = 1e-12 if dtype == "f64" else 2e-5
+        assert np.max(np.abs(got[r] - ref)) <= tol * np.max(np.abs(ref)), r
+
+
+# ----------------------------------------------------------------------------- correlation
+
+def small_case(n, nm, planar, seed):
+    rng = np.random.default_rng(seed)
+    if planar:
+        gf = C.GridSpec((n, n, 1), (0, 0, 0), 1.0)
+        gm = C.GridSpec((nm, nm, 1), (0, 0, 0), 1.0)
+        sf, sm = (1, n, n), (1, nm, nm)
+    else:
+        gf = C.GridSpec((n, n, n), (0, 0, 0), 1.0)
+        gm = C.GridSpec((nm, nm, nm), (0, 0, 0), 1.0)
+        sf, sm = (n, n, n), (nm, nm, nm)
+    rho_f = rng.normal(size=sf) + 1j * rng.normal(size=sf)
+    rho_m = rng.normal(size=sm) + 1j * rng.normal(size=sm)
+    w = rng.uniform(0.5, 1.5, size=sm)
+    return gf, gm, rho_f, rho_m, w
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,nm,planar", [(16, 6, False), (32, 14, False), (32, 19, True)])
+def test_score_volume_matches_oracle(ctxs, dtype, n, nm, planar):
+    ctx = ctxs[dtype]
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, planar, 31 + n)
+    quats = wr.uniform_quaternions(3, 9) if not planar else wr.planar_rotations(23.0, 3)
+    flush_print("score_volume", dtype, n, nm, planar)
+    spec = ctx.spectrum(rho_f, gf)
+    vol = to_np(ctx.score_volume(spec, gf, rho_m, w, gm, quats))
+    c = oc.moving_coefficients(rho_m, w)
+    for r, q in enumerate(quats):
+        ref = oc.score_volume(rho_f, c, q, nm, planar)
+        tol = 1e-11 if dtype == "f64" else 1e-5
+        assert np.max(np.abs(vol[r] - ref)) <= tol * np.max(np.abs(ref)), r
+
+
+def test_score_volume_direct_sum_tiny(ctxs):
+    # brute-force O(N^6) correlation on an 8^3 grid
+    ctx = ctxs["f64"]
+    gf, gm, rho_f, rho_m, w = small_case(8, 2, False, 3)
+    q = wr.uniform_quaternions(1, 4)
+    vol = to_np(ctx.score_volume(ctx.spectrum(rho_f, gf), gf, rho_m, w, gm, q))[0]
+    c = oc.moving_coefficients(rho_m, w)
+    ref = oc.score_volume(rho_f, c, q[0], 2, False, direct=True)
+    assert np.max(np.abs(vol - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("n,nm,planar,nrot,batch", [(16, 6, False, 7, 4), (32, 14, False, 5, 2), (32, 19, True, 9, 4),
+                                                    (8, 2, False, 3, 2), (96, 8, False, 3, 2)])
+def test_score_rotations_peaks_f32(ctxs, path, n, nm, planar, nrot, batch):
+    ctx = ctxs["f32"]
+    ctx.set_option("path", path)
+    ctx.set_option("batch", batch)
+    try:
+        gf, gm, rho_f, rho_m, w = small_case(n, nm, planar, 7 * n + nm)
+        quats = wr.uniform_quaternions(nrot, n) if not planar else wr.planar_rotations(17.0, nrot)
+        flush_print("score_rotations f32 path", path, n, nm, planar, nrot, batch)
+        out = ctx.score_rotations(ctx.spectrum(rho_f, gf), gf, rho_m, w, gm, quats)
+        s, t, nb, ref_t = (to_np(out[k]) for k in ("score", "t", "nbhd", "refined"))
+        c = oc.moving_coefficients(rho_m, w)
+        for r, q in enumerate(quats):
+            vol = oc.score_volume(rho_f, c, q, nm, planar)
+            s0, _, t0 = op.peak(vol)
+            scale = np.abs(vol).max()
+            assert abs(s[r] - s0) <= 2e-5 * scale, (r, s[r], s0)
+            if tuple(t[r]) != t0:  # a near-tie: the oracle's value there must match the max
+                v_at = vol[t[r][2], t[r][1], t[r][0]]
+                assert abs(v_at - s0) <= 2e-5 * scale, (r, t[r], t0)
+            nb0 = op.neighbourhood(vol, tuple(t[r]))
+            assert np.max(np.abs(nb[r] - nb0)) <= 2e-5 * scale
+            assert np.max(np.abs(ref_t[r] - op.subvoxel(nb0, tuple(t[r])))) <= 1e-3
+    finally:
+        ctx.set_option("path", 0)
+        ctx.set_option("batch", 64)
+
+
+@pytest.mark.parametrize("n,nm,planar,nrot", [(16, 6, False, 3), (32, 19, True, 4)])
+def test_score_rotations_f64_exact_peaks(ctxs, n, nm, planar, nrot):
+    ctx = ctxs["f64"]
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, planar, 100 + n)
+    quats = wr.uniform_quaternions(nrot, 3 * n) if not planar else wr.planar_rotations(29.0, nrot)
+    flush_print("score_rotations f64", n, nm, planar)
+    out = ctx.score_rotations(ctx.spectrum(rho_f, gf), gf, rho_m, w, gm, quats)
+    c = oc.moving_coefficients(rho_m, w)
+    for r, q in enumerate(quats):
+        vol = oc.score_volume(rho_f, c, q, nm, planar)
+        s0, _, t0 = op.peak(vol)
+        assert tuple(to_np(out["t"])[r]) == t0
+        assert abs(to_np(out["score"])[r] - s0) <= 1e-11 * np.abs(vol).max()
+        nb0 = op.neighbourhood(vol, t0)
+        assert np.allclose(to_np(out["nbhd"])[r], nb0, atol=1e-11 * np.abs(vol).max())
+        assert np.allclose(to_np(out["refined"])[r], op.subvoxel(nb0, t0), atol=1e-9)
+
+
+# ----------------------------------------------------------------------------- top-k
+
+@pytest.mark.parametrize("n,k", [(5, 3), (576, 17), (3000, 1024), (5000, 5000)])
+def test_topk_order_and_ties(ctxs, n, k):
+    ctx = ctxs["f32"]
+    rng = np.random.default_rng(n)
+    s = rng.integers(0, 50, size=n).astype(np.float32)  # many exact ties
+    got = to_np(ctx.topk(s, k))
+    ref = op.top_k(s.astype(np.float64), k)
+    assert np.array_equal(got, ref)
+
+
+# ----------------------------------------------------------------------------- pose gradient
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("planar", [False, True])
+def test_score_grad_matches_oracle(ctxs, dtype, planar):
+    ctx = ctxs[dtype]
+    n, nm = (16, 6) if not planar else (32, 12)
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, planar, 55)
+    rng = np.random.default_rng(2)
+    B = 21  # ragged against the pose tile
+    t = rng.uniform(0, n, size=(B, 3))
+    q = wr.uniform_quaternions(B, 12)
+    if planar:
+        t[:, 2] = 0.0
+        q = wr.planar_rotations(13.0, B)
+    poses = np.concatenate([t, q * rng.uniform(0.7, 1.3, size=(B, 1))], axis=1)
+    gs = rng.normal(size=B)
+    flush_print("score_grad", dtype, planar, B)
+    score, gp, gw = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=True, want_w=True, grad_scale=gs)
+    score, gp, gw = to_np(score), to_np(gp), to_np(gw).reshape(-1)
+    c = oc.moving_coefficients(rho_m, w)
+    xb = osp.body_positions(nm, planar)
+    gw_ref = np.zeros(len(xb))
+    tol = 1e-10 if dtype == "f64" else 2e-5
+    for b in range(B):
+        f, dt, dq, dw = og.pose_value_and_grad(rho_f, c, rho_m, xb, poses[b, :3], poses[b, 3:])
+        g_ref = np.concatenate([dt, dq])
+        assert abs(score[b] - f) <= tol * max(1.0, abs(f)) * 10, b
+        assert np.max(np.abs(gp[b] - g_ref)) <= tol * 10 * max(1.0, np.max(np.abs(g_ref))), b
+        gw_ref += gs[b] * dw
+    assert np.max(np.abs(gw - gw_ref)) <= tol * 10 * max(1.0, np.max(np.abs(gw_ref)))
+    # value-only mode agrees with the value of the gradient mode
+    s2, _, _ = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=False)
+    assert np.allclose(to_np(s2), score, rtol=1e-6, atol=1e-6 * np.abs(score).max())
+
+
+# ----------------------------------------------------------------------------- end to end, planar
+
+def test_peg_in_hole_end_to_end_f64(ctxs):
+    """The planar workload in FP64 on the GPU (SDFs, spectrum, search) against
+    the oracle: identical best poses and scores to FP64 rounding."""
+    import torch
+    ctx = ctxs["f64"]
+    pair = C.peg_in_hole_2d(seed=0)
+    flush_print("peg_in_hole end to end f64")
+    fx, mv = pair.fixed, pair.moving
+    rho_f = ctx.sdf_build(fx.samples.q, fx.samples.n, fx.samples.w, fx.grid, pair.params)
+    rho_m = ctx.sdf_build(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params)
+    w = torch.ones_like(rho_m.real)  # h^2 = 1
+    out = ctx.score_rotations(ctx.spectrum(rho_f, fx.grid), fx.grid, rho_m, w, mv.grid, pair.quats)
+    fields = oracle_fields(pair)
+    from oracle import pipeline
+    s_ref, t_ref, nb_ref, r_ref = pipeline.score_rotations(fields, pair.quats)
+    s, t = to_np(out["score"]), to_np(out["t"])
+    assert np.max(score_rel_err(s, s_ref)) < 1e-9
+    assert np.array_equal(t, t_ref)
+    assert int(np.argmax(s)) in (0, 18)
