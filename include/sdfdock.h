@@ -107,9 +107,23 @@ const char *sdf_last_error(sdf_ctx ctx);
  *   "batch"         rotations per fused launch sequence (even, 2..256; default 64)
  *   "graph"         1: capture each batch's launch sequence in a hipGraph and replay it
  *   "pencil_group"  rotations sharing one spectrum tile in the fused pencil pass (2 or 4)
+ *   "profile"       1: time every fused kernel with HIP events (see sdf_ctx_stats)
+ * With "graph" = 1 the fused launch sequence of a score_rotations call is
+ * captured once and replayed while the buffers, shapes and stream stay the
+ * same; the null stream cannot be captured and runs without a graph.
  * Errors: SDF_EINVAL for an unknown key or out-of-range value. */
 int sdf_ctx_set_option(sdf_ctx ctx, const char *key, int64_t value);
+/* Read an option, or one of the counters "graph_captures", "graph_launches". */
 int sdf_ctx_get_option(sdf_ctx ctx, const char *key, int64_t *value);
+
+/* Kernel timing.  With the option "profile" = 1 every kernel of the fused
+ * search is bracketed by HIP events on the caller's stream (graphs are not
+ * used meanwhile).  sdf_ctx_stats synchronises on the recorded events and
+ * returns the accumulated time and launch count of one kernel
+ * ("spread_slab", "pencil", "islab_peak", "finish"; unknown names give 0).
+ * sdf_ctx_stats_reset clears the totals. */
+int sdf_ctx_stats(sdf_ctx ctx, const char *kernel, double *total_ms, int64_t *launches);
+int sdf_ctx_stats_reset(sdf_ctx ctx);
 
 /* ------------------------------------------------------- skeletal density */
 

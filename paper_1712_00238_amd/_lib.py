@@ -15,6 +15,7 @@ SDF_OK, SDF_EINVAL, SDF_EUNSUPPORTED, SDF_EHIP, SDF_ENOMEM = 0, -1, -2, -3, -4
 SDF_F32, SDF_F64 = 0, 1
 
 EXPORTS = ["sdf_ctx_create", "sdf_ctx_destroy", "sdf_last_error", "sdf_ctx_set_option", "sdf_ctx_get_option",
+           "sdf_ctx_stats", "sdf_ctx_stats_reset",
            "sdf_build", "sdf_spectrum", "score_rotations", "score_volume", "sdf_spread", "sdf_fft", "sdf_topk",
            "score_grad"]
 
@@ -52,6 +53,8 @@ def load() -> ctypes.CDLL:
         "sdf_last_error": ([vp], ctypes.c_char_p),
         "sdf_ctx_set_option": ([vp, ctypes.c_char_p, i64], ctypes.c_int),
         "sdf_ctx_get_option": ([vp, ctypes.c_char_p, ctypes.POINTER(i64)], ctypes.c_int),
+        "sdf_ctx_stats": ([vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], ctypes.c_int),
+        "sdf_ctx_stats_reset": ([vp], ctypes.c_int),
         "sdf_build": ([vp, vp, vp, vp, i64, gp, pp, vp, vp], ctypes.c_int),
         "sdf_spectrum": ([vp, vp, gp, vp, vp], ctypes.c_int),
         "score_rotations": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),

@@ -77,6 +77,15 @@ class Context:
         self._check(self.lib.sdf_ctx_get_option(self.handle, key.encode(), ctypes.byref(v)))
         return v.value
 
+    def kernel_stats(self, kernel: str):
+        """(total ms, launches) of one fused kernel since the last reset."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self.lib.sdf_ctx_stats(self.handle, kernel.encode(), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def reset_stats(self):
+        self._check(self.lib.sdf_ctx_stats_reset(self.handle))
+
     def _dev(self, a, dtype):
         if isinstance(a, np.ndarray):
             a = torch.from_numpy(a)

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -21,6 +22,59 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
 };
 
+// Per-kernel timing with HIP events, enabled by the "profile" option.
+struct Profiler : sdf::KernelTimer {
+    struct Rec {
+        std::string name;
+        hipEvent_t a, b;
+    };
+    std::vector<hipEvent_t> pool;
+    std::vector<Rec> pending;
+    std::map<std::string, std::pair<double, int64_t>> totals;
+    Rec cur;
+    bool ok = true;
+
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) ok = false;
+        return e;
+    }
+    void begin(const char* name, hipStream_t s) override {
+        cur.name = name;
+        cur.a = get();
+        cur.b = get();
+        if (cur.a) (void)hipEventRecord(cur.a, s);
+    }
+    void end(hipStream_t s) override {
+        if (cur.b) (void)hipEventRecord(cur.b, s);
+        pending.push_back(cur);
+    }
+    void collect() {
+        for (Rec& r : pending) {
+            float ms = 0.f;
+            if (r.a && r.b && hipEventSynchronize(r.b) == hipSuccess &&
+                hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+                auto& t = totals[r.name];
+                t.first += ms;
+                t.second += 1;
+            }
+            if (r.a) pool.push_back(r.a);
+            if (r.b) pool.push_back(r.b);
+        }
+        pending.clear();
+    }
+    void release() {
+        collect();
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        pool.clear();
+    }
+};
+
 struct sdf_ctx_s {
     int device = 0;
     sdf_dtype dtype = SDF_F32;
@@ -32,7 +86,11 @@ struct sdf_ctx_s {
     int64_t opt_batch = 64;
     int64_t opt_graph = 0;
     int64_t opt_pencil_group = 2;
+    int64_t opt_profile = 0;
     GraphEntry graph;
+    Profiler prof;
+    int64_t graph_captures = 0;
+    int64_t graph_launches = 0;
 };
 
 namespace {
@@ -252,15 +310,53 @@ int search_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* r
 
     const T* RT = static_cast<const T*>(L.rT);
     if (want_fused) {
-        for (int64_t r0 = 0; r0 < n_rot; r0 += fp.batch) {
-            const int nb = int(n_rot - r0 < fp.batch ? n_rot - r0 : fp.batch);
-            SDF_TRY_HIP(ctx,
-                        sdf::launch_fused_batch(fp, reinterpret_cast<const float*>(RT) + 9 * r0, nb, L.c, spec,
-                                                L.fused, static_cast<float*>(score) + r0, tout + 3 * r0,
-                                                nbhd ? static_cast<float*>(nbhd) + 27 * r0 : nullptr,
-                                                refined ? refined + 3 * r0 : nullptr, s),
-                        "fused batch");
+        SDF_TRY_HIP(ctx, sdf::launch_fused_prep(fp, L.c, L.fused, s), "fixed-point scale");
+        sdf::KernelTimer* kt = ctx->opt_profile ? &ctx->prof : nullptr;
+        auto enqueue = [&]() -> hipError_t {
+            for (int64_t r0 = 0; r0 < n_rot; r0 += fp.batch) {
+                const int nb = int(n_rot - r0 < fp.batch ? n_rot - r0 : fp.batch);
+                hipError_t e = sdf::launch_fused_batch(fp, reinterpret_cast<const float*>(RT) + 9 * r0, nb, L.c, spec,
+                                                       L.fused, static_cast<float*>(score) + r0, tout + 3 * r0,
+                                                       nbhd ? static_cast<float*>(nbhd) + 27 * r0 : nullptr,
+                                                       refined ? refined + 3 * r0 : nullptr, s, kt);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        };
+        // Replay a captured graph of the whole launch sequence when the same
+        // buffers and shapes come back (capture needs a non-null stream).
+        if (ctx->opt_graph && !kt && s != nullptr) {
+            std::vector<uintptr_t> key = {uintptr_t(spec), uintptr_t(L.c), uintptr_t(L.rT), uintptr_t(L.fused),
+                                          uintptr_t(score), uintptr_t(tout), uintptr_t(nbhd), uintptr_t(refined),
+                                          uintptr_t(n_rot), uintptr_t(N), uintptr_t(nm), uintptr_t(planar),
+                                          uintptr_t(fp.batch), uintptr_t(fp.pencil_group), uintptr_t(s)};
+            if (!(ctx->graph.valid && ctx->graph.key == key)) {
+                drop_graph(ctx);
+                SDF_TRY_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture begin");
+                hipError_t e = enqueue();
+                hipGraph_t g = nullptr;
+                hipError_t e2 = hipStreamEndCapture(s, &g);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return hip_fail(ctx, e != hipSuccess ? e : e2, "graph capture");
+                }
+                hipGraphExec_t ex = nullptr;
+                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    (void)hipGraphDestroy(g);
+                    return hip_fail(ctx, e, "graph instantiate");
+                }
+                ctx->graph.graph = g;
+                ctx->graph.exec = ex;
+                ctx->graph.key = key;
+                ctx->graph.valid = true;
+                ctx->graph_captures += 1;
+            }
+            SDF_TRY_HIP(ctx, hipGraphLaunch(ctx->graph.exec, s), "graph launch");
+            ctx->graph_launches += 1;
+            return SDF_OK;
         }
+        SDF_TRY_HIP(ctx, enqueue(), "fused batch");
         return SDF_OK;
     }
     for (int64_t r = 0; r < n_rot; ++r) {
@@ -313,6 +409,7 @@ void sdf_ctx_destroy(sdf_ctx ctx) {
     if (!ctx) return;
     DeviceGuard dg(ctx->device);
     (void)hipDeviceSynchronize();
+    ctx->prof.release();
     drop_graph(ctx);
     if (ctx->ws) (void)hipFree(ctx->ws);
     delete ctx;
@@ -335,6 +432,9 @@ int sdf_ctx_set_option(sdf_ctx ctx, const char* key, int64_t value) {
     } else if (!std::strcmp(key, "pencil_group")) {
         if (value != 2 && value != 4) return fail(ctx, SDF_EINVAL, "pencil_group must be 2 or 4");
         ctx->opt_pencil_group = value;
+    } else if (!std::strcmp(key, "profile")) {
+        if (value != 0 && value != 1) return fail(ctx, SDF_EINVAL, "profile must be 0 or 1");
+        ctx->opt_profile = value;
     } else {
         return fail(ctx, SDF_EINVAL, std::string("unknown option ") + key);
     }
@@ -347,7 +447,28 @@ int sdf_ctx_get_option(sdf_ctx ctx, const char* key, int64_t* value) {
     else if (!std::strcmp(key, "batch")) *value = ctx->opt_batch;
     else if (!std::strcmp(key, "graph")) *value = ctx->opt_graph;
     else if (!std::strcmp(key, "pencil_group")) *value = ctx->opt_pencil_group;
+    else if (!std::strcmp(key, "profile")) *value = ctx->opt_profile;
+    else if (!std::strcmp(key, "graph_captures")) *value = ctx->graph_captures;
+    else if (!std::strcmp(key, "graph_launches")) *value = ctx->graph_launches;
     else return fail(ctx, SDF_EINVAL, std::string("unknown option ") + key);
+    return SDF_OK;
+}
+
+int sdf_ctx_stats(sdf_ctx ctx, const char* kernel, double* total_ms, int64_t* launches) {
+    if (!ctx || !kernel || !total_ms || !launches) return fail(ctx, SDF_EINVAL, "NULL argument");
+    DeviceGuard dg(ctx->device);
+    ctx->prof.collect();
+    auto it = ctx->prof.totals.find(kernel);
+    *total_ms = it == ctx->prof.totals.end() ? 0.0 : it->second.first;
+    *launches = it == ctx->prof.totals.end() ? 0 : it->second.second;
+    return SDF_OK;
+}
+
+int sdf_ctx_stats_reset(sdf_ctx ctx) {
+    if (!ctx) return fail(ctx, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    ctx->prof.collect();
+    ctx->prof.totals.clear();
     return SDF_OK;
 }
 

@@ -58,6 +58,14 @@ int peak_parts(int N, bool planar);
 template <typename T>
 hipError_t launch_real_part(const void* vol, T* out, int64_t count, hipStream_t s);
 
+// Optional per-kernel timing hook: begin/end bracket one kernel launch on a
+// stream (implemented with HIP events by the ABI layer).
+struct KernelTimer {
+    virtual void begin(const char* name, hipStream_t s) = 0;
+    virtual void end(hipStream_t s) = 0;
+    virtual ~KernelTimer() = default;
+};
+
 // ---- fused FP32 path
 struct FusedPlan {
     int N;
@@ -67,9 +75,12 @@ struct FusedPlan {
     int pencil_group; // rotations per pencil job (2 or 4)
 };
 size_t fused_workspace_bytes(const FusedPlan& fp);
+// once per search call, after the coefficients and before the batches
+hipError_t launch_fused_prep(const FusedPlan& fp, const void* c, void* ws, hipStream_t s);
 // score `n_rot` (<= batch) rotations whose FP32 matrices are R (device, n_rot x 9)
 hipError_t launch_fused_batch(const FusedPlan& fp, const float* R, int n_rot, const void* c, const void* spec,
-                              void* ws, float* score, int32_t* t, float* nbhd, double* refined, hipStream_t s);
+                              void* ws, float* score, int32_t* t, float* nbhd, double* refined, hipStream_t s,
+                              KernelTimer* kt = nullptr);
 
 // ---- top-k
 template <typename T>

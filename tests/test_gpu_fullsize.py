@@ -1,0 +1,161 @@
+"""Full-size GPU parity in the benchmark's launch configuration.
+
+The stored oracle results under tests/golden/ were written by
+tests/golden/make_golden.py from the oracle alone.  The GPU runs the whole
+path from the seeded boundary samples (SDFs, spectrum, fused FP32 search
+with 64-rotation batches replayed from a hipGraph on a side stream) and is
+compared rotation by rotation:
+  * score relative error, floored at 1e-3 of the largest score, <= 1e-4;
+  * identical peak translation, or a near tie: the GPU's t lies in the
+    oracle's 27-neighbourhood with an oracle value within 1e-4 of the peak;
+  * identical best rotation, or the oracle scores the GPU's best within 1e-4.
+SDF values are checked node by node on sampled nodes of the full grid.
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from helpers import flush_print, sdf_compare
+from oracle import sdf as osdf
+from workloads import configs as C
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_peaks(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    a = np.loadtxt(path)
+    return {"q": a[:, 1:5], "score": a[:, 5], "t": a[:, 6:9].astype(int), "refined": a[:, 9:12], "nbhd": a[:, 12:39]}
+
+
+def check_against_golden(gold, s, t, refined, tag, tol=1e-4):
+    s = np.asarray(s, dtype=np.float64)
+    ref = gold["score"]
+    den = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    rel = np.abs(s - ref) / den
+    flush_print(tag, "max rel err", rel.max(), "median", np.median(rel))
+    assert rel.max() <= tol, (tag, int(np.argmax(rel)), rel.max())
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    n_tie = 0
+    for r in range(len(s)):
+        if np.array_equal(t[r], gold["t"][r]):
+            continue
+        d = tuple(int(v) for v in (t[r] - gold["t"][r]))
+        assert d in offs, (tag, r, t[r], gold["t"][r])
+        v = gold["nbhd"][r][offs.index(d)]
+        assert abs(v - ref[r]) <= tol * den[r], (tag, r, v, ref[r])
+        n_tie += 1
+    flush_print(tag, "near-tie translations", n_tie, "of", len(s))
+    b_gpu, b_ref = int(np.argmax(s)), int(np.argmax(ref))
+    assert b_gpu == b_ref or abs(ref[b_gpu] - ref[b_ref]) <= tol * abs(ref[b_ref]), (tag, b_gpu, b_ref)
+
+
+def build_fields_gpu(ctx, pair):
+    fx, mv = pair.fixed, pair.moving
+    rho_f = ctx.sdf_build(fx.samples.q, fx.samples.n, fx.samples.w, fx.grid, pair.params)
+    rho_m = ctx.sdf_build(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params)
+    return rho_f, rho_m
+
+
+def test_mechanical_sdf_sampled_nodes():
+    import torch
+    from paper_1712_00238_amd.api import Context
+    pair = C.mechanical_3d(seed=0)
+    rng = np.random.default_rng(0)
+    with Context(0, "f32") as ctx:
+        flush_print("full-size sdf_build fixed part 128^3")
+        rho_f, rho_m = build_fields_gpu(ctx, pair)
+        torch.cuda.synchronize()
+        for part, rho in ((pair.fixed, rho_f), (pair.moving, rho_m)):
+            g = part.grid
+            flat = rng.choice(g.size, size=3000, replace=False)
+            pts = g.node_positions()[flat]
+            got = rho.reshape(-1)[torch.as_tensor(flat, device=rho.device)].cpu().numpy()
+            rep = sdf_compare_points(got, part.samples, pts, pair.params)
+            flush_print(part.grid.n, rep)
+            assert rep["ok"], rep
+
+
+def sdf_compare_points(got, samples, pts, params, rel_tol=2e-5, band_rel=2e-5):
+    rho, diag = osdf.sdf_points(samples, pts, params, diagnostics=True, band_rel=band_rel)
+    scale = np.abs(rho).max()
+    err = np.abs(got - rho)
+    tol = rel_tol * scale
+    xi_abs = np.abs(diag["xi"])
+    amb_trunc = diag["trunc_margin"] <= band_rel
+    free = (diag["pmc_gap"] <= band_rel * np.maximum(xi_abs, 1.0)) | \
+        (np.abs(xi_abs - params.xi_floor) <= band_rel * np.maximum(xi_abs, 1.0))
+    allowed = np.where(amb_trunc, tol + 1.01 * diag["band_mag"], tol)
+    bad = (err > allowed) & ~free
+    return {"max_err": float(err.max()), "scale": float(scale), "n_bad": int(bad.sum()),
+            "n_amb": int((amb_trunc | free).sum()), "ok": not bad.any()}
+
+
+@pytest.mark.parametrize("graph", [1, 0])
+def test_mechanical_end_to_end_fp32_all_rotations(graph):
+    import torch
+    from paper_1712_00238_amd.api import Context
+    gold = load_peaks("mechanical_3d_seed0.txt")
+    pair = C.mechanical_3d(seed=0)
+    assert np.array_equal(gold["q"], pair.quats)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream), Context(0, "f32") as ctx:
+        ctx.set_option("batch", 64)
+        ctx.set_option("graph", graph)
+        flush_print("mechanical end to end fp32, graph", graph)
+        rho_f, rho_m = build_fields_gpu(ctx, pair)
+        spec = ctx.spectrum(rho_f, pair.fixed.grid)
+        w = torch.ones(rho_m.shape, dtype=torch.float32, device=rho_m.device)
+        out = None
+        results = []
+        for it in range(3):  # later calls replay the captured graph; eager work in between
+            out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats, out=out)
+            results.append(tuple(out[k].cpu().numpy() for k in ("score", "t", "refined")))
+            out["score"].zero_()
+            out["t"].fill_(-1)
+            torch.cuda.synchronize()
+        if graph:
+            assert ctx.get_option("graph_captures") == 1 and ctx.get_option("graph_launches") == 3
+    for s, t, ref in results:
+        check_against_golden(gold, s, t, ref, f"mech fp32 graph={graph}")
+    assert all(np.array_equal(results[0][0], r[0]) for r in results)
+
+
+def test_mechanical_end_to_end_fp64_subset():
+    import torch
+    from paper_1712_00238_amd.api import Context
+    gold = load_peaks("mechanical_3d_seed0.txt")
+    pair = C.mechanical_3d(seed=0)
+    idx = np.arange(0, 576, 24)
+    with Context(0, "f64") as ctx:
+        flush_print("mechanical end to end fp64 (plain path)", len(idx), "rotations")
+        rho_f, rho_m = build_fields_gpu(ctx, pair)
+        spec = ctx.spectrum(rho_f, pair.fixed.grid)
+        w = torch.ones(rho_m.shape, dtype=torch.float64, device=rho_m.device)
+        out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats[idx])
+        s, t = out["score"].cpu().numpy(), out["t"].cpu().numpy()
+    sub = {k: v[idx] for k, v in gold.items()}
+    check_against_golden(sub, s, t, None, "mech fp64", tol=1e-8)
+    assert np.array_equal(t, sub["t"])
+
+
+def test_peg_in_hole_golden_fp32_and_fp64():
+    import torch
+    from paper_1712_00238_amd.api import Context
+    gold = load_peaks("peg_in_hole_2d_seed0.txt")
+    pair = C.peg_in_hole_2d(seed=0)
+    for dtype, tol in (("f64", 1e-9), ("f32", 1e-4)):
+        with Context(0, dtype) as ctx:
+            flush_print("peg in hole golden", dtype)
+            rho_f, rho_m = build_fields_gpu(ctx, pair)
+            spec = ctx.spectrum(rho_f, pair.fixed.grid)
+            w = torch.ones(rho_m.shape, dtype=rho_m.real.dtype, device=rho_m.device)
+            out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats)
+            s, t = out["score"].cpu().numpy(), out["t"].cpu().numpy()
+        check_against_golden(gold, s, t, None, f"peg {dtype}", tol=tol)
