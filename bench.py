@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=64, help="rotations per fused launch sequence")
     ap.add_argument("--pencil-group", type=int, default=2)
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=1, help="tune batch, pencil group and radix schedule first")
     ap.add_argument("--fp64-rotations", type=int, default=64, help="rotations timed on the plain FP64 path")
     ap.add_argument("--grad-poses", type=int, default=1024)
     ap.add_argument("--grad-steps", type=int, default=5)
@@ -178,6 +179,11 @@ def main():
         report["sdf_build_fixed_pairs_per_s"] = fx.samples.count * fx.grid.size / (e0.elapsed_time(e1) * 1e-3)
         report["spectrum_ms"] = e2.elapsed_time(e3)
         w = torch.ones(rho_m.shape, dtype=torch.float32, device=dev)  # h^3 = 1
+        tuned = None
+        if args.autotune:
+            rep = ctx.autotune(fx.grid, mv.grid)
+            tuned = rep["chosen"]
+            args.batch, args.pencil_group = tuned["batch"], tuned["group"]
 
         out = None
         for _ in range(args.warmup):
@@ -283,7 +289,8 @@ def main():
             "config": {"workload": "mechanical_3d: box-with-hole (fixed, 15.7k samples) vs plate-with-peg (moving, "
                                    "4.1k samples), 128^3 grid h=1, 64^3 body box, 576 Hopf rotations",
                        "rotations": n_rot, "batch": args.batch, "graph": bool(args.graph),
-                       "pencil_group": args.pencil_group},
+                       "pencil_group": args.pencil_group, "radix": (tuned or {}).get("radix", 0),
+                       "autotuned": bool(args.autotune)},
             "roofline": roofline,
             "fp64_rotations_per_s": round(report["fp64_rotations_per_s"], 1),
             "pose_grad_evals_per_s": round(report["pose_grad_evals_per_s"], 1),

@@ -108,12 +108,15 @@ const char *sdf_last_error(sdf_ctx ctx);
  *   "graph"         1: capture each batch's launch sequence in a hipGraph and replay it
  *   "pencil_group"  rotations sharing one spectrum tile in the fused pencil pass (2 or 4)
  *   "profile"       1: time every fused kernel with HIP events (see sdf_ctx_stats)
+ *   "radix"         FFT radix schedule of the fused kernels (0, 1, 2; e.g. 128 = 8.4.4, 4.4.8, 2.8.8)
+ *   "autotune"      1: tune each grid-size class on its first search (see sdf_autotune)
  * With "graph" = 1 the fused launch sequence of a score_rotations call is
  * captured once and replayed while the buffers, shapes and stream stay the
  * same; the null stream cannot be captured and runs without a graph.
  * Errors: SDF_EINVAL for an unknown key or out-of-range value. */
 int sdf_ctx_set_option(sdf_ctx ctx, const char *key, int64_t value);
-/* Read an option, or one of the counters "graph_captures", "graph_launches". */
+/* Read an option, the device's compute-unit count "num_cu", or one of the
+ * counters "graph_captures", "graph_launches". */
 int sdf_ctx_get_option(sdf_ctx ctx, const char *key, int64_t *value);
 
 /* Kernel timing.  With the option "profile" = 1 every kernel of the fused
@@ -138,9 +141,12 @@ int sdf_ctx_stats_reset(sdf_ctx ctx);
  *   G(r) = exp(-(r - 1)^2 / (2 sigma^2)), exterior (pmc > 0): lambda = lambda1,
  *   P = (1 - i r)^2; interior: lambda = -lambda2, P = (1 + i r)^2
  *   (this is eq. 13 with the kernel of eq. 15 and zeta = xi + i eta).
- * q, nrm: n x 3 real (positions, outward unit normals); w: n real weights
- * (area elements; arc lengths in 2D).  rho_out: complex, g->n[0]*n[1]*n[2].
- * g, p: host structs.  Any grid shape is accepted.
+ * q, nrm: n x 3 FP64 (positions, outward unit normals); w: n FP64 weights
+ * (area elements; arc lengths in 2D) - FP64 in both precisions.  The
+ * discrete decisions (nearest sample, membership, distance floor, and the
+ * contact-ball test of samples within 1e-4 of its radius) are taken in FP64;
+ * the kernel sum runs in the context's precision.  rho_out: complex,
+ * g->n[0]*n[1]*n[2].  g, p: host structs.  Any grid shape is accepted.
  * Errors: SDF_EINVAL (null pointer, n <= 0, bad grid, invalid params). */
 int sdf_build(sdf_ctx ctx, const void *q, const void *nrm, const void *w, int64_t n,
               const sdf_grid *g, const sdf_params *p, void *rho_out, sdf_stream stream);
@@ -178,6 +184,41 @@ int score_rotations(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed
                     const double *quats, int64_t n_rot,
                     void *peak_score, int32_t *peak_t, void *peak_nbhd, double *refined_t,
                     sdf_stream stream);
+
+/* Many pairs in one call (the uneven batch): each job is one pair with its
+ * own spectrum, moving SDF, weights, quaternions (host) and outputs, as in
+ * score_rotations.  Jobs may differ in N (8..128) and N_M.  FP32 contexts
+ * group the jobs by grid size and run every group's rotations through one
+ * persistent launch sequence per batch, reading per-pair descriptors; FP64
+ * contexts (and "path" = 1) score the pairs one after the other.
+ * Errors: as score_rotations, with the failing job's index in the message. */
+typedef struct {
+    const void *spec_fixed;
+    sdf_grid g_fixed;
+    const void *rho_moving;
+    const void *w_moving;
+    sdf_grid g_moving;
+    const double *quats; /* host, n_rot x 4 */
+    int64_t n_rot;
+    void *peak_score;
+    int32_t *peak_t;
+    void *peak_nbhd;     /* may be NULL */
+    double *refined_t;   /* may be NULL */
+} sdf_pair_job;
+int score_pairs(sdf_ctx ctx, const sdf_pair_job *jobs, int64_t n_jobs, sdf_stream stream);
+
+/* Autotuner for the fused FP32 search of one grid-size class (N, planar,
+ * N_M): times every candidate plan (rotations per batch in {32, 64, 128},
+ * rotations per pencil block in {2, 4}, three FFT radix schedules) on
+ * synthetic inputs, rejects candidates whose peaks differ from the plain
+ * multi-pass path by more than 1e-4 of the largest score on a probe set, and
+ * keeps the fastest for this context (option "autotune" = 1 runs this on the
+ * first search of each class).  report (host, may be NULL) receives a JSON
+ * summary of all candidates, truncated to report_len - 1 bytes.  The
+ * synthetic inputs are allocated for the duration of the call.
+ * Errors: SDF_EINVAL, SDF_EUNSUPPORTED (FP64 context), SDF_ENOMEM, SDF_EHIP. */
+int sdf_autotune(sdf_ctx ctx, const sdf_grid *g_fixed, const sdf_grid *g_moving, char *report, size_t report_len,
+                 sdf_stream stream);
 
 /* Full score volumes Re f(R, t) for every t of each rotation: vol_out is
  * real, n_rot x (grid size), same layout as the grid.  Same inputs and

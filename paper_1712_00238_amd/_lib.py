@@ -16,8 +16,8 @@ SDF_F32, SDF_F64 = 0, 1
 
 EXPORTS = ["sdf_ctx_create", "sdf_ctx_destroy", "sdf_last_error", "sdf_ctx_set_option", "sdf_ctx_get_option",
            "sdf_ctx_stats", "sdf_ctx_stats_reset",
-           "sdf_build", "sdf_spectrum", "score_rotations", "score_volume", "sdf_spread", "sdf_fft", "sdf_topk",
-           "score_grad"]
+           "sdf_build", "sdf_spectrum", "score_rotations", "score_pairs", "sdf_autotune", "score_volume",
+           "sdf_spread", "sdf_fft", "sdf_topk", "score_grad"]
 
 
 class SdfGrid(ctypes.Structure):
@@ -27,6 +27,13 @@ class SdfGrid(ctypes.Structure):
 class SdfParams(ctypes.Structure):
     _fields_ = [("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("eps", ctypes.c_double), ("xi_floor", ctypes.c_double)]
+
+
+class SdfPairJob(ctypes.Structure):
+    _fields_ = [("spec_fixed", ctypes.c_void_p), ("g_fixed", SdfGrid), ("rho_moving", ctypes.c_void_p),
+                ("w_moving", ctypes.c_void_p), ("g_moving", SdfGrid), ("quats", ctypes.c_void_p),
+                ("n_rot", ctypes.c_int64), ("peak_score", ctypes.c_void_p), ("peak_t", ctypes.c_void_p),
+                ("peak_nbhd", ctypes.c_void_p), ("refined_t", ctypes.c_void_p)]
 
 
 class SdfError(RuntimeError):
@@ -58,6 +65,8 @@ def load() -> ctypes.CDLL:
         "sdf_build": ([vp, vp, vp, vp, i64, gp, pp, vp, vp], ctypes.c_int),
         "sdf_spectrum": ([vp, vp, gp, vp, vp], ctypes.c_int),
         "score_rotations": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
+        "score_pairs": ([vp, ctypes.POINTER(SdfPairJob), i64, vp], ctypes.c_int),
+        "sdf_autotune": ([vp, gp, gp, ctypes.c_char_p, ctypes.c_size_t, vp], ctypes.c_int),
         "score_volume": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp], ctypes.c_int),
         "sdf_spread": ([vp, gp, vp, vp, gp, vp, i64, vp, vp], ctypes.c_int),
         "sdf_fft": ([vp, vp, vp, gp, ctypes.c_int, vp], ctypes.c_int),

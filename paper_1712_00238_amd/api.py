@@ -94,9 +94,9 @@ class Context:
     # ------------------------------------------------------------------ SDF
     def sdf_build(self, q, n, w, grid, params, out=None):
         """Skeletal density function of one solid on ``grid`` -> complex (nz, ny, nx)."""
-        q = self._dev(q, self.real)
-        n = self._dev(n, self.real)
-        w = self._dev(w, self.real)
+        q = self._dev(q, torch.float64)
+        n = self._dev(n, torch.float64)
+        w = self._dev(w, torch.float64)
         nx, ny, nz = grid.n
         if out is None:
             out = torch.empty((nz, ny, nx), dtype=self.cplx, device=self.device)
@@ -135,6 +135,44 @@ class Context:
                                              _ptr(out["score"]), _ptr(out["t"]), _ptr(out["nbhd"]),
                                              _ptr(out["refined"]), _stream(self.device)))
         return out
+
+    def score_pairs(self, jobs, nbhd=True, refined=True):
+        """Many pairs in one call.  ``jobs``: sequence of dicts with keys spec,
+        g_fixed, rho_moving, w_moving, g_moving, quats.  Returns one output
+        dict per job (score, t, nbhd, refined)."""
+        arr = (_lib.SdfPairJob * len(jobs))()
+        keep, outs = [], []
+        for i, j in enumerate(jobs):
+            q = np.ascontiguousarray(np.asarray(j["quats"], dtype=np.float64).reshape(-1, 4))
+            spec = self._dev(j["spec"], self.cplx)
+            rm = self._dev(j["rho_moving"], self.cplx)
+            wm = self._dev(j["w_moving"], self.real)
+            n = len(q)
+            out = {"score": torch.empty(n, dtype=self.real, device=self.device),
+                   "t": torch.empty((n, 3), dtype=torch.int32, device=self.device),
+                   "nbhd": torch.empty((n, 27), dtype=self.real, device=self.device) if nbhd else None,
+                   "refined": torch.empty((n, 3), dtype=torch.float64, device=self.device) if refined else None}
+            keep += [q, spec, rm, wm]
+            outs.append(out)
+            a = arr[i]
+            a.spec_fixed, a.rho_moving, a.w_moving = spec.data_ptr(), rm.data_ptr(), wm.data_ptr()
+            a.g_fixed, a.g_moving = _lib.make_grid(j["g_fixed"]), _lib.make_grid(j["g_moving"])
+            a.quats, a.n_rot = q.ctypes.data, n
+            a.peak_score, a.peak_t = out["score"].data_ptr(), out["t"].data_ptr()
+            a.peak_nbhd = out["nbhd"].data_ptr() if nbhd else None
+            a.refined_t = out["refined"].data_ptr() if refined else None
+        self._check(self.lib.score_pairs(self.handle, arr, len(jobs), _stream(self.device)))
+        del keep
+        return outs
+
+    def autotune(self, g_fixed, g_moving) -> dict:
+        """Tune the fused search for this grid-size class; returns the report."""
+        import json
+        buf = ctypes.create_string_buffer(1 << 16)
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.sdf_autotune(self.handle, ctypes.byref(gf), ctypes.byref(gm), buf, len(buf),
+                                          _stream(self.device)))
+        return json.loads(buf.value.decode())
 
     def score_volume(self, spec, g_fixed, rho_moving, w_moving, g_moving, quats):
         q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))

@@ -3,6 +3,7 @@
 // any entry point; every failure returns a code and records a message.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -14,6 +15,10 @@
 
 #include "launch.hpp"
 #include "sdfdock.h"
+
+struct Tuned {
+    int batch, group, radix;
+};
 
 struct GraphEntry {
     bool valid = false;
@@ -87,6 +92,15 @@ struct sdf_ctx_s {
     int64_t opt_graph = 0;
     int64_t opt_pencil_group = 2;
     int64_t opt_profile = 0;
+    int64_t opt_radix = 0;
+    int64_t opt_autotune = 0;
+    int num_cu = 256;
+    std::map<uint64_t, Tuned> tuned;
+    std::string last_report;
+    // descriptors of the last fused search still resident in the workspace
+    bool fused_cache_valid = false;
+    void* fused_cache_base = nullptr;
+    std::vector<char> fused_cache_jobs, fused_cache_rots;
     GraphEntry graph;
     Profiler prof;
     int64_t graph_captures = 0;
@@ -245,138 +259,417 @@ void drop_graph(sdf_ctx ctx) {
 }
 
 // ------------------------------------------------------------------ search core
-struct Layout {
-    double* quats;
-    double* r64;
-    void* rT;
-    void* c;
-    void* grid;   // plain path: per-rotation complex grid(s)
-    void* pval;
-    int* pidx;
-    void* fused;  // fused path workspace
-    size_t total;
+// One pair of a search, as the ABI receives it.
+struct PairIn {
+    const void* spec;
+    const sdf_grid* gf;
+    const void* rho_m;
+    const void* w_m;
+    const sdf_grid* gm;
+    const double* quats;
+    int64_t n_rot;
+    void* score;
+    int32_t* t;
+    void* nbhd;
+    double* refined;
 };
-
-template <typename T>
-Layout carve_search(char* base, int64_t n_rot, int64_t K, int64_t G, int nparts, int plain_batch,
-                    const sdf::FusedPlan* fp) {
-    Carve cv{base};
-    Layout L{};
-    L.quats = static_cast<double*>(cv.take(sizeof(double) * 4 * n_rot));
-    L.r64 = static_cast<double*>(cv.take(sizeof(double) * 9 * n_rot));
-    L.rT = cv.take(sizeof(T) * 9 * n_rot);
-    L.c = cv.take(2 * sizeof(T) * K);
-    if (fp) {
-        L.fused = cv.take(sdf::fused_workspace_bytes(*fp));
-        L.grid = nullptr;
-        L.pval = nullptr;
-        L.pidx = nullptr;
-    } else {
-        L.grid = cv.take(2 * sizeof(T) * G * plain_batch);
-        L.pval = cv.take(sizeof(T) * nparts * plain_batch);
-        L.pidx = static_cast<int*>(cv.take(sizeof(int) * nparts * plain_batch));
-        L.fused = nullptr;
-    }
-    L.total = cv.off;
-    return L;
-}
 
 enum class Mode { Peaks, Volume };
 
+// Plain path for one pair: one rotation per launch sequence.
 template <typename T>
-int search_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* rho_m, const void* w_m,
-                const sdf_grid* gm, const double* quats, int64_t n_rot, Mode mode, void* score, int32_t* tout,
-                void* nbhd, double* refined, void* vol_out, hipStream_t s) {
-    const int N = gf->n[0];
-    const bool planar = gf->n[2] == 1;
-    const int nm = gm->n[0];
-    const int64_t K = gsize(gm);
-    const int64_t G = gsize(gf);
+int plain_pair(sdf_ctx ctx, const PairIn& pr, Mode mode, void* vol_out, hipStream_t s) {
+    ctx->fused_cache_valid = false;
+    const int N = pr.gf->n[0];
+    const bool planar = pr.gf->n[2] == 1;
+    const int nm = pr.gm->n[0];
+    const int64_t K = gsize(pr.gm), G = gsize(pr.gf);
+    const int64_t n_rot = pr.n_rot;
     const int nparts = sdf::peak_parts<T>(N, planar);
-    const bool want_fused = std::is_same<T, float>::value && mode == Mode::Peaks &&
-                            (ctx->opt_path == 2 || ctx->opt_path == 0);
-    sdf::FusedPlan fp{N, nm, planar, int(ctx->opt_batch), int(ctx->opt_pencil_group)};
-    if (want_fused && fp.batch > n_rot) fp.batch = int((n_rot + 1) / 2 * 2);
-    const int plain_batch = 1;
-    Layout L = carve_search<T>(nullptr, n_rot, K, G, nparts, plain_batch, want_fused ? &fp : nullptr);
-    int rc = ensure_ws(ctx, L.total);
+    Carve cv{nullptr};
+    cv.take(sizeof(double) * 4 * n_rot);
+    cv.take(sizeof(double) * 9 * n_rot);
+    cv.take(sizeof(T) * 9 * n_rot);
+    cv.take(2 * sizeof(T) * K);
+    cv.take(2 * sizeof(T) * G);
+    cv.take(sizeof(T) * nparts);
+    cv.take(sizeof(int) * nparts);
+    int rc = ensure_ws(ctx, cv.off);
     if (rc) return rc;
-    L = carve_search<T>(static_cast<char*>(ctx->ws), n_rot, K, G, nparts, plain_batch, want_fused ? &fp : nullptr);
-
-    SDF_TRY_HIP(ctx, hipMemcpyAsync(L.quats, quats, sizeof(double) * 4 * n_rot, hipMemcpyHostToDevice, s),
+    Carve c2{static_cast<char*>(ctx->ws)};
+    double* qd = static_cast<double*>(c2.take(sizeof(double) * 4 * n_rot));
+    double* r64 = static_cast<double*>(c2.take(sizeof(double) * 9 * n_rot));
+    T* RT = static_cast<T*>(c2.take(sizeof(T) * 9 * n_rot));
+    void* c = c2.take(2 * sizeof(T) * K);
+    void* grid = c2.take(2 * sizeof(T) * G);
+    T* pval = static_cast<T*>(c2.take(sizeof(T) * nparts));
+    int* pidx = static_cast<int*>(c2.take(sizeof(int) * nparts));
+    SDF_TRY_HIP(ctx, hipMemcpyAsync(qd, pr.quats, sizeof(double) * 4 * n_rot, hipMemcpyHostToDevice, s),
                 "quaternion upload");
-    SDF_TRY_HIP(ctx, sdf::launch_quat_to_rot<T>(L.quats, n_rot, L.r64, static_cast<T*>(L.rT), s), "rotations");
-    SDF_TRY_HIP(ctx, sdf::launch_coef<T>(rho_m, static_cast<const T*>(w_m), K, L.c, s), "coefficients");
-
-    const T* RT = static_cast<const T*>(L.rT);
-    if (want_fused) {
-        SDF_TRY_HIP(ctx, sdf::launch_fused_prep(fp, L.c, L.fused, s), "fixed-point scale");
-        sdf::KernelTimer* kt = ctx->opt_profile ? &ctx->prof : nullptr;
-        auto enqueue = [&]() -> hipError_t {
-            for (int64_t r0 = 0; r0 < n_rot; r0 += fp.batch) {
-                const int nb = int(n_rot - r0 < fp.batch ? n_rot - r0 : fp.batch);
-                hipError_t e = sdf::launch_fused_batch(fp, reinterpret_cast<const float*>(RT) + 9 * r0, nb, L.c, spec,
-                                                       L.fused, static_cast<float*>(score) + r0, tout + 3 * r0,
-                                                       nbhd ? static_cast<float*>(nbhd) + 27 * r0 : nullptr,
-                                                       refined ? refined + 3 * r0 : nullptr, s, kt);
-                if (e != hipSuccess) return e;
-            }
-            return hipSuccess;
-        };
-        // Replay a captured graph of the whole launch sequence when the same
-        // buffers and shapes come back (capture needs a non-null stream).
-        if (ctx->opt_graph && !kt && s != nullptr) {
-            std::vector<uintptr_t> key = {uintptr_t(spec), uintptr_t(L.c), uintptr_t(L.rT), uintptr_t(L.fused),
-                                          uintptr_t(score), uintptr_t(tout), uintptr_t(nbhd), uintptr_t(refined),
-                                          uintptr_t(n_rot), uintptr_t(N), uintptr_t(nm), uintptr_t(planar),
-                                          uintptr_t(fp.batch), uintptr_t(fp.pencil_group), uintptr_t(s)};
-            if (!(ctx->graph.valid && ctx->graph.key == key)) {
-                drop_graph(ctx);
-                SDF_TRY_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture begin");
-                hipError_t e = enqueue();
-                hipGraph_t g = nullptr;
-                hipError_t e2 = hipStreamEndCapture(s, &g);
-                if (e != hipSuccess || e2 != hipSuccess) {
-                    if (g) (void)hipGraphDestroy(g);
-                    return hip_fail(ctx, e != hipSuccess ? e : e2, "graph capture");
-                }
-                hipGraphExec_t ex = nullptr;
-                e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
-                if (e != hipSuccess) {
-                    (void)hipGraphDestroy(g);
-                    return hip_fail(ctx, e, "graph instantiate");
-                }
-                ctx->graph.graph = g;
-                ctx->graph.exec = ex;
-                ctx->graph.key = key;
-                ctx->graph.valid = true;
-                ctx->graph_captures += 1;
-            }
-            SDF_TRY_HIP(ctx, hipGraphLaunch(ctx->graph.exec, s), "graph launch");
-            ctx->graph_launches += 1;
-            return SDF_OK;
-        }
-        SDF_TRY_HIP(ctx, enqueue(), "fused batch");
-        return SDF_OK;
-    }
+    SDF_TRY_HIP(ctx, sdf::launch_quat_to_rot<T>(qd, n_rot, r64, RT, s), "rotations");
+    SDF_TRY_HIP(ctx, sdf::launch_coef<T>(pr.rho_m, static_cast<const T*>(pr.w_m), K, c, s), "coefficients");
     for (int64_t r = 0; r < n_rot; ++r) {
-        SDF_TRY_HIP(ctx, sdf::launch_zero<T>(L.grid, G, s), "zero");
-        SDF_TRY_HIP(ctx, sdf::launch_spread_atomic<T>(L.c, nm, planar, RT + 9 * r, 1, T(-1), N, L.grid, s),
-                    "spread");
-        SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(L.grid, N, planar, 1, -1, 1.0, s), "forward fft");
-        SDF_TRY_HIP(ctx, sdf::launch_mul_spec<T>(L.grid, spec, G, 1, s), "spectral product");
-        SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(L.grid, N, planar, 1, +1, 1.0, s), "inverse fft");
+        SDF_TRY_HIP(ctx, sdf::launch_zero<T>(grid, G, s), "zero");
+        SDF_TRY_HIP(ctx, sdf::launch_spread_atomic<T>(c, nm, planar, RT + 9 * r, 1, T(-1), N, grid, s), "spread");
+        SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, 1, -1, 1.0, s), "forward fft");
+        SDF_TRY_HIP(ctx, sdf::launch_mul_spec<T>(grid, pr.spec, G, 1, s), "spectral product");
+        SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, 1, +1, 1.0, s), "inverse fft");
         if (mode == Mode::Volume) {
-            SDF_TRY_HIP(ctx, sdf::launch_real_part<T>(L.grid, static_cast<T*>(vol_out) + r * G, G, s), "real part");
+            SDF_TRY_HIP(ctx, sdf::launch_real_part<T>(grid, static_cast<T*>(vol_out) + r * G, G, s), "real part");
         } else {
             SDF_TRY_HIP(ctx,
-                        sdf::launch_peak<T>(L.grid, true, N, planar, 1, static_cast<T*>(L.pval), L.pidx, nparts,
-                                            static_cast<T*>(score) + r, tout + 3 * r,
-                                            nbhd ? static_cast<T*>(nbhd) + 27 * r : nullptr,
-                                            refined ? refined + 3 * r : nullptr, s),
+                        sdf::launch_peak<T>(grid, true, N, planar, 1, pval, pidx, nparts,
+                                            static_cast<T*>(pr.score) + r, pr.t + 3 * r,
+                                            pr.nbhd ? static_cast<T*>(pr.nbhd) + 27 * r : nullptr,
+                                            pr.refined ? pr.refined + 3 * r : nullptr, s),
                         "peak");
         }
     }
+    return SDF_OK;
+}
+
+uint64_t class_key(int N, bool planar) { return uint64_t(N) * 2 + (planar ? 1 : 0); }
+
+// Plan of one grid-size class: autotuned choice, else the context options.
+sdf::FusedPlan plan_for(sdf_ctx ctx, int N, bool planar, int64_t rots_in_class) {
+    sdf::FusedPlan fp{N, planar, int(ctx->opt_batch), int(ctx->opt_pencil_group), int(ctx->opt_radix),
+                      ctx->num_cu};
+    auto it = ctx->tuned.find(class_key(N, planar));
+    if (it != ctx->tuned.end()) {
+        fp.batch = it->second.batch;
+        fp.pencil_group = it->second.group;
+        fp.radix = it->second.radix;
+    }
+    if (fp.batch > rots_in_class) fp.batch = int((rots_in_class + 1) / 2 * 2);
+    if (fp.batch < 2) fp.batch = 2;
+    return fp;
+}
+
+int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std::string* report);
+
+// Fused FP32 search over any number of pairs.  Pairs are grouped by grid
+// size; each group's rotations run in batches through the persistent fused
+// kernels, all reading per-pair descriptors.
+int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
+    const int nj = int(pairs.size());
+    // classes in order of first appearance, jobs sorted by class
+    std::vector<uint64_t> classes;
+    for (const PairIn& p : pairs) {
+        const uint64_t k = class_key(p.gf->n[0], p.gf->n[2] == 1);
+        if (std::find(classes.begin(), classes.end(), k) == classes.end()) classes.push_back(k);
+    }
+    if (ctx->opt_autotune) {
+        for (uint64_t k : classes) {
+            if (ctx->tuned.count(k)) continue;
+            int nm = 0;
+            for (const PairIn& p : pairs)
+                if (class_key(p.gf->n[0], p.gf->n[2] == 1) == k) nm = std::max(nm, p.gm->n[0]);
+            int rc = autotune_class(ctx, int(k / 2), (k & 1) != 0, nm, s, nullptr);
+            if (rc) return rc;
+        }
+    }
+    std::vector<int> order;
+    for (uint64_t k : classes)
+        for (int j = 0; j < nj; ++j)
+            if (class_key(pairs[j].gf->n[0], pairs[j].gf->n[2] == 1) == k) order.push_back(j);
+    int64_t total_rot = 0;
+    for (const PairIn& p : pairs) total_rot += p.n_rot;
+    // workspace: descriptors, rotation inputs, per-pair coefficients and scales, prep scratch, batch buffers
+    std::vector<sdf::FusedPlan> plans;
+    std::vector<int64_t> class_rots(classes.size(), 0);
+    for (size_t ci = 0; ci < classes.size(); ++ci)
+        for (const PairIn& p : pairs)
+            if (class_key(p.gf->n[0], p.gf->n[2] == 1) == classes[ci]) class_rots[ci] += p.n_rot;
+    size_t batch_bytes = 0;
+    for (size_t ci = 0; ci < classes.size(); ++ci) {
+        plans.push_back(plan_for(ctx, int(classes[ci] / 2), (classes[ci] & 1) != 0, class_rots[ci]));
+        batch_bytes = std::max(batch_bytes, sdf::fused_workspace_bytes(plans.back()));
+    }
+    auto carve = [&](char* base, std::vector<void*>* cptr, std::vector<float*>* sptr, sdf::FusedJob** jobs_d,
+                     sdf::FusedRot** rots_d, sdf::RotInput** rin_d, void** prep, void** fused) {
+        Carve cv{base};
+        *jobs_d = static_cast<sdf::FusedJob*>(cv.take(sizeof(sdf::FusedJob) * nj));
+        *rots_d = static_cast<sdf::FusedRot*>(cv.take(sizeof(sdf::FusedRot) * total_rot));
+        *rin_d = static_cast<sdf::RotInput*>(cv.take(sizeof(sdf::RotInput) * total_rot));
+        *prep = cv.take(sdf::fused_prep_scratch_bytes(nj));
+        for (int j = 0; j < nj; ++j) {
+            void* c = cv.take(sizeof(float) * 2 * size_t(gsize(pairs[j].gm)));
+            float* sc = static_cast<float*>(cv.take(2 * sizeof(float)));
+            if (cptr) (*cptr)[j] = c;
+            if (sptr) (*sptr)[j] = sc;
+        }
+        *fused = cv.take(batch_bytes);
+        return cv.off;
+    };
+    sdf::FusedJob* jobs_d;
+    sdf::FusedRot* rots_d;
+    sdf::RotInput* rin_d;
+    void *prep, *fused;
+    const size_t need = carve(nullptr, nullptr, nullptr, &jobs_d, &rots_d, &rin_d, &prep, &fused);
+    int rc = ensure_ws(ctx, need);
+    if (rc) return rc;
+    std::vector<void*> cptr(nj);
+    std::vector<float*> sptr(nj);
+    carve(static_cast<char*>(ctx->ws), &cptr, &sptr, &jobs_d, &rots_d, &rin_d, &prep, &fused);
+    // host tables (pinned staging is unnecessary: these are a few KB and copied synchronously)
+    std::vector<sdf::FusedJob> jobs_h(nj);
+    std::vector<sdf::RotInput> rin_h;
+    rin_h.reserve(size_t(total_rot));
+    for (int jj : order) {
+        const PairIn& p = pairs[jj];
+        jobs_h[jj] = sdf::FusedJob{cptr[jj], p.spec, sptr[jj], static_cast<float*>(p.score), p.t,
+                                   static_cast<float*>(p.nbhd), p.refined, p.gm->n[0], p.gf->n[2] == 1 ? 1 : 0};
+        for (int64_t r = 0; r < p.n_rot; ++r) {
+            sdf::RotInput ri;
+            for (int a = 0; a < 4; ++a) ri.q[a] = p.quats[4 * r + a];
+            ri.job = jj;
+            ri.local = int(r);
+            rin_h.push_back(ri);
+        }
+    }
+    // Upload the tables only when they differ from the ones still resident in
+    // the workspace: a repeated search (same pairs, same rotations) enqueues
+    // kernels only and never waits on the host.
+    const char* jb = reinterpret_cast<const char*>(jobs_h.data());
+    const char* rb = reinterpret_cast<const char*>(rin_h.data());
+    const size_t jbytes = sizeof(sdf::FusedJob) * nj, rbytes = sizeof(sdf::RotInput) * total_rot;
+    const bool cached = ctx->fused_cache_valid && ctx->fused_cache_base == ctx->ws &&
+                        ctx->fused_cache_jobs.size() == jbytes && ctx->fused_cache_rots.size() == rbytes &&
+                        std::memcmp(ctx->fused_cache_jobs.data(), jb, jbytes) == 0 &&
+                        std::memcmp(ctx->fused_cache_rots.data(), rb, rbytes) == 0;
+    if (!cached) {
+        ctx->fused_cache_valid = false;
+        SDF_TRY_HIP(ctx, hipMemcpyAsync(jobs_d, jb, jbytes, hipMemcpyHostToDevice, s), "job table upload");
+        SDF_TRY_HIP(ctx, hipMemcpyAsync(rin_d, rb, rbytes, hipMemcpyHostToDevice, s), "rotation upload");
+        // the copies read pageable host memory that goes out of scope on return
+        SDF_TRY_HIP(ctx, hipStreamSynchronize(s), "upload");
+        SDF_TRY_HIP(ctx, sdf::launch_rot_desc(rin_d, total_rot, rots_d, s), "rotations");
+        ctx->fused_cache_jobs.assign(jb, jb + jbytes);
+        ctx->fused_cache_rots.assign(rb, rb + rbytes);
+        ctx->fused_cache_base = ctx->ws;
+        ctx->fused_cache_valid = true;
+    }
+    for (int j = 0; j < nj; ++j)
+        SDF_TRY_HIP(ctx,
+                    sdf::launch_coef<float>(pairs[j].rho_m, static_cast<const float*>(pairs[j].w_m),
+                                            gsize(pairs[j].gm), cptr[j], s),
+                    "coefficients");
+    SDF_TRY_HIP(ctx, sdf::launch_fused_prep(jobs_d, nj, prep, s), "fixed-point scale");
+
+    sdf::KernelTimer* kt = ctx->opt_profile ? &ctx->prof : nullptr;
+    auto enqueue = [&]() -> hipError_t {
+        int64_t r0 = 0;
+        for (size_t ci = 0; ci < classes.size(); ++ci) {
+            const sdf::FusedPlan& fp = plans[ci];
+            for (int64_t b = 0; b < class_rots[ci]; b += fp.batch) {
+                const int nb = int(std::min<int64_t>(fp.batch, class_rots[ci] - b));
+                hipError_t e = sdf::launch_fused_batch(fp, rots_d + r0 + b, nb, jobs_d, fused, s, kt);
+                if (e != hipSuccess) return e;
+            }
+            r0 += class_rots[ci];
+        }
+        return hipSuccess;
+    };
+    if (ctx->opt_graph && !kt && s != nullptr) {
+        std::vector<uintptr_t> key = {uintptr_t(ctx->ws), uintptr_t(nj), uintptr_t(total_rot), uintptr_t(s)};
+        for (const sdf::FusedPlan& fp : plans) {
+            key.push_back(uintptr_t(fp.N) * 1315423911u + uintptr_t(fp.batch) * 31u + uintptr_t(fp.pencil_group) * 7u +
+                          uintptr_t(fp.radix) + (fp.planar ? 977u : 0u));
+        }
+        for (int j = 0; j < nj; ++j) {
+            const PairIn& p = pairs[j];
+            key.insert(key.end(), {uintptr_t(p.spec), uintptr_t(p.score), uintptr_t(p.t), uintptr_t(p.nbhd),
+                                   uintptr_t(p.refined), uintptr_t(p.n_rot), uintptr_t(p.gf->n[0]),
+                                   uintptr_t(p.gf->n[2]), uintptr_t(p.gm->n[0])});
+        }
+        if (!(ctx->graph.valid && ctx->graph.key == key)) {
+            drop_graph(ctx);
+            SDF_TRY_HIP(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "graph capture begin");
+            hipError_t e = enqueue();
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(ctx, e != hipSuccess ? e : e2, "graph capture");
+            }
+            hipGraphExec_t ex = nullptr;
+            e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return hip_fail(ctx, e, "graph instantiate");
+            }
+            ctx->graph.graph = g;
+            ctx->graph.exec = ex;
+            ctx->graph.key = key;
+            ctx->graph.valid = true;
+            ctx->graph_captures += 1;
+        }
+        SDF_TRY_HIP(ctx, hipGraphLaunch(ctx->graph.exec, s), "graph launch");
+        ctx->graph_launches += 1;
+        return SDF_OK;
+    }
+    SDF_TRY_HIP(ctx, enqueue(), "fused batch");
+    return SDF_OK;
+}
+
+template <typename T>
+int search_impl(sdf_ctx ctx, const std::vector<PairIn>& pairs, Mode mode, void* vol_out, hipStream_t s) {
+    const bool fused = std::is_same<T, float>::value && mode == Mode::Peaks && ctx->opt_path != 1;
+    if (fused) return fused_pairs(ctx, pairs, s);
+    for (const PairIn& p : pairs) {
+        int rc = plain_pair<T>(ctx, p, mode, vol_out, s);
+        if (rc) return rc;
+    }
+    return SDF_OK;
+}
+
+// Autotuner: times candidate plans of one grid-size class on synthetic
+// inputs and keeps the fastest whose peaks agree with the plain FP32 path.
+int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std::string* report) {
+    if (ctx->dtype != SDF_F32) return SDF_OK;
+    ctx->fused_cache_valid = false;
+    const int nz = planar ? 1 : N;
+    const int64_t G = int64_t(N) * N * nz;
+    const int64_t K = int64_t(n_m) * n_m * (planar ? 1 : n_m);
+    const int n_probe = 8;  // rotations compared with the plain path
+    const int n_time = 128; // rotations timed per candidate
+    // synthetic pair in its own allocations (freed at the end)
+    void *spec = nullptr, *rho = nullptr, *w = nullptr, *sc = nullptr, *tt = nullptr;
+    void *sc_ref = nullptr, *tt_ref = nullptr;
+    auto cleanup = [&]() {
+        for (void* p : {spec, rho, w, sc, tt, sc_ref, tt_ref})
+            if (p) (void)hipFree(p);
+    };
+    if (hipMalloc(&spec, 8 * G) != hipSuccess || hipMalloc(&rho, 8 * K) != hipSuccess ||
+        hipMalloc(&w, 4 * K) != hipSuccess || hipMalloc(&sc, 4 * n_time) != hipSuccess ||
+        hipMalloc(&tt, 12 * n_time) != hipSuccess || hipMalloc(&sc_ref, 4 * n_probe) != hipSuccess ||
+        hipMalloc(&tt_ref, 12 * n_probe) != hipSuccess) {
+        cleanup();
+        (void)hipGetLastError();
+        return fail(ctx, SDF_ENOMEM, "autotune allocation failed");
+    }
+    (void)sdf::launch_fill_random(spec, G, 11, 1e-3f, s);
+    (void)sdf::launch_fill_random(rho, K, 12, 2.f, s);
+    // w = 1: fill as complex pairs of (1, 1) over K/2 complex slots is awkward; use a real fill kernel
+    {
+        std::vector<float> ones(size_t(K), 1.f);  // unit body weights
+        if (hipMemcpyAsync(w, ones.data(), 4 * K, hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            cleanup();
+            return fail(ctx, SDF_EHIP, "autotune upload failed");
+        }
+    }
+    std::vector<double> q(4 * n_time);
+    uint64_t st = 0x9e3779b97f4a7c15ull;
+    auto rnd = [&]() {
+        st ^= st << 13;
+        st ^= st >> 7;
+        st ^= st << 17;
+        return double(st >> 11) * (1.0 / 9007199254740992.0);
+    };
+    for (int r = 0; r < n_time; ++r) {
+        if (planar) {
+            const double th = 2 * 3.14159265358979323846 * rnd();
+            q[4 * r] = std::cos(th / 2);
+            q[4 * r + 1] = 0;
+            q[4 * r + 2] = 0;
+            q[4 * r + 3] = std::sin(th / 2);
+        } else {
+            const double u1 = rnd(), u2 = rnd(), u3 = rnd();
+            q[4 * r] = std::sqrt(u1) * std::cos(2 * 3.14159265358979323846 * u3);
+            q[4 * r + 1] = std::sqrt(1 - u1) * std::sin(2 * 3.14159265358979323846 * u2);
+            q[4 * r + 2] = std::sqrt(1 - u1) * std::cos(2 * 3.14159265358979323846 * u2);
+            q[4 * r + 3] = std::sqrt(u1) * std::sin(2 * 3.14159265358979323846 * u3);
+        }
+    }
+    sdf_grid gf{{N, N, nz}, {0, 0, 0}, 1.0};
+    sdf_grid gm{{n_m, n_m, planar ? 1 : n_m}, {0, 0, 0}, 1.0};
+    // reference peaks from the plain path
+    PairIn ref{spec, &gf, rho, w, &gm, q.data(), n_probe, sc_ref, static_cast<int32_t*>(tt_ref), nullptr, nullptr};
+    int rc = plain_pair<float>(ctx, ref, Mode::Peaks, nullptr, s);
+    if (rc) {
+        cleanup();
+        return rc;
+    }
+    std::vector<float> s_ref(n_probe), s_got(n_probe);
+    std::vector<int32_t> t_ref(3 * n_probe), t_got(3 * n_probe);
+    if (hipStreamSynchronize(s) != hipSuccess || hipMemcpy(s_ref.data(), sc_ref, 4 * n_probe, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(t_ref.data(), tt_ref, 12 * n_probe, hipMemcpyDeviceToHost) != hipSuccess) {
+        cleanup();
+        return fail(ctx, SDF_EHIP, "autotune readback failed");
+    }
+    float smax = 0.f;
+    for (float v : s_ref) smax = std::max(smax, std::fabs(v));
+    const int64_t save_batch = ctx->opt_batch, save_group = ctx->opt_pencil_group, save_radix = ctx->opt_radix;
+    const int64_t save_graph = ctx->opt_graph, save_auto = ctx->opt_autotune, save_prof = ctx->opt_profile;
+    ctx->opt_graph = 0;
+    ctx->opt_autotune = 0;
+    ctx->opt_profile = 0;
+    ctx->tuned.erase(class_key(N, planar));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    Tuned best{int(save_batch), int(save_group), int(save_radix)};
+    float best_ms = 1e30f;
+    std::string rep = "{\"N\": " + std::to_string(N) + ", \"n_m\": " + std::to_string(n_m) +
+                      ", \"planar\": " + (planar ? "true" : "false") + ", \"candidates\": [";
+    bool first = true;
+    for (int batch : {32, 64, 128}) {
+        for (int group : {2, 4}) {
+            for (int radix : {0, 1, 2}) {
+                ctx->opt_batch = batch;
+                ctx->opt_pencil_group = group;
+                ctx->opt_radix = radix;
+                PairIn pr{spec, &gf, rho, w, &gm, q.data(), n_time, sc, static_cast<int32_t*>(tt), nullptr, nullptr};
+                std::vector<PairIn> one{pr};
+                rc = fused_pairs(ctx, one, s);  // warm-up and parity probe
+                bool ok = rc == SDF_OK;
+                if (ok) {
+                    ok = hipStreamSynchronize(s) == hipSuccess &&
+                         hipMemcpy(s_got.data(), sc, 4 * n_probe, hipMemcpyDeviceToHost) == hipSuccess &&
+                         hipMemcpy(t_got.data(), tt, 12 * n_probe, hipMemcpyDeviceToHost) == hipSuccess;
+                    for (int r = 0; ok && r < n_probe; ++r)
+                        ok = std::fabs(s_got[r] - s_ref[r]) <= 1e-4f * smax + 1e-30f;
+                }
+                float ms = -1.f;
+                if (ok) {
+                    (void)hipEventRecord(e0, s);
+                    for (int it = 0; it < 2 && rc == SDF_OK; ++it) rc = fused_pairs(ctx, one, s);
+                    (void)hipEventRecord(e1, s);
+                    (void)hipEventSynchronize(e1);
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ms /= 2;
+                    if (rc == SDF_OK && ms < best_ms) {
+                        best_ms = ms;
+                        best = Tuned{batch, group, radix};
+                    }
+                }
+                if (!first) rep += ", ";
+                first = false;
+                rep += "{\"batch\": " + std::to_string(batch) + ", \"group\": " + std::to_string(group) +
+                       ", \"radix\": " + std::to_string(radix) + ", \"parity\": " + (ok ? "true" : "false") +
+                       ", \"ms_per_rotation\": " + std::to_string(ms / n_time) + "}";
+                rc = SDF_OK;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->opt_batch = save_batch;
+    ctx->opt_pencil_group = save_group;
+    ctx->opt_radix = save_radix;
+    ctx->opt_graph = save_graph;
+    ctx->opt_autotune = save_auto;
+    ctx->opt_profile = save_prof;
+    (void)hipStreamSynchronize(s);
+    cleanup();
+    if (best_ms >= 1e30f) return fail(ctx, SDF_EHIP, "autotune: no candidate passed the parity probe");
+    ctx->tuned[class_key(N, planar)] = best;
+    rep += "], \"chosen\": {\"batch\": " + std::to_string(best.batch) + ", \"group\": " +
+           std::to_string(best.group) + ", \"radix\": " + std::to_string(best.radix) +
+           ", \"ms_per_rotation\": " + std::to_string(best_ms / n_time) + "}}";
+    if (report) *report = rep;
+    ctx->last_report = rep;
     return SDF_OK;
 }
 
@@ -401,6 +694,9 @@ int sdf_ctx_create(sdf_ctx* out, int device, sdf_dtype dtype, size_t workspace_c
     ctx->device = device;
     ctx->dtype = dtype;
     ctx->cap = workspace_cap_bytes;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        ctx->num_cu = prop.multiProcessorCount;
     *out = ctx;
     return SDF_OK;
 }
@@ -426,6 +722,7 @@ int sdf_ctx_set_option(sdf_ctx ctx, const char* key, int64_t value) {
     } else if (!std::strcmp(key, "batch")) {
         if (value < 2 || value > 256 || (value & 1)) return fail(ctx, SDF_EINVAL, "batch must be even, 2..256");
         ctx->opt_batch = value;
+        ctx->tuned.clear();
     } else if (!std::strcmp(key, "graph")) {
         if (value != 0 && value != 1) return fail(ctx, SDF_EINVAL, "graph must be 0 or 1");
         ctx->opt_graph = value;
@@ -435,6 +732,13 @@ int sdf_ctx_set_option(sdf_ctx ctx, const char* key, int64_t value) {
     } else if (!std::strcmp(key, "profile")) {
         if (value != 0 && value != 1) return fail(ctx, SDF_EINVAL, "profile must be 0 or 1");
         ctx->opt_profile = value;
+    } else if (!std::strcmp(key, "radix")) {
+        if (value < 0 || value > 2) return fail(ctx, SDF_EINVAL, "radix must be 0, 1 or 2");
+        ctx->opt_radix = value;
+        ctx->tuned.clear();
+    } else if (!std::strcmp(key, "autotune")) {
+        if (value != 0 && value != 1) return fail(ctx, SDF_EINVAL, "autotune must be 0 or 1");
+        ctx->opt_autotune = value;
     } else {
         return fail(ctx, SDF_EINVAL, std::string("unknown option ") + key);
     }
@@ -448,6 +752,9 @@ int sdf_ctx_get_option(sdf_ctx ctx, const char* key, int64_t* value) {
     else if (!std::strcmp(key, "graph")) *value = ctx->opt_graph;
     else if (!std::strcmp(key, "pencil_group")) *value = ctx->opt_pencil_group;
     else if (!std::strcmp(key, "profile")) *value = ctx->opt_profile;
+    else if (!std::strcmp(key, "radix")) *value = ctx->opt_radix;
+    else if (!std::strcmp(key, "autotune")) *value = ctx->opt_autotune;
+    else if (!std::strcmp(key, "num_cu")) *value = ctx->num_cu;
     else if (!std::strcmp(key, "graph_captures")) *value = ctx->graph_captures;
     else if (!std::strcmp(key, "graph_launches")) *value = ctx->graph_launches;
     else return fail(ctx, SDF_EINVAL, std::string("unknown option ") + key);
@@ -485,13 +792,11 @@ int sdf_build(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_
     if (!dg.ok) return fail(ctx, SDF_EHIP, "cannot select device");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const sdf::ParamDesc pd{p->lambda1, p->lambda2, p->sigma, p->eps, p->xi_floor};
-    hipError_t e;
-    if (ctx->dtype == SDF_F64)
-        e = sdf::launch_sdf_build<double>(static_cast<const double*>(q), static_cast<const double*>(nrm),
-                                          static_cast<const double*>(w), n, desc(g), pd, rho_out, s);
-    else
-        e = sdf::launch_sdf_build<float>(static_cast<const float*>(q), static_cast<const float*>(nrm),
-                                         static_cast<const float*>(w), n, desc(g), pd, rho_out, s);
+    const double* qd = static_cast<const double*>(q);
+    const double* nd = static_cast<const double*>(nrm);
+    const double* wd = static_cast<const double*>(w);
+    hipError_t e = ctx->dtype == SDF_F64 ? sdf::launch_sdf_build<double>(qd, nd, wd, n, desc(g), pd, rho_out, s)
+                                         : sdf::launch_sdf_build<float>(qd, nd, wd, n, desc(g), pd, rho_out, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "sdf_build");
     return SDF_OK;
 }
@@ -540,14 +845,58 @@ int score_rotations(sdf_ctx ctx, const void* spec_fixed, const sdf_grid* g_fixed
     if (rc) return rc;
     rc = check_quats(ctx, quats, n_rot);
     if (rc) return rc;
+    if (n_rot > (int64_t(1) << 28)) return fail(ctx, SDF_EINVAL, "n_rot too large");
     if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (ctx->dtype == SDF_F64)
-        return search_impl<double>(ctx, spec_fixed, g_fixed, rho_moving, w_moving, g_moving, quats, n_rot,
-                                   Mode::Peaks, peak_score, peak_t, peak_nbhd, refined_t, nullptr, s);
-    return search_impl<float>(ctx, spec_fixed, g_fixed, rho_moving, w_moving, g_moving, quats, n_rot, Mode::Peaks,
-                              peak_score, peak_t, peak_nbhd, refined_t, nullptr, s);
+    std::vector<PairIn> pairs{PairIn{spec_fixed, g_fixed, rho_moving, w_moving, g_moving, quats, n_rot, peak_score,
+                                     peak_t, peak_nbhd, refined_t}};
+    if (ctx->dtype == SDF_F64) return search_impl<double>(ctx, pairs, Mode::Peaks, nullptr, s);
+    return search_impl<float>(ctx, pairs, Mode::Peaks, nullptr, s);
+}
+
+int score_pairs(sdf_ctx ctx, const sdf_pair_job* jobs, int64_t n_jobs, sdf_stream stream) {
+    if (!jobs || n_jobs <= 0) return fail(ctx, SDF_EINVAL, "need n_jobs > 0 and a job array");
+    if (n_jobs > (int64_t(1) << 20)) return fail(ctx, SDF_EINVAL, "too many jobs");
+    std::vector<PairIn> pairs;
+    int64_t total = 0;
+    for (int64_t j = 0; j < n_jobs; ++j) {
+        const sdf_pair_job& jb = jobs[j];
+        if (!jb.spec_fixed || !jb.rho_moving || !jb.w_moving || !jb.peak_score || !jb.peak_t)
+            return fail(ctx, SDF_EINVAL, "job " + std::to_string(j) + ": NULL array");
+        int rc = check_pair(ctx, &jb.g_fixed, &jb.g_moving, true);
+        if (rc) return fail(ctx, rc, "job " + std::to_string(j) + ": " + g_err);
+        rc = check_quats(ctx, jb.quats, jb.n_rot);
+        if (rc) return fail(ctx, rc, "job " + std::to_string(j) + ": " + g_err);
+        total += jb.n_rot;
+        pairs.push_back(PairIn{jb.spec_fixed, &jb.g_fixed, jb.rho_moving, jb.w_moving, &jb.g_moving, jb.quats,
+                               jb.n_rot, jb.peak_score, jb.peak_t, jb.peak_nbhd, jb.refined_t});
+    }
+    if (total > (int64_t(1) << 28)) return fail(ctx, SDF_EINVAL, "too many rotations");
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->dtype == SDF_F64) return search_impl<double>(ctx, pairs, Mode::Peaks, nullptr, s);
+    return search_impl<float>(ctx, pairs, Mode::Peaks, nullptr, s);
+}
+
+int sdf_autotune(sdf_ctx ctx, const sdf_grid* g_fixed, const sdf_grid* g_moving, char* report, size_t report_len,
+                 sdf_stream stream) {
+    int rc = check_pair(ctx, g_fixed, g_moving, true);
+    if (rc) return rc;
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    if (ctx->dtype != SDF_F32) return fail(ctx, SDF_EUNSUPPORTED, "autotuning applies to FP32 contexts");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    std::string rep;
+    rc = autotune_class(ctx, g_fixed->n[0], g_fixed->n[2] == 1, g_moving->n[0], s, &rep);
+    if (rc) return rc;
+    if (report && report_len > 0) {
+        const size_t n = std::min(report_len - 1, rep.size());
+        std::memcpy(report, rep.data(), n);
+        report[n] = 0;
+    }
+    return SDF_OK;
 }
 
 int score_volume(sdf_ctx ctx, const void* spec_fixed, const sdf_grid* g_fixed, const void* rho_moving,
@@ -561,11 +910,10 @@ int score_volume(sdf_ctx ctx, const void* spec_fixed, const sdf_grid* g_fixed, c
     if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (ctx->dtype == SDF_F64)
-        return search_impl<double>(ctx, spec_fixed, g_fixed, rho_moving, w_moving, g_moving, quats, n_rot,
-                                   Mode::Volume, nullptr, nullptr, nullptr, nullptr, vol_out, s);
-    return search_impl<float>(ctx, spec_fixed, g_fixed, rho_moving, w_moving, g_moving, quats, n_rot, Mode::Volume,
-                              nullptr, nullptr, nullptr, nullptr, vol_out, s);
+    std::vector<PairIn> pairs{PairIn{spec_fixed, g_fixed, rho_moving, w_moving, g_moving, quats, n_rot, nullptr,
+                                     nullptr, nullptr, nullptr}};
+    if (ctx->dtype == SDF_F64) return search_impl<double>(ctx, pairs, Mode::Volume, vol_out, s);
+    return search_impl<float>(ctx, pairs, Mode::Volume, vol_out, s);
 }
 
 int sdf_spread(sdf_ctx ctx, const sdf_grid* g_fixed, const void* rho_moving, const void* w_moving,
@@ -577,6 +925,7 @@ int sdf_spread(sdf_ctx ctx, const sdf_grid* g_fixed, const void* rho_moving, con
     if (rc) return rc;
     if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
+    ctx->fused_cache_valid = false;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t K = gsize(g_moving), G = gsize(g_fixed);
     const bool planar = g_fixed->n[2] == 1;
@@ -620,6 +969,7 @@ int sdf_topk(sdf_ctx ctx, const void* scores, int64_t n, int64_t k, int32_t* idx
     if (n > (int64_t(1) << 30)) return fail(ctx, SDF_EINVAL, "n too large");
     if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
+    ctx->fused_cache_valid = false;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = ensure_ws(ctx, sdf::topk_workspace_bytes(n));
     if (rc) return rc;
@@ -640,6 +990,7 @@ int score_grad(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, cons
     if (rc) return rc;
     if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
+    ctx->fused_cache_valid = false;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool planar = g_fixed->n[2] == 1;
     const int N = g_fixed->n[0], nm = g_moving->n[0];

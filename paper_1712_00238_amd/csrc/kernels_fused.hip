@@ -29,6 +29,12 @@
 //                   accumulation); K5 assembles the 27 values and refines the
 //                   peak per axis in FP64.
 //
+// Work is described by descriptors: one FusedJob per pair (coefficients,
+// spectrum, fixed-point scale, outputs) and one FusedRot per rotation (FP32
+// matrix, owning pair, local index), so one launch sequence serves any mix
+// of pairs that share the grid size N.  K1-K3 are persistent: a grid sized
+// to the device walks the batch's work items with a stride.
+//
 // Correlation form: f(R, t) = sum_p rho_F(p) M_R(p - t) is a circular
 // convolution of rho_F with the reflected spread Mr(u) = M_R(-u), i.e. the
 // spread of the samples at -R x_k / h.  So fft(f) = S(k) * fft(Mr)(k) with
@@ -46,6 +52,7 @@ using cf = cplx<float>;
 constexpr int kSlabBlock = 1024;
 constexpr int kPencilBlock = 512;
 constexpr int kFinishBlock = 256;
+constexpr int kPrepBlocks = 64;
 
 template <int N>
 constexpr int pencil_width() {
@@ -54,12 +61,75 @@ constexpr int pencil_width() {
 
 size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
-// ------------------------------------------------------------------ K1
-// ------------------------------------------------------------------ K0
-constexpr int kPrepBlocks = 256;
+// radix schedules selectable per size (threads per line stay N / 8)
+template <int N, int P>
+struct FusedRadix;
+template <> struct FusedRadix<8, 0> { using type = Radices<8>; };
+template <> struct FusedRadix<8, 1> { using type = Radices<2, 4>; };
+template <> struct FusedRadix<8, 2> { using type = Radices<4, 2>; };
+template <> struct FusedRadix<16, 0> { using type = Radices<4, 4>; };
+template <> struct FusedRadix<16, 1> { using type = Radices<8, 2>; };
+template <> struct FusedRadix<16, 2> { using type = Radices<2, 8>; };
+template <> struct FusedRadix<32, 0> { using type = Radices<8, 4>; };
+template <> struct FusedRadix<32, 1> { using type = Radices<4, 8>; };
+template <> struct FusedRadix<32, 2> { using type = Radices<2, 4, 4>; };
+template <> struct FusedRadix<64, 0> { using type = Radices<8, 8>; };
+template <> struct FusedRadix<64, 1> { using type = Radices<4, 4, 4>; };
+template <> struct FusedRadix<64, 2> { using type = Radices<2, 4, 8>; };
+template <> struct FusedRadix<96, 0> { using type = Radices<8, 4, 3>; };
+template <> struct FusedRadix<96, 1> { using type = Radices<3, 4, 8>; };
+template <> struct FusedRadix<96, 2> { using type = Radices<4, 8, 3>; };
+template <> struct FusedRadix<128, 0> { using type = Radices<8, 4, 4>; };
+template <> struct FusedRadix<128, 1> { using type = Radices<4, 4, 8>; };
+template <> struct FusedRadix<128, 2> { using type = Radices<2, 8, 8>; };
 
-__global__ __launch_bounds__(256) void cmax_partial_kernel(const cf* __restrict__ c, int64_t K,
+// Copy COUNT 16-byte words from global memory to LDS: every thread issues
+// all of its loads before its first LDS write, so the loads overlap.
+template <int COUNT, int BLOCK>
+__device__ __forceinline__ void stage_to_lds(float4* __restrict__ lds, const float4* __restrict__ g) {
+    constexpr int PER = (COUNT + BLOCK - 1) / BLOCK;
+    float4 r[PER];
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int i = threadIdx.x + p * BLOCK;
+        if (COUNT % BLOCK == 0 || i < COUNT) r[p] = g[i];
+    }
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+        const int i = threadIdx.x + p * BLOCK;
+        if (COUNT % BLOCK == 0 || i < COUNT) lds[i] = r[p];
+    }
+}
+
+// ------------------------------------------------------------------ rotations
+__global__ void rot_desc_kernel(const RotInput* __restrict__ in, int64_t n, FusedRot* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const RotInput r = in[i];
+    double w = r.q[0], x = r.q[1], y = r.q[2], z = r.q[3];
+    const double inv = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    w *= inv;
+    x *= inv;
+    y *= inv;
+    z *= inv;
+    const double m[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z),     2 * (x * z + w * y),
+                         2 * (x * y + w * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                         2 * (x * z - w * y),     2 * (y * z + w * x),     1 - 2 * (x * x + y * y)};
+    FusedRot o;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) o.R[a] = float(m[a]);
+    o.job = r.job;
+    o.local = r.local;
+    o.pad = 0;
+    out[i] = o;
+}
+
+// ------------------------------------------------------------------ K0
+__global__ __launch_bounds__(256) void cmax_partial_kernel(const FusedJob* __restrict__ jobs,
                                                            float* __restrict__ part) {
+    const FusedJob jb = jobs[blockIdx.y];
+    const cf* c = static_cast<const cf*>(jb.c);
+    const int64_t K = int64_t(jb.n_m) * jb.n_m * (jb.planar ? 1 : jb.n_m);
     float m = 0.f;
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < K; i += int64_t(gridDim.x) * 256) {
         const cf v = c[i];
@@ -69,105 +139,59 @@ __global__ __launch_bounds__(256) void cmax_partial_kernel(const cf* __restrict_
     __shared__ float wm[4];
     if (threadIdx.x % warpSize == 0) wm[threadIdx.x / warpSize] = m;
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+    if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
 }
 
-// scale[0] = fixed-point units per unit value, scale[1] = its inverse
-__global__ void cmax_final_kernel(const float* __restrict__ part, int n, float* __restrict__ scale) {
+// scale = fixed-point units per unit value: |node sum| <= 8 max|c| maps into 2^31
+__global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float* __restrict__ part, int nparts) {
     float m = 0.f;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmaxf(m, part[i]);
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = fmaxf(m, part[blockIdx.x * nparts + i]);
     for (int off = warpSize / 2; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if (threadIdx.x == 0) {
-        // |node sum| <= 8 max|c|  ->  8 max|c| * S <= 2^31
         const float sc = m > 0.f ? 268435456.f / m : 1.f;
-        scale[0] = sc;
-        scale[1] = 1.f / sc;
+        float* out = jobs[blockIdx.x].scale;
+        out[0] = sc;
+        out[1] = 1.f / sc;
     }
 }
 
 // ------------------------------------------------------------------ K1
-template <int N>
-__global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const float* __restrict__ Rm,
-                                                                 const cf* __restrict__ c, int n_m, int planar,
-                                                                 const float* __restrict__ scale,
-                                                                 cf* __restrict__ slabs) {
+// Work item = (z-slab, rotation), z fastest.
+template <int N, int P>
+__global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot* __restrict__ rots,
+                                                                 const FusedJob* __restrict__ jobs, int n_rot,
+                                                                 int planar, cf* __restrict__ slabs) {
+    using Plan = typename FusedRadix<N, P>::type;
     __shared__ cf slab[N * N];
     __shared__ cf tw[N];
-    const int z = blockIdx.x;
-    const int rot = blockIdx.y;
     const int nz = planar ? 1 : N;
     fill_twiddles<float, N>(tw);
-    int* acc = reinterpret_cast<int*>(slab);  // fixed-point (re, im) pairs
-    for (int i = threadIdx.x; i < 2 * N * N; i += kSlabBlock) acc[i] = 0;
-    const float S = scale[0];
-    __syncthreads();
-
-    // reflected rotation: positions y_k = Rp (k - n_m / 2), Rp = -R
-    float Rp[9];
+    int* acc = reinterpret_cast<int*>(slab);  // re plane [0, N^2), im plane [N^2, 2 N^2)
+    const int items = nz * n_rot;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int z = item % nz;
+        const int rot = item / nz;
+        const FusedRot fr = rots[rot];
+        const FusedJob jb = jobs[fr.job];
+        const cf* __restrict__ c = static_cast<const cf*>(jb.c);
+        const int n_m = jb.n_m;
+        __syncthreads();  // previous item's slab fully stored
+        for (int i = threadIdx.x; i < 2 * N * N; i += kSlabBlock) acc[i] = 0;
+        const float S = jb.scale[0];
+        __syncthreads();
+        // reflected rotation: positions y_k = Rp (k - n_m / 2), Rp = -R
+        float Rp[9];
 #pragma unroll
-    for (int a = 0; a < 9; ++a) Rp[a] = -Rm[9 * rot + a];
-    const float half = 0.5f * float(n_m);
-    if (planar) {
-        const int K = n_m * n_m;
-        for (int k = threadIdx.x; k < K; k += kSlabBlock) {
-            const cf ck = c[k];
-            const float cre = ck.re * S, cim = ck.im * S;
-            const float bx = float(k % n_m) - half, by = float(k / n_m) - half;
-            const float yx = Rp[0] * bx + Rp[1] * by;
-            const float yy = Rp[3] * bx + Rp[4] * by;
-            const float fx = floorf(yx), fy = floorf(yy);
-            float wx[4], wy[4];
-            bspline3_weights(yx - fx, wx);
-            bspline3_weights(yy - fy, wy);
-            const int ix = int(fx) - 1, iy = int(fy) - 1;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int row = wrap(iy + b, N) * N;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) {
-                    const float wt = wx[a] * wy[b];
-                    const int idx = 2 * (row + wrap(ix + a, N));
-                    atomicAdd(acc + idx, __float2int_rn(cre * wt));
-                    atomicAdd(acc + idx + 1, __float2int_rn(cim * wt));
-                }
-            }
-        }
-    } else {
-        // dominant body axis of the z row: walk it, enumerate the other two
-        int ax = 0;
-        float best = fabsf(Rp[6]);
-        if (fabsf(Rp[7]) > best) { ax = 1; best = fabsf(Rp[7]); }
-        if (fabsf(Rp[8]) > best) { ax = 2; }
-        const int b1 = ax == 0 ? 1 : 0;
-        const int b2 = ax == 2 ? 1 : 2;
-        const float sa = Rp[6 + ax];
-        const float zc = float(z < N / 2 ? z : z - N);  // centred image of this slab
-        const int pairs = n_m * n_m;
-        for (int pidx = threadIdx.x; pidx < pairs; pidx += kSlabBlock) {
-            int kk[3];
-            kk[b1] = pidx % n_m;
-            kk[b2] = pidx / n_m;
-            const float base = Rp[6 + b1] * (float(kk[b1]) - half) + Rp[6 + b2] * (float(kk[b2]) - half);
-            float lo_f = (zc - 2.f - base) / sa, hi_f = (zc + 2.f - base) / sa;
-            if (lo_f > hi_f) { float t = lo_f; lo_f = hi_f; hi_f = t; }
-            int lo = int(floorf(lo_f + half)), hi = int(ceilf(hi_f + half));
-            lo = lo < 0 ? 0 : lo;
-            hi = hi > n_m - 1 ? n_m - 1 : hi;
-            for (int ka = lo; ka <= hi; ++ka) {
-                kk[ax] = ka;
-                const float bx = float(kk[0]) - half, by = float(kk[1]) - half, bz = float(kk[2]) - half;
-                const float yz = Rp[6] * bx + Rp[7] * by + Rp[8] * bz;
-                const float dz = zc - yz;
-                if (!(fabsf(dz) < 2.f)) continue;
-                const float yx = Rp[0] * bx + Rp[1] * by + Rp[2] * bz;
-                const float yy = Rp[3] * bx + Rp[4] * by + Rp[5] * bz;
-                const float ad = fabsf(dz);
-                float wz;
-                if (ad < 1.f) wz = 2.f / 3.f - ad * ad + 0.5f * ad * ad * ad;
-                else { const float b = 2.f - ad; wz = b * b * b / 6.f; }
-                const int k = (kk[2] * n_m + kk[1]) * n_m + kk[0];
+        for (int a = 0; a < 9; ++a) Rp[a] = -fr.R[a];
+        const float half = 0.5f * float(n_m);
+        if (planar) {
+            const int K = n_m * n_m;
+            for (int k = threadIdx.x; k < K; k += kSlabBlock) {
                 const cf ck = c[k];
-                const float cre = ck.re * (wz * S), cim = ck.im * (wz * S);
+                const float cre = ck.re * S, cim = ck.im * S;
+                const float bx = float(k % n_m) - half, by = float(k / n_m) - half;
+                const float yx = Rp[0] * bx + Rp[1] * by;
+                const float yy = Rp[3] * bx + Rp[4] * by;
                 const float fx = floorf(yx), fy = floorf(yy);
                 float wx[4], wy[4];
                 bspline3_weights(yx - fx, wx);
@@ -179,25 +203,110 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const float* __
 #pragma unroll
                     for (int a = 0; a < 4; ++a) {
                         const float wt = wx[a] * wy[b];
-                        const int idx = 2 * (row + wrap(ix + a, N));
+                        const int idx = row + wrap(ix + a, N);
                         atomicAdd(acc + idx, __float2int_rn(cre * wt));
-                        atomicAdd(acc + idx + 1, __float2int_rn(cim * wt));
+                        atomicAdd(acc + N * N + idx, __float2int_rn(cim * wt));
+                    }
+                }
+            }
+        } else {
+            // Walk body lines along the axis ax most aligned with z: for each
+            // (k_b1, k_b2) the samples y(ka) = y0 + ka d (d = column ax of the
+            // reflected rotation) cross the slab support |z - y_z| < 2 for a
+            // short run of ka; positions and indices advance by constant
+            // steps and the next coefficient is fetched one step ahead.
+            int ax = 0;
+            float best = fabsf(Rp[6]);
+            if (fabsf(Rp[7]) > best) { ax = 1; best = fabsf(Rp[7]); }
+            if (fabsf(Rp[8]) > best) { ax = 2; }
+            // consecutive lanes step along the remaining axis most aligned
+            // with x, so their stencils land in consecutive LDS banks
+            int b1 = ax == 0 ? 1 : 0;
+            int b2 = ax == 2 ? 1 : 2;
+            if (fabsf(Rp[b2]) > fabsf(Rp[b1])) { const int t = b1; b1 = b2; b2 = t; }
+            const float dx = Rp[ax], dy = Rp[3 + ax], dzs = Rp[6 + ax];
+            const float inv_dz = 1.f / dzs;
+            const int kstride[3] = {1, n_m, n_m * n_m};
+            const int sax = kstride[ax];
+            const float zc = float(z < N / 2 ? z : z - N);  // centred image of this slab
+            const int pairs = n_m * n_m;
+            for (int pidx = threadIdx.x; pidx < pairs; pidx += kSlabBlock) {
+                const int i1 = pidx % n_m, i2 = pidx / n_m;
+                const float u1 = float(i1) - half, u2 = float(i2) - half, u0 = -half;
+                const float y0x = Rp[b1] * u1 + Rp[b2] * u2 + dx * u0;
+                const float y0y = Rp[3 + b1] * u1 + Rp[3 + b2] * u2 + dy * u0;
+                const float y0z = Rp[6 + b1] * u1 + Rp[6 + b2] * u2 + dzs * u0;
+                float lo_f = (zc - 2.f - y0z) * inv_dz, hi_f = (zc + 2.f - y0z) * inv_dz;
+                if (lo_f > hi_f) { const float t = lo_f; lo_f = hi_f; hi_f = t; }
+                int lo = int(floorf(lo_f)), hi = int(ceilf(hi_f));
+                lo = lo < 0 ? 0 : lo;
+                hi = hi > n_m - 1 ? n_m - 1 : hi;
+                if (lo > hi) continue;
+                const int k0 = i1 * kstride[b1] + i2 * kstride[b2];
+                cf cnext = c[k0 + lo * sax];
+                for (int ka = lo; ka <= hi; ++ka) {
+                    const cf ck = cnext;
+                    if (ka < hi) cnext = c[k0 + (ka + 1) * sax];
+                    const float fk = float(ka);
+                    const float yz = y0z + fk * dzs;
+                    const float ad = fabsf(zc - yz);
+                    if (!(ad < 2.f)) continue;
+                    const float yx = y0x + fk * dx;
+                    const float yy = y0y + fk * dy;
+                    float wz;
+                    if (ad < 1.f) wz = 2.f / 3.f - ad * ad + 0.5f * ad * ad * ad;
+                    else { const float b = 2.f - ad; wz = b * b * b / 6.f; }
+                    const float sw = wz * S;
+                    const float fx = floorf(yx), fy = floorf(yy);
+                    float wx[4], wy[4];
+                    bspline3_weights(yx - fx, wx);
+                    bspline3_weights(yy - fy, wy);
+                    const int ix = int(fx) - 1, iy = int(fy) - 1;
+                    float xr[4], xi[4];
+                    int col[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        xr[a] = ck.re * sw * wx[a];
+                        xi[a] = ck.im * sw * wx[a];
+                        col[a] = wrap(ix + a, N);
+                    }
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int row = wrap(iy + b, N) * N;
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            const int idx = row + col[a];
+                            atomicAdd(acc + idx, __float2int_rn(xr[a] * wy[b]));
+                            atomicAdd(acc + N * N + idx, __float2int_rn(xi[a] * wy[b]));
+                        }
                     }
                 }
             }
         }
+        __syncthreads();
+        {
+            // planes -> interleaved complex, in place: read everything, then write
+            constexpr int PER = (N * N + kSlabBlock - 1) / kSlabBlock;
+            const float inv = jb.scale[1];
+            cf v[PER];
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int i = threadIdx.x + p * kSlabBlock;
+                if ((N * N) % kSlabBlock == 0 || i < N * N) v[p] = mk(float(acc[i]) * inv, float(acc[N * N + i]) * inv);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int i = threadIdx.x + p * kSlabBlock;
+                if ((N * N) % kSlabBlock == 0 || i < N * N) slab[i] = v[p];
+            }
+        }
+        __syncthreads();
+        lds_fft_lines<float, N, -1, false, Plan>(slab, 1, N, N, tw);  // along x
+        lds_fft_lines<float, N, -1, true, Plan>(slab, N, 1, N, tw);   // along y
+        cf* out = slabs + (int64_t(rot) * nz + z) * N * N;
+        for (int i = threadIdx.x; i < N * N; i += kSlabBlock) out[i] = slab[i];
     }
-    __syncthreads();
-    const float inv = scale[1];
-    for (int i = threadIdx.x; i < N * N; i += kSlabBlock) {
-        const int2 v = reinterpret_cast<const int2*>(acc)[i];
-        slab[i] = mk(float(v.x) * inv, float(v.y) * inv);
-    }
-    __syncthreads();
-    lds_fft_lines<float, N, -1, false>(slab, 1, N, N, tw);  // along x
-    lds_fft_lines<float, N, -1, true>(slab, N, 1, N, tw);   // along y
-    cf* out = slabs + (int64_t(rot) * nz + z) * N * N;
-    for (int i = threadIdx.x; i < N * N; i += kSlabBlock) out[i] = slab[i];
 }
 
 // ------------------------------------------------------------------ K2
@@ -222,79 +331,115 @@ constexpr int pencil_jobs() {
     return (N / 2 - 1) * (N / W) + 2 * ((N / 2 + 1 + W - 1) / W);
 }
 
-// NZ = N (3D) or 1 (planar); GR rotations per block (2 or 4)
-template <int N, int NZ, int GR>
-__global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const cf* __restrict__ slabs,
-                                                              const cf* __restrict__ spec, int nb,
+// Work item = (pencil tile pair, group of GR rotations).  NZ = N (3D) or 1 (planar).
+template <int N, int NZ, int GR, int P>
+__global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __restrict__ rots,
+                                                              const FusedJob* __restrict__ jobs, int n_rot,
+                                                              const cf* __restrict__ slabs,
                                                               cf* __restrict__ packed) {
+    using Plan = typename FusedRadix<(NZ > 1 ? NZ : 8), P>::type;
     constexpr int W = pencil_width<N>();
     constexpr int NL = 2 * W * GR;  // lines: (rotation, tile, column)
     __shared__ cf buf[NZ * NL];
     __shared__ cf tw[NZ > 1 ? NZ : 1];
-    const PencilJob job = pencil_job<N>(blockIdx.x);
-    const int g0 = blockIdx.y * GR;  // first rotation of the group in the batch
+    __shared__ const cf* spec_of[GR];
     const int64_t G = int64_t(N) * N * NZ;
-    const int kyt[2] = {job.ky, (N - job.ky) % N};
     if constexpr (NZ > 1) fill_twiddles<float, NZ>(tw);
-
     auto line_of = [](int r, int t, int cc) { return ((r & 1) * GR + (r >> 1) * 2 + t) * W + cc; };
-    auto kx_of = [&](int t, int cc) { return t == 0 ? job.x0 + cc : (N - job.x0 - cc) % N; };
-
-    // load both tiles of every rotation of the group (zeros for missing rotations)
-    for (int i = threadIdx.x; i < GR * 2 * NZ * W; i += kPencilBlock) {
-        const int cc = i % W;
-        const int kz = (i / W) % NZ;
-        const int t = (i / (W * NZ)) % 2;
-        const int r = i / (W * NZ * 2);
-        const int rot = g0 + r;
-        cf v = mk(0.f, 0.f);
-        if (rot < nb) v = slabs[int64_t(rot) * G + (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)];
-        buf[kz * NL + line_of(r, t, cc)] = v;
-    }
-    __syncthreads();
-    if constexpr (NZ > 1) lds_fft_lines<float, NZ, -1, true>(buf, NL, 1, NL, tw);
-    else __syncthreads();
-    // product with the fixed spectrum (read once, used by every rotation)
-    for (int i = threadIdx.x; i < 2 * NZ * W; i += kPencilBlock) {
-        const int cc = i % W;
-        const int kz = (i / W) % NZ;
-        const int t = i / (W * NZ);
-        const cf sv = spec[(int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)];
-#pragma unroll
-        for (int r = 0; r < GR; ++r) {
-            cf& y = buf[kz * NL + line_of(r, t, cc)];
-            y = y * sv;
+    const int ngroups = (n_rot + GR - 1) / GR;
+    const int items = pencil_jobs<N>() * ngroups;
+    const int npair = (n_rot + 1) / 2;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const PencilJob job = pencil_job<N>(item % pencil_jobs<N>());
+        const int g0 = (item / pencil_jobs<N>()) * GR;  // first rotation of the group
+        const int kyt[2] = {job.ky, (N - job.ky) % N};
+        auto kx_of = [&](int t, int cc) { return t == 0 ? job.x0 + cc : (N - job.x0 - cc) % N; };
+        __syncthreads();  // previous item done with buf / spec_of
+        if (threadIdx.x < GR) {
+            const int rot = g0 + threadIdx.x;
+            spec_of[threadIdx.x] = rot < n_rot ? static_cast<const cf*>(jobs[rots[rot].job].spec) : nullptr;
         }
-    }
-    __syncthreads();
-    // Hermitian folding of rotation pairs: A lines receive Z = H_A + i H_B
-    for (int i = threadIdx.x; i < (GR / 2) * NZ * W; i += kPencilBlock) {
-        const int cc = i % W;
-        const int kz = (i / W) % NZ;
-        const int p = i / (W * NZ);
-        const int mkz = (NZ - kz) % NZ;
-        const int a0 = line_of(2 * p, 0, cc), a1 = line_of(2 * p, 1, cc);
-        const int b0 = line_of(2 * p + 1, 0, cc), b1 = line_of(2 * p + 1, 1, cc);
-        const cf ya0 = buf[kz * NL + a0], ya1 = buf[mkz * NL + a1];
-        const cf yb0 = buf[kz * NL + b0], yb1 = buf[mkz * NL + b1];
-        const cf ha = (ya0 + conj(ya1)) * 0.5f;
-        const cf hb = (yb0 + conj(yb1)) * 0.5f;
-        buf[kz * NL + a0] = mk(ha.re - hb.im, ha.im + hb.re);
-        buf[mkz * NL + a1] = mk(ha.re + hb.im, hb.re - ha.im);
-    }
-    __syncthreads();
-    if constexpr (NZ > 1) lds_fft_lines<float, NZ, 1, true>(buf, NL, 1, GR * W, tw);
-    // write the folded pencils of each pair
-    const int pair0 = g0 / 2;
-    const int npair = (nb + 1) / 2;
-    for (int i = threadIdx.x; i < (GR / 2) * 2 * NZ * W; i += kPencilBlock) {
-        const int cc = i % W;
-        const int kz = (i / W) % NZ;
-        const int t = (i / (W * NZ)) % 2;
-        const int p = i / (W * NZ * 2);
-        if (pair0 + p >= npair) continue;
-        packed[int64_t(pair0 + p) * G + (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)] =
-            buf[kz * NL + line_of(2 * p, t, cc)];
+        // load both tiles of every rotation of the group (zeros for missing
+        // rotations); all loads of a thread are issued before its LDS writes
+        {
+            constexpr int TOT = GR * 2 * NZ * W;
+            constexpr int PER = (TOT + kPencilBlock - 1) / kPencilBlock;
+            cf v[PER];
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int i = threadIdx.x + p * kPencilBlock;
+                const int cc = i % W;
+                const int kz = (i / W) % NZ;
+                const int t = (i / (W * NZ)) % 2;
+                const int r = i / (W * NZ * 2);
+                const int rot = g0 + r;
+                v[p] = mk(0.f, 0.f);
+                if ((TOT % kPencilBlock == 0 || i < TOT) && rot < n_rot)
+                    v[p] = slabs[int64_t(rot) * G + (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)];
+            }
+#pragma unroll
+            for (int p = 0; p < PER; ++p) {
+                const int i = threadIdx.x + p * kPencilBlock;
+                if (TOT % kPencilBlock == 0 || i < TOT) {
+                    const int cc = i % W;
+                    const int kz = (i / W) % NZ;
+                    const int t = (i / (W * NZ)) % 2;
+                    const int r = i / (W * NZ * 2);
+                    buf[kz * NL + line_of(r, t, cc)] = v[p];
+                }
+            }
+        }
+        __syncthreads();
+        if constexpr (NZ > 1) lds_fft_lines<float, NZ, -1, true, Plan>(buf, NL, 1, NL, tw);
+        // product with each rotation's fixed spectrum (shared spectra hit in cache)
+        for (int i = threadIdx.x; i < 2 * NZ * W; i += kPencilBlock) {
+            const int cc = i % W;
+            const int kz = (i / W) % NZ;
+            const int t = i / (W * NZ);
+            const int64_t off = (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc);
+            const cf* prev = nullptr;
+            cf sv = mk(0.f, 0.f);
+#pragma unroll
+            for (int r = 0; r < GR; ++r) {
+                const cf* sp = spec_of[r];
+                if (sp == nullptr) continue;
+                if (sp != prev) {
+                    sv = sp[off];
+                    prev = sp;
+                }
+                cf& y = buf[kz * NL + line_of(r, t, cc)];
+                y = y * sv;
+            }
+        }
+        __syncthreads();
+        // Hermitian folding of rotation pairs: A lines receive Z = H_A + i H_B
+        for (int i = threadIdx.x; i < (GR / 2) * NZ * W; i += kPencilBlock) {
+            const int cc = i % W;
+            const int kz = (i / W) % NZ;
+            const int p = i / (W * NZ);
+            const int mkz = (NZ - kz) % NZ;
+            const int a0 = line_of(2 * p, 0, cc), a1 = line_of(2 * p, 1, cc);
+            const int b0 = line_of(2 * p + 1, 0, cc), b1 = line_of(2 * p + 1, 1, cc);
+            const cf ya0 = buf[kz * NL + a0], ya1 = buf[mkz * NL + a1];
+            const cf yb0 = buf[kz * NL + b0], yb1 = buf[mkz * NL + b1];
+            const cf ha = (ya0 + conj(ya1)) * 0.5f;
+            const cf hb = (yb0 + conj(yb1)) * 0.5f;
+            buf[kz * NL + a0] = mk(ha.re - hb.im, ha.im + hb.re);
+            buf[mkz * NL + a1] = mk(ha.re + hb.im, hb.re - ha.im);
+        }
+        __syncthreads();
+        if constexpr (NZ > 1) lds_fft_lines<float, NZ, 1, true, Plan>(buf, NL, 1, GR * W, tw);
+        // write the folded pencils of each pair
+        const int pair0 = g0 / 2;
+        for (int i = threadIdx.x; i < (GR / 2) * 2 * NZ * W; i += kPencilBlock) {
+            const int cc = i % W;
+            const int kz = (i / W) % NZ;
+            const int t = (i / (W * NZ)) % 2;
+            const int p = i / (W * NZ * 2);
+            if (pair0 + p >= npair) continue;
+            packed[int64_t(pair0 + p) * G + (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)] =
+                buf[kz * NL + line_of(2 * p, t, cc)];
+        }
     }
 }
 
@@ -314,48 +459,55 @@ __device__ __forceinline__ void wave_argmax(float& v, int& i) {
     }
 }
 
-template <int N>
-__global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __restrict__ packed, int nz, int nb,
+// Work item = (z-slab, rotation pair), z fastest.
+template <int N, int P>
+__global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __restrict__ packed, int nz, int n_rot,
                                                                 float* __restrict__ pval, int* __restrict__ pidx) {
+    using Plan = typename FusedRadix<N, P>::type;
     __shared__ cf slab[N * N];
     __shared__ cf tw[N];
     __shared__ float rv[2][kSlabBlock / 64];
     __shared__ int ri[2][kSlabBlock / 64];
-    const int z = blockIdx.x, pair = blockIdx.y;
     fill_twiddles<float, N>(tw);
-    const cf* src = packed + (int64_t(pair) * nz + z) * N * N;
-    for (int i = threadIdx.x; i < N * N; i += kSlabBlock) slab[i] = src[i];
-    __syncthreads();
-    lds_fft_lines<float, N, 1, true>(slab, N, 1, N, tw);   // along y
-    lds_fft_lines<float, N, 1, false>(slab, 1, N, N, tw);  // along x
-    float va = -INFINITY, vb = -INFINITY;
-    int ia = 0x7fffffff, ib = 0x7fffffff;
-    const int zoff = z * N * N;
-    for (int i = threadIdx.x; i < N * N; i += kSlabBlock) {
-        const cf v = slab[i];
-        if (better(v.re, zoff + i, va, ia)) { va = v.re; ia = zoff + i; }
-        if (better(v.im, zoff + i, vb, ib)) { vb = v.im; ib = zoff + i; }
-    }
-    wave_argmax(va, ia);
-    wave_argmax(vb, ib);
-    const int lane = threadIdx.x % warpSize, wid = threadIdx.x / warpSize;
-    if (lane == 0) {
-        rv[0][wid] = va;
-        ri[0][wid] = ia;
-        rv[1][wid] = vb;
-        ri[1][wid] = ib;
-    }
-    __syncthreads();
-    if (threadIdx.x < 2) {
-        const int w = threadIdx.x;
-        float bv = rv[w][0];
-        int bi = ri[w][0];
-        for (int k = 1; k < kSlabBlock / 64; ++k)
-            if (better(rv[w][k], ri[w][k], bv, bi)) { bv = rv[w][k]; bi = ri[w][k]; }
-        const int rot = 2 * pair + w;
-        if (rot < nb) {
-            pval[int64_t(rot) * nz + z] = bv;
-            pidx[int64_t(rot) * nz + z] = bi;
+    const int npair = (n_rot + 1) / 2;
+    const int items = nz * npair;
+    for (int item = blockIdx.x; item < items; item += gridDim.x) {
+        const int z = item % nz, pair = item / nz;
+        const cf* src = packed + (int64_t(pair) * nz + z) * N * N;
+        __syncthreads();
+        stage_to_lds<N * N / 2, kSlabBlock>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
+        __syncthreads();
+        lds_fft_lines<float, N, 1, true, Plan>(slab, N, 1, N, tw);   // along y
+        lds_fft_lines<float, N, 1, false, Plan>(slab, 1, N, N, tw);  // along x
+        float va = -INFINITY, vb = -INFINITY;
+        int ia = 0x7fffffff, ib = 0x7fffffff;
+        const int zoff = z * N * N;
+        for (int i = threadIdx.x; i < N * N; i += kSlabBlock) {
+            const cf v = slab[i];
+            if (better(v.re, zoff + i, va, ia)) { va = v.re; ia = zoff + i; }
+            if (better(v.im, zoff + i, vb, ib)) { vb = v.im; ib = zoff + i; }
+        }
+        wave_argmax(va, ia);
+        wave_argmax(vb, ib);
+        const int lane = threadIdx.x % warpSize, wid = threadIdx.x / warpSize;
+        if (lane == 0) {
+            rv[0][wid] = va;
+            ri[0][wid] = ia;
+            rv[1][wid] = vb;
+            ri[1][wid] = ib;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2) {
+            const int w = threadIdx.x;
+            float bv = rv[w][0];
+            int bi = ri[w][0];
+            for (int k = 1; k < kSlabBlock / 64; ++k)
+                if (better(rv[w][k], ri[w][k], bv, bi)) { bv = rv[w][k]; bi = ri[w][k]; }
+            const int rot = 2 * pair + w;
+            if (rot < n_rot) {
+                pval[int64_t(rot) * nz + z] = bv;
+                pidx[int64_t(rot) * nz + z] = bi;
+            }
         }
     }
 }
@@ -371,8 +523,8 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
                                                                    const float* __restrict__ pval,
                                                                    const int* __restrict__ pidx,
                                                                    double* __restrict__ nbbuf,
-                                                                   float* __restrict__ score,
-                                                                   int32_t* __restrict__ tout) {
+                                                                   const FusedRot* __restrict__ rots,
+                                                                   const FusedJob* __restrict__ jobs) {
     __shared__ float sv[kFinishBlock];
     __shared__ int si[kFinishBlock];
     __shared__ double twr[N], twi[N];
@@ -465,22 +617,29 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
         }
     }
     if (dzi == 1 && threadIdx.x == 0) {
-        score[rot] = bv;
-        tout[3 * rot] = tx;
-        tout[3 * rot + 1] = ty;
-        tout[3 * rot + 2] = tz;
+        const FusedRot fr = rots[rot];
+        const FusedJob jb = jobs[fr.job];
+        jb.score[fr.local] = bv;
+        jb.t[3 * fr.local] = tx;
+        jb.t[3 * fr.local + 1] = ty;
+        jb.t[3 * fr.local + 2] = tz;
     }
 }
 
 // per rotation: neighbourhood out, per-axis parabola vertex in FP64
-__global__ void finish_rot_kernel(const double* __restrict__ nbbuf, const int32_t* __restrict__ tout, int n_rot,
-                                  float* __restrict__ nbhd, double* __restrict__ refined) {
+__global__ void finish_rot_kernel(const double* __restrict__ nbbuf, const FusedRot* __restrict__ rots,
+                                  const FusedJob* __restrict__ jobs, int n_rot) {
     const int rot = blockIdx.x * blockDim.x + threadIdx.x;
     if (rot >= n_rot) return;
+    const FusedRot fr = rots[rot];
+    const FusedJob jb = jobs[fr.job];
+    const int loc = fr.local;
     const double* nb = nbbuf + 27 * int64_t(rot);
-    if (nbhd)
-        for (int a = 0; a < 27; ++a) nbhd[27 * int64_t(rot) + a] = float(nb[a]);
-    if (refined) {
+    if (jb.nbhd)
+        for (int a = 0; a < 27; ++a) jb.nbhd[27 * int64_t(loc) + a] = float(nb[a]);
+    if (jb.refined) {
+        const int32_t* tout = jb.t;
+        double* refined = jb.refined;
         const double f0 = nb[13];
         const double fm[3] = {nb[12], nb[10], nb[4]};
         const double fp[3] = {nb[14], nb[16], nb[22]};
@@ -491,7 +650,7 @@ __global__ void finish_rot_kernel(const double* __restrict__ nbbuf, const int32_
                 d = (fm[a] - fp[a]) / (2.0 * den);
                 d = d < -0.5 ? -0.5 : (d > 0.5 ? 0.5 : d);
             }
-            refined[3 * rot + a] = double(tout[3 * rot + a]) + d;
+            refined[3 * loc + a] = double(tout[3 * loc + a]) + d;
         }
     }
 }
@@ -507,101 +666,153 @@ struct TimerScope {
     }
 };
 
-template <int N>
-hipError_t fused_impl(const FusedPlan& fp, const float* R, int n_rot, const void* c, const void* spec, void* ws,
-                      float* score, int32_t* t, float* nbhd, double* refined, hipStream_t s, KernelTimer* kt) {
-    const int nz = fp.planar ? 1 : N;
-    const int64_t G = int64_t(N) * N * nz;
-    const int npair = (n_rot + 1) / 2;
-    char* base = static_cast<char*>(ws);
-    cf* slabs = reinterpret_cast<cf*>(base);
-    size_t off = align256(sizeof(cf) * G * fp.batch);
-    cf* packed = reinterpret_cast<cf*>(base + off);
-    off += align256(sizeof(cf) * G * ((fp.batch + 1) / 2));
-    float* pval = reinterpret_cast<float*>(base + off);
-    off += align256(sizeof(float) * nz * fp.batch);
-    int* pidx = reinterpret_cast<int*>(base + off);
-    off += align256(sizeof(int) * nz * fp.batch);
-    double* nbbuf = reinterpret_cast<double*>(base + off);
-    off += align256(sizeof(double) * 27 * fp.batch);
-    const float* scale = reinterpret_cast<const float*>(base + off + align256(sizeof(float) * kPrepBlocks));
+struct FusedLayout {
+    cf* slabs;
+    cf* packed;
+    float* pval;
+    int* pidx;
+    double* nbbuf;
+    size_t total;
+};
 
-    const cf* cc = static_cast<const cf*>(c);
+FusedLayout fused_layout(const FusedPlan& fp, void* ws) {
+    const int nz = fp.planar ? 1 : fp.N;
+    const int64_t G = int64_t(fp.N) * fp.N * nz;
+    char* base = static_cast<char*>(ws);
+    FusedLayout L{};
+    size_t off = 0;
+    L.slabs = reinterpret_cast<cf*>(base + off);
+    off += align256(sizeof(cf) * G * fp.batch);
+    L.packed = reinterpret_cast<cf*>(base + off);
+    off += align256(sizeof(cf) * G * ((fp.batch + 1) / 2));
+    L.pval = reinterpret_cast<float*>(base + off);
+    off += align256(sizeof(float) * nz * fp.batch);
+    L.pidx = reinterpret_cast<int*>(base + off);
+    off += align256(sizeof(int) * nz * fp.batch);
+    L.nbbuf = reinterpret_cast<double*>(base + off);
+    off += align256(sizeof(double) * 27 * fp.batch);
+    L.total = off;
+    return L;
+}
+
+unsigned persistent_grid(int items, int cap) {
+    if (cap <= 0 || items <= cap) return unsigned(items > 0 ? items : 1);
+    return unsigned(cap);
+}
+
+template <int N, int P>
+hipError_t fused_impl(const FusedPlan& fp, const FusedRot* rots, int n_rot, const FusedJob* jobs, void* ws,
+                      hipStream_t s, KernelTimer* kt) {
+    const int nz = fp.planar ? 1 : N;
+    const int npair = (n_rot + 1) / 2;
+    const FusedLayout L = fused_layout(fp, ws);
     {
         TimerScope ts(kt, "spread_slab", s);
-        hipLaunchKernelGGL(spread_slab_kernel<N>, dim3(nz, n_rot), dim3(kSlabBlock), 0, s, R, cc, fp.n_m,
-                           fp.planar ? 1 : 0, scale, slabs);
+        hipLaunchKernelGGL((spread_slab_kernel<N, P>), dim3(persistent_grid(nz * n_rot, fp.max_wgs)),
+                           dim3(kSlabBlock), 0, s, rots, jobs, n_rot, fp.planar ? 1 : 0, L.slabs);
     }
     const int gr = fp.pencil_group;
-    const dim3 g2{unsigned(pencil_jobs<N>()), unsigned((n_rot + gr - 1) / gr), 1u};
-    const cf* sp = static_cast<const cf*>(spec);
+    const int items2 = pencil_jobs<N>() * ((n_rot + gr - 1) / gr);
+    const dim3 g2{persistent_grid(items2, fp.max_wgs * (gr == 2 ? 2 : 1)), 1u, 1u};
     {
         TimerScope ts(kt, "pencil", s);
         if (fp.planar) {
             if (gr == 4)
-                hipLaunchKernelGGL((pencil_kernel<N, 1, 4>), g2, dim3(kPencilBlock), 0, s, slabs, sp, n_rot, packed);
+                hipLaunchKernelGGL((pencil_kernel<N, 1, 4, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
+                                   L.packed);
             else
-                hipLaunchKernelGGL((pencil_kernel<N, 1, 2>), g2, dim3(kPencilBlock), 0, s, slabs, sp, n_rot, packed);
+                hipLaunchKernelGGL((pencil_kernel<N, 1, 2, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
+                                   L.packed);
         } else {
             if (gr == 4)
-                hipLaunchKernelGGL((pencil_kernel<N, N, 4>), g2, dim3(kPencilBlock), 0, s, slabs, sp, n_rot, packed);
+                hipLaunchKernelGGL((pencil_kernel<N, N, 4, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
+                                   L.packed);
             else
-                hipLaunchKernelGGL((pencil_kernel<N, N, 2>), g2, dim3(kPencilBlock), 0, s, slabs, sp, n_rot, packed);
+                hipLaunchKernelGGL((pencil_kernel<N, N, 2, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
+                                   L.packed);
         }
     }
     {
         TimerScope ts(kt, "islab_peak", s);
-        hipLaunchKernelGGL(islab_peak_kernel<N>, dim3(nz, npair), dim3(kSlabBlock), 0, s, packed, nz, n_rot, pval,
-                           pidx);
+        hipLaunchKernelGGL((islab_peak_kernel<N, P>), dim3(persistent_grid(nz * npair, fp.max_wgs)), dim3(kSlabBlock),
+                           0, s, L.packed, nz, n_rot, L.pval, L.pidx);
     }
     {
         TimerScope ts(kt, "finish", s);
         const dim3 g4{unsigned(fp.planar ? 1 : 3), unsigned(n_rot), 1u};
-        hipLaunchKernelGGL(finish_slab_kernel<N>, g4, dim3(kFinishBlock), 0, s, packed, nz, pval, pidx, nbbuf, score,
-                           t);
-        hipLaunchKernelGGL(finish_rot_kernel, dim3(unsigned((n_rot + 63) / 64)), dim3(64), 0, s, nbbuf, t, n_rot,
-                           nbhd, refined);
+        hipLaunchKernelGGL(finish_slab_kernel<N>, g4, dim3(kFinishBlock), 0, s, L.packed, nz, L.pval, L.pidx, L.nbbuf,
+                           rots, jobs);
+        hipLaunchKernelGGL(finish_rot_kernel, dim3(unsigned((n_rot + 63) / 64)), dim3(64), 0, s, L.nbbuf, rots, jobs,
+                           n_rot);
     }
     return hipGetLastError();
+}
+
+template <int N>
+hipError_t fused_dispatch(const FusedPlan& fp, const FusedRot* rots, int n_rot, const FusedJob* jobs, void* ws,
+                          hipStream_t s, KernelTimer* kt) {
+    switch (fp.radix) {
+        case 0: return fused_impl<N, 0>(fp, rots, n_rot, jobs, ws, s, kt);
+        case 1: return fused_impl<N, 1>(fp, rots, n_rot, jobs, ws, s, kt);
+        case 2: return fused_impl<N, 2>(fp, rots, n_rot, jobs, ws, s, kt);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352dU;
+    x ^= x >> 15;
+    x *= 0x846ca68bU;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void fill_random_kernel(cf* __restrict__ p, int64_t n, uint32_t seed, float amp) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) {
+        const uint32_t a = hash32(uint32_t(i) * 2u + seed * 0x9e3779b9U);
+        const uint32_t b = hash32(uint32_t(i) * 2u + 1u + seed * 0x9e3779b9U);
+        p[i] = mk(amp * (float(a) * 2.3283064e-10f - 0.5f), amp * (float(b) * 2.3283064e-10f - 0.5f));
+    }
 }
 
 }  // namespace
 
-size_t fused_workspace_bytes(const FusedPlan& fp) {
-    const int nz = fp.planar ? 1 : fp.N;
-    const int64_t G = int64_t(fp.N) * fp.N * nz;
-    return align256(sizeof(cf) * G * fp.batch) + align256(sizeof(cf) * G * ((fp.batch + 1) / 2)) +
-           align256(sizeof(float) * nz * fp.batch) + align256(sizeof(int) * nz * fp.batch) +
-           align256(sizeof(double) * 27 * fp.batch) + align256(sizeof(float) * kPrepBlocks) + align256(2 * sizeof(float));
-}
+size_t fused_workspace_bytes(const FusedPlan& fp) { return fused_layout(fp, nullptr).total; }
 
-// Once per call, before the batches: max |c_k| and the fixed-point scale.
-hipError_t launch_fused_prep(const FusedPlan& fp, const void* c, void* ws, hipStream_t s) {
-    const int nz = fp.planar ? 1 : fp.N;
-    const int64_t G = int64_t(fp.N) * fp.N * nz;
-    const int64_t K = int64_t(fp.n_m) * fp.n_m * (fp.planar ? 1 : fp.n_m);
-    size_t off = align256(sizeof(cf) * G * fp.batch) + align256(sizeof(cf) * G * ((fp.batch + 1) / 2)) +
-                 align256(sizeof(float) * nz * fp.batch) + align256(sizeof(int) * nz * fp.batch) +
-                 align256(sizeof(double) * 27 * fp.batch);
-    float* part = reinterpret_cast<float*>(static_cast<char*>(ws) + off);
-    float* scale = reinterpret_cast<float*>(static_cast<char*>(ws) + off + align256(sizeof(float) * kPrepBlocks));
-    hipLaunchKernelGGL(cmax_partial_kernel, dim3(kPrepBlocks), dim3(256), 0, s, static_cast<const cf*>(c), K, part);
-    hipLaunchKernelGGL(cmax_final_kernel, dim3(1), dim3(256), 0, s, part, kPrepBlocks, scale);
+size_t fused_prep_scratch_bytes(int n_jobs) { return align256(sizeof(float) * kPrepBlocks * size_t(n_jobs)); }
+
+hipError_t launch_rot_desc(const RotInput* in, int64_t n, FusedRot* out, hipStream_t s) {
+    hipLaunchKernelGGL(rot_desc_kernel, dim3(unsigned((n + 63) / 64)), dim3(64), 0, s, in, n, out);
     return hipGetLastError();
 }
 
-hipError_t launch_fused_batch(const FusedPlan& fp, const float* R, int n_rot, const void* c, const void* spec,
-                              void* ws, float* score, int32_t* t, float* nbhd, double* refined, hipStream_t s,
-                              KernelTimer* kt) {
+hipError_t launch_fused_prep(const FusedJob* jobs, int n_jobs, void* scratch, hipStream_t s) {
+    float* part = static_cast<float*>(scratch);
+    const dim3 g1{unsigned(kPrepBlocks), unsigned(n_jobs), 1u};
+    hipLaunchKernelGGL(cmax_partial_kernel, g1, dim3(256), 0, s, jobs, part);
+    hipLaunchKernelGGL(cmax_final_kernel, dim3(unsigned(n_jobs)), dim3(64), 0, s, jobs, part, kPrepBlocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_batch(const FusedPlan& fp, const FusedRot* rots, int n_rot, const FusedJob* jobs, void* ws,
+                              hipStream_t s, KernelTimer* kt) {
     switch (fp.N) {
-        case 8: return fused_impl<8>(fp, R, n_rot, c, spec, ws, score, t, nbhd, refined, s, kt);
-        case 16: return fused_impl<16>(fp, R, n_rot, c, spec, ws, score, t, nbhd, refined, s, kt);
-        case 32: return fused_impl<32>(fp, R, n_rot, c, spec, ws, score, t, nbhd, refined, s, kt);
-        case 64: return fused_impl<64>(fp, R, n_rot, c, spec, ws, score, t, nbhd, refined, s, kt);
-        case 96: return fused_impl<96>(fp, R, n_rot, c, spec, ws, score, t, nbhd, refined, s, kt);
-        case 128: return fused_impl<128>(fp, R, n_rot, c, spec, ws, score, t, nbhd, refined, s, kt);
+        case 8: return fused_dispatch<8>(fp, rots, n_rot, jobs, ws, s, kt);
+        case 16: return fused_dispatch<16>(fp, rots, n_rot, jobs, ws, s, kt);
+        case 32: return fused_dispatch<32>(fp, rots, n_rot, jobs, ws, s, kt);
+        case 64: return fused_dispatch<64>(fp, rots, n_rot, jobs, ws, s, kt);
+        case 96: return fused_dispatch<96>(fp, rots, n_rot, jobs, ws, s, kt);
+        case 128: return fused_dispatch<128>(fp, rots, n_rot, jobs, ws, s, kt);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_fill_random(void* data, int64_t count, uint32_t seed, float amp, hipStream_t s) {
+    hipLaunchKernelGGL(fill_random_kernel, dim3(1024), dim3(256), 0, s, static_cast<cf*>(data), count, seed, amp);
+    return hipGetLastError();
 }
 
 }  // namespace sdf

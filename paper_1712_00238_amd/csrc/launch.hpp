@@ -17,9 +17,9 @@ struct ParamDesc {
     double lambda1, lambda2, sigma, eps, xi_floor;
 };
 
-// ---- skeletal density (sdf_build)
+// ---- skeletal density (sdf_build): FP64 samples, output in T
 template <typename T>
-hipError_t launch_sdf_build(const T* q, const T* n, const T* w, int64_t ns, const GridDesc& g,
+hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
                             const ParamDesc& p, void* rho_out, hipStream_t s);
 
 // ---- rotations: quaternions (FP64, device) -> R (FP64 and cast to T), n x 9 row-major
@@ -67,20 +67,51 @@ struct KernelTimer {
 };
 
 // ---- fused FP32 path
+// One pair of a (possibly multi-pair) search, device-resident.
+struct FusedJob {
+    const void* c;       // complex64 coefficients c_k = w_k rho_M(x_k), n_m^3 (n_m^2 planar)
+    const void* spec;    // complex64 fixed spectrum
+    float* scale;        // [fixed-point scale, its inverse], written by the prep kernels
+    float* score;        // per-rotation outputs of this pair
+    int32_t* t;
+    float* nbhd;         // may be null
+    double* refined;     // may be null
+    int n_m;
+    int planar;          // 1: n_m^2 x 1 body box
+};
+// One rotation of the search, device-resident: FP32 matrix, owning pair,
+// index of the rotation within that pair's outputs.
+struct FusedRot {
+    float R[9];
+    int job;
+    int local;
+    int pad;
+};
+// Host-side input of one rotation: FP64 quaternion, pair, local index.
+struct RotInput {
+    double q[4];
+    int job;
+    int local;
+};
 struct FusedPlan {
     int N;
-    int n_m;
     bool planar;
-    int batch;        // rotations per batch (even)
-    int pencil_group; // rotations per pencil job (2 or 4)
+    int batch;         // rotations per batch
+    int pencil_group;  // rotations per pencil block (2 or 4)
+    int radix;         // radix schedule variant (0, 1, 2)
+    int max_wgs;       // persistent grid size cap (0 = one work item per block)
 };
 size_t fused_workspace_bytes(const FusedPlan& fp);
-// once per search call, after the coefficients and before the batches
-hipError_t launch_fused_prep(const FusedPlan& fp, const void* c, void* ws, hipStream_t s);
-// score `n_rot` (<= batch) rotations whose FP32 matrices are R (device, n_rot x 9)
-hipError_t launch_fused_batch(const FusedPlan& fp, const float* R, int n_rot, const void* c, const void* spec,
-                              void* ws, float* score, int32_t* t, float* nbhd, double* refined, hipStream_t s,
-                              KernelTimer* kt = nullptr);
+// quaternions -> FusedRot descriptors (FP64 matrix, cast to FP32)
+hipError_t launch_rot_desc(const RotInput* in, int64_t n, FusedRot* out, hipStream_t s);
+// per pair: max |c_k| and the fixed-point scale (written through jobs[j].scale)
+hipError_t launch_fused_prep(const FusedJob* jobs, int n_jobs, void* scratch, hipStream_t s);
+size_t fused_prep_scratch_bytes(int n_jobs);
+// score rotations rots[0 .. n_rot) (n_rot <= fp.batch) of one grid-size class
+hipError_t launch_fused_batch(const FusedPlan& fp, const FusedRot* rots, int n_rot, const FusedJob* jobs, void* ws,
+                              hipStream_t s, KernelTimer* kt = nullptr);
+// deterministic pseudo-random complex64 fill (autotune inputs)
+hipError_t launch_fill_random(void* data, int64_t count, uint32_t seed, float amp, hipStream_t s);
 
 // ---- top-k
 template <typename T>

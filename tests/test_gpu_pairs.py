@@ -1,0 +1,134 @@
+"""The uneven multi-pair search (score_pairs) and the autotuner, through the
+C ABI, against the FP64 oracle and against the FP64 GPU path."""
+
+import numpy as np
+import pytest
+
+from helpers import flush_print
+from oracle import correlate as oc
+from oracle import peak as op
+from workloads import configs as C
+from workloads import rotations as wr
+
+pytestmark = pytest.mark.gpu
+
+
+def rand_case(n, nm, planar, seed):
+    rng = np.random.default_rng(seed)
+    if planar:
+        gf = C.GridSpec((n, n, 1), (0, 0, 0), 1.0)
+        gm = C.GridSpec((nm, nm, 1), (0, 0, 0), 1.0)
+        sf, sm = (1, n, n), (1, nm, nm)
+    else:
+        gf = C.GridSpec((n, n, n), (0, 0, 0), 1.0)
+        gm = C.GridSpec((nm, nm, nm), (0, 0, 0), 1.0)
+        sf, sm = (n, n, n), (nm, nm, nm)
+    rho_f = rng.normal(size=sf) + 1j * rng.normal(size=sf)
+    rho_m = rng.normal(size=sm) + 1j * rng.normal(size=sm)
+    w = rng.uniform(0.5, 1.5, size=sm)
+    return gf, gm, rho_f, rho_m, w
+
+
+@pytest.fixture(scope="module")
+def ctx32():
+    from paper_1712_00238_amd.api import Context
+    c = Context(0, "f32")
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("batch,group", [(4, 2), (6, 4), (64, 2)])
+def test_score_pairs_mixed_sizes_match_oracle(ctx32, batch, group):
+    ctx = ctx32
+    ctx.set_option("batch", batch)
+    ctx.set_option("pencil_group", group)
+    specs = [(16, 6, False, 5), (32, 14, False, 3), (16, 4, False, 4), (32, 19, True, 7), (8, 2, False, 2),
+             (32, 10, False, 1)]
+    jobs, refs = [], []
+    try:
+        for i, (n, nm, planar, nrot) in enumerate(specs):
+            gf, gm, rho_f, rho_m, w = rand_case(n, nm, planar, 100 + i)
+            quats = wr.planar_rotations(31.0, nrot) if planar else wr.uniform_quaternions(nrot, 200 + i)
+            jobs.append({"spec": ctx.spectrum(rho_f, gf), "g_fixed": gf, "rho_moving": rho_m, "w_moving": w,
+                         "g_moving": gm, "quats": quats})
+            refs.append((rho_f, oc.moving_coefficients(rho_m, w), nm, planar, quats))
+        flush_print("score_pairs", len(jobs), "jobs, batch", batch, "group", group)
+        outs = ctx.score_pairs(jobs)
+        for (rho_f, c, nm, planar, quats), out in zip(refs, outs):
+            s, t, nb = (out[k].cpu().numpy() for k in ("score", "t", "nbhd"))
+            for r, q in enumerate(quats):
+                vol = oc.score_volume(rho_f, c, q, nm, planar)
+                s0, _, t0 = op.peak(vol)
+                scale = np.abs(vol).max()
+                assert abs(s[r] - s0) <= 2e-5 * scale
+                if tuple(t[r]) != t0:
+                    assert abs(vol[t[r][2], t[r][1], t[r][0]] - s0) <= 2e-5 * scale
+                assert np.max(np.abs(nb[r] - op.neighbourhood(vol, tuple(t[r])))) <= 2e-5 * scale
+    finally:
+        ctx.set_option("batch", 64)
+        ctx.set_option("pencil_group", 2)
+
+
+def test_score_pairs_rejects_a_bad_job(ctx32):
+    from paper_1712_00238_amd._lib import SdfError
+    gf, gm, rho_f, rho_m, w = rand_case(16, 6, False, 1)
+    good = {"spec": ctx32.spectrum(rho_f, gf), "g_fixed": gf, "rho_moving": rho_m, "w_moving": w, "g_moving": gm,
+            "quats": wr.uniform_quaternions(2, 1)}
+    bad = dict(good, g_moving=C.GridSpec((12, 12, 12), (0, 0, 0), 1.0))
+    with pytest.raises(SdfError, match="job 1"):
+        ctx32.score_pairs([good, bad])
+
+
+def test_autotune_picks_a_parity_clean_plan(ctx32):
+    gf, gm, rho_f, rho_m, w = rand_case(32, 14, False, 9)
+    flush_print("autotune 32^3 / 14^3")
+    rep = ctx32.autotune(gf, gm)
+    assert rep["N"] == 32 and len(rep["candidates"]) == 18
+    chosen = rep["chosen"]
+    assert any(c["parity"] and c["batch"] == chosen["batch"] and c["group"] == chosen["group"] and
+               c["radix"] == chosen["radix"] for c in rep["candidates"])
+    # every radix schedule passes the parity probe
+    assert all(c["parity"] for c in rep["candidates"])
+    quats = wr.uniform_quaternions(9, 5)
+    out = ctx32.score_rotations(ctx32.spectrum(rho_f, gf), gf, rho_m, w, gm, quats)
+    c = oc.moving_coefficients(rho_m, w)
+    for r, q in enumerate(quats):
+        vol = oc.score_volume(rho_f, c, q, 14, False)
+        assert abs(out["score"].cpu().numpy()[r] - vol.max()) <= 2e-5 * np.abs(vol).max()
+
+
+def test_uneven_batch_fp32_against_fp64_on_sampled_pairs():
+    """Uneven batch of protein-like pairs (grids 64^3 / 96^3 / 128^3 chosen by
+    extent): FP32 fused multi-pair search against the FP64 GPU path, 16
+    sampled pairs x 24 rotations, per-rotation error <= 1e-4 (floored at 1e-3
+    of the pair's largest score) and identical best rotation per pair."""
+    import torch
+    from paper_1712_00238_amd.api import Context
+    idx = list(range(0, 256, 16))
+    c32, c64 = Context(0, "f32"), Context(0, "f64")
+    jobs32, res64 = [], []
+    try:
+        for i in idx:
+            pair = C.uneven_pair(i, n_rot=24)
+            fx, mv = pair.fixed, pair.moving
+            flush_print("uneven pair", i, fx.grid.n[0], mv.grid.n[0], fx.samples.count, mv.samples.count)
+            r32 = [c32.sdf_build(p.samples.q, p.samples.n, p.samples.w, p.grid, pair.params) for p in (fx, mv)]
+            r64 = [c64.sdf_build(p.samples.q, p.samples.n, p.samples.w, p.grid, pair.params) for p in (fx, mv)]
+            w32 = torch.ones(r32[1].shape, dtype=torch.float32, device=r32[1].device)
+            w64 = torch.ones(r64[1].shape, dtype=torch.float64, device=r64[1].device)
+            jobs32.append({"spec": c32.spectrum(r32[0], fx.grid), "g_fixed": fx.grid, "rho_moving": r32[1],
+                           "w_moving": w32, "g_moving": mv.grid, "quats": pair.quats})
+            o64 = c64.score_rotations(c64.spectrum(r64[0], fx.grid), fx.grid, r64[1], w64, mv.grid, pair.quats)
+            res64.append((o64["score"].cpu().numpy(), o64["t"].cpu().numpy()))
+            torch.cuda.synchronize()
+        outs = c32.score_pairs(jobs32)
+        for (s64, t64), o in zip(res64, outs):
+            s32 = o["score"].cpu().numpy().astype(np.float64)
+            den = np.maximum(np.abs(s64), 1e-3 * np.abs(s64).max())
+            rel = np.abs(s32 - s64) / den
+            assert rel.max() <= 1e-4, rel.max()
+            assert int(np.argmax(s32)) == int(np.argmax(s64)) or \
+                abs(s64[int(np.argmax(s32))] - s64.max()) <= 1e-4 * abs(s64.max())
+    finally:
+        c32.close()
+        c64.close()
