@@ -159,3 +159,21 @@ def test_peg_in_hole_golden_fp32_and_fp64():
             out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats)
             s, t = out["score"].cpu().numpy(), out["t"].cpu().numpy()
         check_against_golden(gold, s, t, None, f"peg {dtype}", tol=tol)
+
+
+def test_protein_like_end_to_end_fp32():
+    """Protein-like pair (2000-sphere receptor on 128^3, 500-sphere ligand in a
+    64^3 body box): SDFs from 241k / 57k samples, 64 seeded rotations."""
+    import torch
+    from paper_1712_00238_amd.api import Context
+    gold = load_peaks("protein_like_seed0.txt")
+    pair = C.protein_like(seed=0, n_rot=64)
+    assert np.array_equal(gold["q"], pair.quats)
+    with Context(0, "f32") as ctx:
+        flush_print("protein-like end to end fp32, 64 rotations")
+        rho_f, rho_m = build_fields_gpu(ctx, pair)
+        spec = ctx.spectrum(rho_f, pair.fixed.grid)
+        w = torch.ones(rho_m.shape, dtype=torch.float32, device=rho_m.device)
+        out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats)
+        s, t, ref = (out[k].cpu().numpy() for k in ("score", "t", "refined"))
+    check_against_golden(gold, s, t, ref, "protein fp32")
