@@ -44,7 +44,7 @@ __device__ __forceinline__ T bspline3(T s) {
     if (a < T(1)) return T(2) / T(3) - a * a + T(0.5) * a * a * a;
     if (a < T(2)) {
         T b = T(2) - a;
-        return b * b * b / T(6);
+        return b * b * b * T(1.0 / 6.0);
     }
     return T(0);
 }
@@ -53,10 +53,10 @@ template <typename T>
 __device__ __forceinline__ void bspline3_weights(T f, T w[4]) {
     T g = T(1) - f;
     T f2 = f * f, f3 = f2 * f;
-    w[0] = g * g * g / T(6);                               // beta(1 + f)
+    w[0] = g * g * g * T(1.0 / 6.0);                       // beta(1 + f)
     w[1] = T(2) / T(3) - f2 + T(0.5) * f3;                 // beta(f)
     w[2] = T(2) / T(3) - g * g + T(0.5) * g * g * g;        // beta(1 - f)
-    w[3] = f3 / T(6);                                      // beta(2 - f)
+    w[3] = f3 * T(1.0 / 6.0);                              // beta(2 - f)
 }
 // d/dy of beta(node - y) for the same 4 nodes: -beta'(node - y).
 template <typename T>
@@ -66,6 +66,15 @@ __device__ __forceinline__ void bspline3_dweights(T f, T d[4]) {
     d[1] = -T(2) * f + T(1.5) * f * f;  // node - y = -f
     d[2] = T(2) * g - T(1.5) * g * g;   // node - y = 1 - f
     d[3] = T(0.5) * f * f;              // node - y = 2 - f
+}
+
+// Load through a pointer known to address global memory (one fetched from a
+// descriptor would otherwise become a flat access, which also occupies the
+// LDS counter and so delays waits on LDS operations).
+__device__ __forceinline__ cplx<float> gload(const cplx<float>* p, int64_t i) {
+    using GPtr = const __attribute__((address_space(1))) unsigned long long*;
+    const unsigned long long v = ((GPtr)p)[i];
+    return mk(__uint_as_float(unsigned(v)), __uint_as_float(unsigned(v >> 32)));
 }
 
 __device__ __forceinline__ int wrap(int i, int n) {

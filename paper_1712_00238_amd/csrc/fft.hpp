@@ -85,12 +85,49 @@ __device__ __forceinline__ void dft8(cplx<T>* v) {
     v[3] = e[3] + o3;
     v[7] = e[3] - o3;
 }
+// v * (c + s S i): multiplication by a unit root given by its cosine and
+// the magnitude of its sine
+template <typename T, int S>
+__device__ __forceinline__ cplx<T> rot_by(cplx<T> v, T c, T s) {
+    const T ss = S > 0 ? s : -s;
+    return mk(v.re * c - v.im * ss, v.re * ss + v.im * c);
+}
+// 16 = 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle by w16^(n2 k1), DFT4
+// over n2; output k1 + 4 k2
+template <typename T, int S>
+__device__ __forceinline__ void dft16(cplx<T>* v) {
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173), r = T(0.70710678118654752440);
+    cplx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+        dft4<T, S>(a[n2]);
+    }
+    a[1][1] = rot_by<T, S>(a[1][1], c1, s1);   // w^1
+    a[1][2] = rot_by<T, S>(a[1][2], r, r);     // w^2
+    a[1][3] = rot_by<T, S>(a[1][3], s1, c1);   // w^3
+    a[2][1] = rot_by<T, S>(a[2][1], r, r);     // w^2
+    a[2][2] = mul_i<T, S>(a[2][2]);            // w^4
+    a[2][3] = rot_by<T, S>(a[2][3], -r, r);    // w^6
+    a[3][1] = rot_by<T, S>(a[3][1], s1, c1);   // w^3
+    a[3][2] = rot_by<T, S>(a[3][2], -r, r);    // w^6
+    a[3][3] = rot_by<T, S>(a[3][3], -c1, -s1); // w^9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cplx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4<T, S>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+}
 template <typename T, int S, int R>
 __device__ __forceinline__ void dftR(cplx<T>* v) {
     if constexpr (R == 2) dft2<T, S>(v);
     else if constexpr (R == 3) dft3<T, S>(v);
     else if constexpr (R == 4) dft4<T, S>(v);
     else if constexpr (R == 8) dft8<T, S>(v);
+    else if constexpr (R == 16) dft16<T, S>(v);
 }
 
 // Twiddle table tw[m] = exp(-2 pi i m / N), m < N, filled by the whole block.

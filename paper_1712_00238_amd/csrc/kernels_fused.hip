@@ -156,138 +156,330 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 }
 
 // ------------------------------------------------------------------ K1
+// Slab layouts.  Generic sizes keep the interleaved complex N x N slab and
+// two N x N integer planes over the same bytes, with periodic wrap of the
+// stencil.  N = 64 and 128 use a padded row layout: row y holds the re plane
+// (N ints), the im plane (N ints) and 8 pad ints, so the complex row that
+// replaces it after conversion has N + 4 entries and consecutive rows start
+// 8 banks apart (unpadded rows put every row on the same banks and double the
+// scatter's conflict stalls).  Positions are stored shifted by N / 2 in x and y,
+// which the fitting rule for the rotated body box keeps inside [0, N), so no
+// index wraps and the 16 stencil addresses of a sample are one base plus
+// constant offsets.  The shift multiplies the slab's 2D DFT by (-1)^(kx+ky),
+// removed when the slab is written.
+template <int N>
+struct SlabLayout {
+    static constexpr bool kFast = N == 64 || N == 128;
+    static constexpr int kRowInts = kFast ? 2 * N + 8 : N;   // ints per accumulation row
+    static constexpr int kImOff = kFast ? N : N * N;          // im plane offset (ints)
+    static constexpr int kInts = kFast ? N * kRowInts : 2 * N * N;
+    static constexpr int kRowCf = kRowInts / 2;                // complex stride after conversion (fast)
+    static constexpr int kShift = kFast ? N / 2 : 0;
+};
+
+__device__ __forceinline__ int fixed_rpi(float v) {
+    // round to nearest (halves up) in one instruction
+    int r;
+    asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// Add a 4 x 4 stencil of fixed-point values (re in vr, im in vi, index
+// 4 b + a for node (ix + a, iy + b)) to the slab planes.
+template <int N>
+__device__ __forceinline__ void flush_stencil(int* __restrict__ acc, int ix, int iy, const int vr[16],
+                                              const int vi[16]) {
+    using L = SlabLayout<N>;
+    if constexpr (L::kFast) {
+        const int base = (iy + L::kShift) * L::kRowInts + ix + L::kShift;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                atomicAdd(acc + base + b * L::kRowInts + a, vr[4 * b + a]);
+                atomicAdd(acc + base + b * L::kRowInts + L::kImOff + a, vi[4 * b + a]);
+            }
+        }
+    } else {
+        int col[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) col[a] = wrap(ix + a, N);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = wrap(iy + b, N) * N;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                atomicAdd(acc + row + col[a], vr[4 * b + a]);
+                atomicAdd(acc + L::kImOff + row + col[a], vi[4 * b + a]);
+            }
+        }
+    }
+}
+
+// Spread the samples of one (rotation, z-slab) item into the integer planes.
+template <int N>
+__device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRot& fr, const cf* __restrict__ c,
+                                            int n_m, float S, int z, bool planar) {
+    // reflected rotation: positions y_k = Rp (k - n_m / 2), Rp = -R
+    float Rp[9];
+#pragma unroll
+    for (int a = 0; a < 9; ++a) Rp[a] = -fr.R[a];
+    const float half = 0.5f * float(n_m);
+    if (planar) {
+        const int K = n_m * n_m;
+        for (int k = threadIdx.x; k < K; k += kSlabBlock) {
+            const cf ck = gload(c, k);
+            const float bx = float(k % n_m) - half, by = float(k / n_m) - half;
+            const float yx = Rp[0] * bx + Rp[1] * by;
+            const float yy = Rp[3] * bx + Rp[4] * by;
+            const float fx = floorf(yx), fy = floorf(yy);
+            float wx[4], wy[4], xr[4], xi[4];
+            bspline3_weights(yx - fx, wx);
+            bspline3_weights(yy - fy, wy);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                xr[a] = ck.re * S * wx[a];
+                xi[a] = ck.im * S * wx[a];
+            }
+            int vr[16], vi[16];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    vr[4 * b + a] = fixed_rpi(xr[a] * wy[b]);
+                    vi[4 * b + a] = fixed_rpi(xi[a] * wy[b]);
+                }
+            }
+            flush_stencil<N>(acc, int(fx) - 1, int(fy) - 1, vr, vi);
+        }
+        return;
+    }
+    // Walk body lines along the axis ax most aligned with z: for each
+    // (k_b1, k_b2) the samples y(ka) = y0 + ka d (d = column ax of the
+    // reflected rotation) cross the slab support |z - y_z| < 2 for a short
+    // run of ka; the next coefficient is fetched one step ahead.  A wave
+    // takes an 8 x 8 block of lines (b1 most aligned with x), whose samples
+    // sit at nearby heights and project onto a compact patch of the slab.
+    // Consecutive samples of a line whose stencils share a base are summed
+    // in registers (exact integer sums) and added to LDS once.
+    int ax = 0;
+    float best = fabsf(Rp[6]);
+    if (fabsf(Rp[7]) > best) { ax = 1; best = fabsf(Rp[7]); }
+    if (fabsf(Rp[8]) > best) { ax = 2; }
+    int b1 = ax == 0 ? 1 : 0;
+    int b2 = ax == 2 ? 1 : 2;
+    if (fabsf(Rp[b2]) > fabsf(Rp[b1])) { const int t = b1; b1 = b2; b2 = t; }
+    const float dx = Rp[ax], dy = Rp[3 + ax], dzs = Rp[6 + ax];
+    const float inv_dz = 1.f / dzs;
+    const int kstride[3] = {1, n_m, n_m * n_m};
+    const int sax = kstride[ax];
+    const float zc = float(z < N / 2 ? z : z - N);  // centred image of this slab
+    const int pairs = n_m * n_m;
+    const bool blocks8 = (n_m & 7) == 0;
+    const int nb8 = n_m >> 3;
+    for (int pidx = threadIdx.x; pidx < pairs; pidx += kSlabBlock) {
+        int i1, i2;
+        if (blocks8) {
+            const int w = pidx >> 6, l = pidx & 63;
+            i1 = (w % nb8) * 8 + (l & 7);
+            i2 = (w / nb8) * 8 + (l >> 3);
+        } else {
+            i1 = pidx % n_m;
+            i2 = pidx / n_m;
+        }
+        const float u1 = float(i1) - half, u2 = float(i2) - half, u0 = -half;
+        const float y0x = Rp[b1] * u1 + Rp[b2] * u2 + dx * u0;
+        const float y0y = Rp[3 + b1] * u1 + Rp[3 + b2] * u2 + dy * u0;
+        const float y0z = Rp[6 + b1] * u1 + Rp[6 + b2] * u2 + dzs * u0;
+        float lo_f = (zc - 2.f - y0z) * inv_dz, hi_f = (zc + 2.f - y0z) * inv_dz;
+        if (lo_f > hi_f) { const float t = lo_f; lo_f = hi_f; hi_f = t; }
+        // samples strictly inside (lo_f, hi_f); a 1e-3 margin keeps any
+        // sample that rounding could place inside, and the support test
+        // below decides
+        int lo = int(floorf(lo_f + 0.999f)), hi = int(ceilf(hi_f - 0.999f));
+        lo = lo < 0 ? 0 : lo;
+        hi = hi > n_m - 1 ? n_m - 1 : hi;
+        if (lo > hi) continue;
+        const int k0 = i1 * kstride[b1] + i2 * kstride[b2];
+        cf cnext = gload(c, k0 + lo * sax);
+        int vr[16], vi[16];
+        int cx = 0, cy = 0;
+        bool open = false;
+        for (int ka = lo; ka <= hi; ++ka) {
+            const cf ck = cnext;
+            if (ka < hi) cnext = gload(c, k0 + (ka + 1) * sax);
+            const float fk = float(ka);
+            const float yz = y0z + fk * dzs;
+            const float ad = fabsf(zc - yz);
+            if (!(ad < 2.f)) continue;
+            const float yx = y0x + fk * dx;
+            const float yy = y0y + fk * dy;
+            float wz;
+            if (ad < 1.f) wz = 2.f / 3.f - ad * ad + 0.5f * ad * ad * ad;
+            else { const float b = 2.f - ad; wz = b * b * b * (1.f / 6.f); }
+            const float sw = wz * S;
+            const float fx = floorf(yx), fy = floorf(yy);
+            float wx[4], wy[4], xr[4], xi[4];
+            bspline3_weights(yx - fx, wx);
+            bspline3_weights(yy - fy, wy);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                xr[a] = ck.re * sw * wx[a];
+                xi[a] = ck.im * sw * wx[a];
+            }
+            const int ix = int(fx) - 1, iy = int(fy) - 1;
+            if (!open || ix != cx || iy != cy) {
+                if (open) flush_stencil<N>(acc, cx, cy, vr, vi);
+                open = true;
+                cx = ix;
+                cy = iy;
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    vr[q] = 0;
+                    vi[q] = 0;
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    vr[4 * b + a] += fixed_rpi(xr[a] * wy[b]);
+                    vi[4 * b + a] += fixed_rpi(xi[a] * wy[b]);
+                }
+            }
+        }
+        if (open) flush_stencil<N>(acc, cx, cy, vr, vi);
+    }
+}
+
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// Forward 2D DFT of the padded slab (N = 8 R1, R1 = 8 or 16) and its store.
+// Along x, 8 consecutive lanes own one row for both passes (radix R1, then
+// radix 8 with twiddles), so the x transform needs no block barrier: one
+// wave's LDS operations complete in issue order.  The first pass reads the
+// integer planes and converts.  Along y, pass C (radix R1) is split by a
+// barrier between its reads and writes; pass D (radix 8) reads, writes the
+// result to global memory with the (-1)^(kx+ky) shift correction, and
+// clears the LDS words it read for the next item.
+template <int N>
+__device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const cf* __restrict__ tw, float inv,
+                                                    cf* __restrict__ out) {
+    using L = SlabLayout<N>;
+    constexpr int R1 = N / 8;
+    constexpr int NB = N / 8;   // radix-8 butterflies per line
+    constexpr int RS = L::kRowCf;
+    cf* slab = reinterpret_cast<cf*>(acc);
+    // opaque copy of the thread index: keeps the compiler from hoisting this
+    // phase's ~60 address registers out of the item loop, where they would
+    // stay live through the scatter and spill
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    {
+        const int y = t / 8, j = t % 8;
+        if (y < N) {
+            cf v[R1];
+#pragma unroll
+            for (int r = 0; r < R1; ++r) {
+                const int x = j + 8 * r;
+                v[r] = mk(float(acc[y * L::kRowInts + x]) * inv, float(acc[y * L::kRowInts + L::kImOff + x]) * inv);
+            }
+            compiler_fence();
+            dftR<float, -1, R1>(v);
+#pragma unroll
+            for (int r = 0; r < R1; ++r) slab[y * RS + j * R1 + r] = v[r];
+            compiler_fence();
+#pragma unroll
+            for (int m = 0; m < NB / 8; ++m) {
+                const int jj = j + 8 * m;  // k = jj
+                cf u[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + jj + NB * r];
+#pragma unroll
+                for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
+                dft8<float, -1>(u);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) slab[y * RS + jj + NB * r] = u[r];
+            }
+        }
+    }
+    __syncthreads();
+    const int x = t % N, jb = t / N;
+    const bool on = jb < 8;
+    {
+        cf v[R1];
+        if (on) {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[r] = slab[(jb + 8 * r) * RS + x];
+            dftR<float, -1, R1>(v);
+        }
+        __syncthreads();
+        if (on) {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + x] = v[r];
+        }
+        __syncthreads();
+    }
+    if (on) {
+#pragma unroll
+        for (int m = 0; m < NB / 8; ++m) {
+            const int jj = jb + 8 * m;
+            cf u[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + x];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
+            dft8<float, -1>(u);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int ky = jj + NB * r;
+                const float sg = ((x + ky) & 1) ? -1.f : 1.f;
+                out[ky * N + x] = u[r] * sg;
+                slab[ky * RS + x] = mk(0.f, 0.f);
+            }
+        }
+    }
+}
+
 // Work item = (z-slab, rotation), z fastest.
 template <int N, int P>
 __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot* __restrict__ rots,
                                                                  const FusedJob* __restrict__ jobs, int n_rot,
                                                                  int planar, cf* __restrict__ slabs) {
+    using L = SlabLayout<N>;
     using Plan = typename FusedRadix<N, P>::type;
-    __shared__ cf slab[N * N];
+    __shared__ int acc[L::kInts];
     __shared__ cf tw[N];
-    const int nz = planar ? 1 : N;
     fill_twiddles<float, N>(tw);
-    int* acc = reinterpret_cast<int*>(slab);  // re plane [0, N^2), im plane [N^2, 2 N^2)
+    const int nz = planar ? 1 : N;
     const int items = nz * n_rot;
+    if constexpr (L::kFast) {
+        for (int i = threadIdx.x; i < L::kInts; i += kSlabBlock) acc[i] = 0;  // later items clear as they store
+    }
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        const int z = item % nz;
+        // The scatter work of a slab follows the body's cross-section at its
+        // height, largest near z = 0.  With the grid a multiple of nz a
+        // block would see the same z for every rotation; offsetting z by
+        // 53 (odd) per rotation gives every block a spread of heights.
         const int rot = item / nz;
+        const int z = (item % nz + 53 * (rot % nz)) % nz;
         const FusedRot fr = rots[rot];
         const FusedJob jb = jobs[fr.job];
-        const cf* __restrict__ c = static_cast<const cf*>(jb.c);
-        const int n_m = jb.n_m;
-        __syncthreads();  // previous item's slab fully stored
-        for (int i = threadIdx.x; i < 2 * N * N; i += kSlabBlock) acc[i] = 0;
-        const float S = jb.scale[0];
-        __syncthreads();
-        // reflected rotation: positions y_k = Rp (k - n_m / 2), Rp = -R
-        float Rp[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) Rp[a] = -fr.R[a];
-        const float half = 0.5f * float(n_m);
-        if (planar) {
-            const int K = n_m * n_m;
-            for (int k = threadIdx.x; k < K; k += kSlabBlock) {
-                const cf ck = c[k];
-                const float cre = ck.re * S, cim = ck.im * S;
-                const float bx = float(k % n_m) - half, by = float(k / n_m) - half;
-                const float yx = Rp[0] * bx + Rp[1] * by;
-                const float yy = Rp[3] * bx + Rp[4] * by;
-                const float fx = floorf(yx), fy = floorf(yy);
-                float wx[4], wy[4];
-                bspline3_weights(yx - fx, wx);
-                bspline3_weights(yy - fy, wy);
-                const int ix = int(fx) - 1, iy = int(fy) - 1;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int row = wrap(iy + b, N) * N;
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        const float wt = wx[a] * wy[b];
-                        const int idx = row + wrap(ix + a, N);
-                        atomicAdd(acc + idx, __float2int_rn(cre * wt));
-                        atomicAdd(acc + N * N + idx, __float2int_rn(cim * wt));
-                    }
-                }
-            }
-        } else {
-            // Walk body lines along the axis ax most aligned with z: for each
-            // (k_b1, k_b2) the samples y(ka) = y0 + ka d (d = column ax of the
-            // reflected rotation) cross the slab support |z - y_z| < 2 for a
-            // short run of ka; positions and indices advance by constant
-            // steps and the next coefficient is fetched one step ahead.
-            int ax = 0;
-            float best = fabsf(Rp[6]);
-            if (fabsf(Rp[7]) > best) { ax = 1; best = fabsf(Rp[7]); }
-            if (fabsf(Rp[8]) > best) { ax = 2; }
-            // consecutive lanes step along the remaining axis most aligned
-            // with x, so their stencils land in consecutive LDS banks
-            int b1 = ax == 0 ? 1 : 0;
-            int b2 = ax == 2 ? 1 : 2;
-            if (fabsf(Rp[b2]) > fabsf(Rp[b1])) { const int t = b1; b1 = b2; b2 = t; }
-            const float dx = Rp[ax], dy = Rp[3 + ax], dzs = Rp[6 + ax];
-            const float inv_dz = 1.f / dzs;
-            const int kstride[3] = {1, n_m, n_m * n_m};
-            const int sax = kstride[ax];
-            const float zc = float(z < N / 2 ? z : z - N);  // centred image of this slab
-            const int pairs = n_m * n_m;
-            for (int pidx = threadIdx.x; pidx < pairs; pidx += kSlabBlock) {
-                const int i1 = pidx % n_m, i2 = pidx / n_m;
-                const float u1 = float(i1) - half, u2 = float(i2) - half, u0 = -half;
-                const float y0x = Rp[b1] * u1 + Rp[b2] * u2 + dx * u0;
-                const float y0y = Rp[3 + b1] * u1 + Rp[3 + b2] * u2 + dy * u0;
-                const float y0z = Rp[6 + b1] * u1 + Rp[6 + b2] * u2 + dzs * u0;
-                float lo_f = (zc - 2.f - y0z) * inv_dz, hi_f = (zc + 2.f - y0z) * inv_dz;
-                if (lo_f > hi_f) { const float t = lo_f; lo_f = hi_f; hi_f = t; }
-                int lo = int(floorf(lo_f)), hi = int(ceilf(hi_f));
-                lo = lo < 0 ? 0 : lo;
-                hi = hi > n_m - 1 ? n_m - 1 : hi;
-                if (lo > hi) continue;
-                const int k0 = i1 * kstride[b1] + i2 * kstride[b2];
-                cf cnext = c[k0 + lo * sax];
-                for (int ka = lo; ka <= hi; ++ka) {
-                    const cf ck = cnext;
-                    if (ka < hi) cnext = c[k0 + (ka + 1) * sax];
-                    const float fk = float(ka);
-                    const float yz = y0z + fk * dzs;
-                    const float ad = fabsf(zc - yz);
-                    if (!(ad < 2.f)) continue;
-                    const float yx = y0x + fk * dx;
-                    const float yy = y0y + fk * dy;
-                    float wz;
-                    if (ad < 1.f) wz = 2.f / 3.f - ad * ad + 0.5f * ad * ad * ad;
-                    else { const float b = 2.f - ad; wz = b * b * b / 6.f; }
-                    const float sw = wz * S;
-                    const float fx = floorf(yx), fy = floorf(yy);
-                    float wx[4], wy[4];
-                    bspline3_weights(yx - fx, wx);
-                    bspline3_weights(yy - fy, wy);
-                    const int ix = int(fx) - 1, iy = int(fy) - 1;
-                    float xr[4], xi[4];
-                    int col[4];
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        xr[a] = ck.re * sw * wx[a];
-                        xi[a] = ck.im * sw * wx[a];
-                        col[a] = wrap(ix + a, N);
-                    }
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int row = wrap(iy + b, N) * N;
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            const int idx = row + col[a];
-                            atomicAdd(acc + idx, __float2int_rn(xr[a] * wy[b]));
-                            atomicAdd(acc + N * N + idx, __float2int_rn(xi[a] * wy[b]));
-                        }
-                    }
-                }
-            }
+        __syncthreads();  // previous item done with the slab
+        if constexpr (!L::kFast) {
+            for (int i = threadIdx.x; i < L::kInts; i += kSlabBlock) acc[i] = 0;
+            __syncthreads();
         }
+        spread_item<N>(acc, fr, static_cast<const cf*>(jb.c), jb.n_m, jb.scale[0], z, planar != 0);
         __syncthreads();
-        {
+        cf* out = slabs + (int64_t(rot) * nz + z) * N * N;
+        const float inv = jb.scale[1];
+        if constexpr (L::kFast) {
+            slab_fft_store_fast<N>(acc, tw, inv, out);
+        } else {
             // planes -> interleaved complex, in place: read everything, then write
+            cf* slab = reinterpret_cast<cf*>(acc);
             constexpr int PER = (N * N + kSlabBlock - 1) / kSlabBlock;
-            const float inv = jb.scale[1];
             cf v[PER];
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
@@ -300,12 +492,11 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
                 const int i = threadIdx.x + p * kSlabBlock;
                 if ((N * N) % kSlabBlock == 0 || i < N * N) slab[i] = v[p];
             }
+            __syncthreads();
+            lds_fft_lines<float, N, -1, false, Plan>(slab, 1, N, N, tw);  // along x
+            lds_fft_lines<float, N, -1, true, Plan>(slab, N, 1, N, tw);   // along y
+            for (int i = threadIdx.x; i < N * N; i += kSlabBlock) out[i] = slab[i];
         }
-        __syncthreads();
-        lds_fft_lines<float, N, -1, false, Plan>(slab, 1, N, N, tw);  // along x
-        lds_fft_lines<float, N, -1, true, Plan>(slab, N, 1, N, tw);   // along y
-        cf* out = slabs + (int64_t(rot) * nz + z) * N * N;
-        for (int i = threadIdx.x; i < N * N; i += kSlabBlock) out[i] = slab[i];
     }
 }
 
