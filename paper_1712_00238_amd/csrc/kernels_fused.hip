@@ -522,6 +522,121 @@ constexpr int pencil_jobs() {
     return (N / 2 - 1) * (N / W) + 2 * ((N / 2 + 1 + W - 1) / W);
 }
 
+// Fast pencil pass for NZ = N = 8 R1 (R1 = 8 or 16).  LDS holds the NL
+// lines of the item at row stride NL + 8 (element kz of line l at
+// kz (NL + 8) + l).
+//  A  forward radix-R1 pass along z, read straight from global memory;
+//  B  forward radix-8 pass in place, times the fixed spectrum;
+//  F  Hermitian folding in place: the unit (pair, column, kz) reads the k
+//     lines a0, b0 at kz and the -k lines a1, b1 at -kz and writes Z to a0
+//     at kz and a1 at -kz, positions no other unit touches;
+//  I  inverse radix-R1 and radix-8 passes over the Z lines, 8 lines per
+//     wave (no block barrier between them), the last pass writing global
+//     memory.
+template <int N, int GR>
+__device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict__ slabs, cf* __restrict__ packed,
+                                                 cf* __restrict__ buf, const cf* __restrict__ tw,
+                                                 const cf* const* spec_of, const PencilJob job, int g0) {
+    constexpr int W = pencil_width<N>();
+    constexpr int NL = 2 * W * GR;
+    constexpr int NLP = NL + 8;
+    constexpr int R1 = N / 8;
+    constexpr int NB = N / 8;
+    constexpr int64_t G = int64_t(N) * N * N;
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int kyt[2] = {job.ky, (N - job.ky) % N};
+    auto kx_of = [&](int tt, int cc) { return tt == 0 ? job.x0 + cc : (N - job.x0 - cc) % N; };
+    // line l = ((r & 1) GR + (r >> 1) 2 + tile) W + cc
+    auto line_rot = [](int l) {
+        const int q = l / W;
+        return 2 * ((q % GR) / 2) + q / GR;
+    };
+    // ---- A
+    for (int b = t; b < NL * 8; b += kPencilBlock) {
+        const int l = b % NL, j = b / NL;
+        const int cc = l % W, tt = (l / W) % 2;
+        const int rot = g0 + line_rot(l);
+        cf v[R1];
+        if (rot < n_rot) {
+            const cf* src = slabs + int64_t(rot) * G + int64_t(kyt[tt]) * N + kx_of(tt, cc);
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[r] = src[int64_t(j + 8 * r) * N * N];
+            dftR<float, -1, R1>(v);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) v[r] = mk(0.f, 0.f);
+        }
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buf[(j * R1 + r) * NLP + l] = v[r];
+    }
+    __syncthreads();
+    // ---- B
+    for (int b = t; b < NL * NB; b += kPencilBlock) {
+        const int l = b % NL, jj = b / NL;
+        const int cc = l % W, tt = (l / W) % 2;
+        const cf* sp = spec_of[line_rot(l)];
+        cf u[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) u[r] = buf[(jj + NB * r) * NLP + l];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
+        dft8<float, -1>(u);
+        const int64_t col = int64_t(kyt[tt]) * N + kx_of(tt, cc);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const cf sv = sp ? gload(sp, int64_t(jj + NB * r) * N * N + col) : mk(0.f, 0.f);
+            buf[(jj + NB * r) * NLP + l] = u[r] * sv;
+        }
+    }
+    __syncthreads();
+    // ---- F
+    for (int u = t; u < (GR / 2) * W * N; u += kPencilBlock) {
+        const int cc = u % W, kz = (u / W) % N, p = u / (W * N);
+        const int mkz = (N - kz) % N;
+        const int a0 = (2 * p) * W + cc, a1 = (2 * p + 1) * W + cc;
+        const int b0 = (GR + 2 * p) * W + cc, b1 = (GR + 2 * p + 1) * W + cc;
+        const cf ya0 = buf[kz * NLP + a0], ya1 = buf[mkz * NLP + a1];
+        const cf yb0 = buf[kz * NLP + b0], yb1 = buf[mkz * NLP + b1];
+        const cf ha = (ya0 + conj(ya1)) * 0.5f;
+        const cf hb = (yb0 + conj(yb1)) * 0.5f;
+        buf[kz * NLP + a0] = mk(ha.re - hb.im, ha.im + hb.re);
+        buf[mkz * NLP + a1] = mk(ha.re + hb.im, hb.re - ha.im);
+    }
+    __syncthreads();
+    // ---- I: Z lines are lines [0, GR W); wave w takes lines 8 w .. 8 w + 7
+    for (int wv = t >> 6; wv < GR * W / 8; wv += kPencilBlock / 64) {
+        const int lane = t & 63;
+        const int l = wv * 8 + (lane & 7), j = lane >> 3;
+        cf v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = buf[(j + 8 * r) * NLP + l];
+        compiler_fence();
+        dftR<float, 1, R1>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buf[(j * R1 + r) * NLP + l] = v[r];
+        compiler_fence();
+        const int cc = l % W, q = l / W, p = q / 2, tt = q % 2;
+        const int pair = g0 / 2 + p;
+        const bool store = pair < (n_rot + 1) / 2;
+        cf* dst = packed + int64_t(pair) * G + int64_t(kyt[tt]) * N + kx_of(tt, cc);
+#pragma unroll
+        for (int m = 0; m < NB / 8; ++m) {
+            const int jj = j + 8 * m;
+            cf uu[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) uu[r] = buf[(jj + NB * r) * NLP + l];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) uu[r] = uu[r] * conj(tw[r * jj]);
+            dft8<float, 1>(uu);
+            if (store) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) dst[int64_t(jj + NB * r) * N * N] = uu[r];
+            }
+        }
+    }
+}
+
 // Work item = (pencil tile pair, group of GR rotations).  NZ = N (3D) or 1 (planar).
 template <int N, int NZ, int GR, int P>
 __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __restrict__ rots,
@@ -531,7 +646,8 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
     using Plan = typename FusedRadix<(NZ > 1 ? NZ : 8), P>::type;
     constexpr int W = pencil_width<N>();
     constexpr int NL = 2 * W * GR;  // lines: (rotation, tile, column)
-    __shared__ cf buf[NZ * NL];
+    constexpr bool kFast = NZ == N && SlabLayout<N>::kFast;
+    __shared__ cf buf[kFast ? NZ * (NL + 8) : NZ * NL];
     __shared__ cf tw[NZ > 1 ? NZ : 1];
     __shared__ const cf* spec_of[GR];
     const int64_t G = int64_t(N) * N * NZ;
@@ -549,6 +665,11 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
         if (threadIdx.x < GR) {
             const int rot = g0 + threadIdx.x;
             spec_of[threadIdx.x] = rot < n_rot ? static_cast<const cf*>(jobs[rots[rot].job].spec) : nullptr;
+        }
+        if constexpr (kFast) {
+            __syncthreads();
+            pencil_item_fast<N, GR>(n_rot, slabs, packed, buf, tw, spec_of, job, g0);
+            continue;
         }
         // load both tiles of every rotation of the group (zeros for missing
         // rotations); all loads of a thread are issued before its LDS writes
@@ -650,12 +771,89 @@ __device__ __forceinline__ void wave_argmax(float& v, int& i) {
     }
 }
 
+__device__ __forceinline__ void take(float v, int i, float& bv, int& bi) {
+    if (better(v, i, bv, bi)) {
+        bv = v;
+        bi = i;
+    }
+}
+
+// Inverse 2D DFT of one folded slab (N = 8 R1, R1 = 8 or 16) with the
+// per-thread argmax of its real (rotation A) and imaginary (rotation B)
+// parts.  Pass A (radix R1 along y) reads global memory directly; pass B
+// (radix 8) runs in place; along x, 8 lanes own a row for both passes, and
+// the outputs of the last pass go straight to the argmax.
+template <int N>
+__device__ __forceinline__ void islab_fft_argmax_fast(const cf* __restrict__ src, cf* __restrict__ slab,
+                                                      const cf* __restrict__ tw, int zoff, float& va, int& ia,
+                                                      float& vb, int& ib) {
+    constexpr int R1 = N / 8;
+    constexpr int NB = N / 8;
+    constexpr int RS = N + 4;  // padded row stride (complex entries)
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    const int x = t % N, jb = t / N;
+    const bool on = jb < 8;
+    if (on) {
+        cf v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = src[(jb + 8 * r) * N + x];
+        dftR<float, 1, R1>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + x] = v[r];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+        for (int m = 0; m < NB / 8; ++m) {
+            const int jj = jb + 8 * m;
+            cf u[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + x];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) u[r] = u[r] * conj(tw[r * jj]);
+            dft8<float, 1>(u);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) slab[(jj + NB * r) * RS + x] = u[r];
+        }
+    }
+    __syncthreads();
+    const int y = t / 8, j = t % 8;
+    if (y < N) {
+        cf v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = slab[y * RS + j + 8 * r];
+        compiler_fence();
+        dftR<float, 1, R1>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) slab[y * RS + j * R1 + r] = v[r];
+        compiler_fence();
+#pragma unroll
+        for (int m = 0; m < NB / 8; ++m) {
+            const int jj = j + 8 * m;
+            cf u[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + jj + NB * r];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) u[r] = u[r] * conj(tw[r * jj]);
+            dft8<float, 1>(u);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                const int idx = zoff + y * N + jj + NB * r;
+                take(u[r].re, idx, va, ia);
+                take(u[r].im, idx, vb, ib);
+            }
+        }
+    }
+}
+
 // Work item = (z-slab, rotation pair), z fastest.
 template <int N, int P>
 __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __restrict__ packed, int nz, int n_rot,
                                                                 float* __restrict__ pval, int* __restrict__ pidx) {
     using Plan = typename FusedRadix<N, P>::type;
-    __shared__ cf slab[N * N];
+    constexpr bool kFast = SlabLayout<N>::kFast;
+    __shared__ cf slab[kFast ? N * (N + 4) : N * N];
     __shared__ cf tw[N];
     __shared__ float rv[2][kSlabBlock / 64];
     __shared__ int ri[2][kSlabBlock / 64];
@@ -665,18 +863,22 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int z = item % nz, pair = item / nz;
         const cf* src = packed + (int64_t(pair) * nz + z) * N * N;
-        __syncthreads();
-        stage_to_lds<N * N / 2, kSlabBlock>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
-        __syncthreads();
-        lds_fft_lines<float, N, 1, true, Plan>(slab, N, 1, N, tw);   // along y
-        lds_fft_lines<float, N, 1, false, Plan>(slab, 1, N, N, tw);  // along x
         float va = -INFINITY, vb = -INFINITY;
         int ia = 0x7fffffff, ib = 0x7fffffff;
         const int zoff = z * N * N;
-        for (int i = threadIdx.x; i < N * N; i += kSlabBlock) {
-            const cf v = slab[i];
-            if (better(v.re, zoff + i, va, ia)) { va = v.re; ia = zoff + i; }
-            if (better(v.im, zoff + i, vb, ib)) { vb = v.im; ib = zoff + i; }
+        __syncthreads();
+        if constexpr (kFast) {
+            islab_fft_argmax_fast<N>(src, slab, tw, zoff, va, ia, vb, ib);
+        } else {
+            stage_to_lds<N * N / 2, kSlabBlock>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
+            __syncthreads();
+            lds_fft_lines<float, N, 1, true, Plan>(slab, N, 1, N, tw);   // along y
+            lds_fft_lines<float, N, 1, false, Plan>(slab, 1, N, N, tw);  // along x
+            for (int i = threadIdx.x; i < N * N; i += kSlabBlock) {
+                const cf v = slab[i];
+                take(v.re, zoff + i, va, ia);
+                take(v.im, zoff + i, vb, ib);
+            }
         }
         wave_argmax(va, ia);
         wave_argmax(vb, ib);
