@@ -91,7 +91,11 @@ def algorithmic_bytes(kernel: str, nb: int, N: int, n_m: int, planar: bool) -> f
     raise KeyError(kernel)
 
 
-def load_traffic(kernel: str, sha: str):
+def load_traffic(kernel: str, sha: str, rotations: int):
+    """HBM bytes of one launch of `kernel` over `rotations` rotations, from the
+    counter summary under profiles/ (FETCH_SIZE + WRITE_SIZE per rotation,
+    calibrated against a plain copy); None when the kernel sources changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -100,7 +104,7 @@ def load_traffic(kernel: str, sha: str):
     k = rec.get("kernels", {}).get(kernel)
     if not k or rec.get("source_sha") != sha:
         return None
-    return k.get("hbm_bytes_per_launch")
+    return k["hbm_bytes_per_rotation"] * rotations
 
 
 def cpu_baseline(pair, n_rot: int):
@@ -221,7 +225,7 @@ def main():
             v["achieved_GBs"] = v["algorithmic_bytes_per_launch"] / (v["avg_us"] * 1e-6) / 1e9
         dom = max(kernels, key=lambda k: kernels[k]["share"])
         sha = sources_sha()
-        traffic = load_traffic(dom, sha)
+        traffic = load_traffic(dom, sha, nb_full)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(kernels[dom]["achieved_GBs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(kernels[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),

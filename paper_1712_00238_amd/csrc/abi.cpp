@@ -388,8 +388,10 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
         plans.push_back(plan_for(ctx, int(classes[ci] / 2), (classes[ci] & 1) != 0, class_rots[ci]));
         batch_bytes = std::max(batch_bytes, sdf::fused_workspace_bytes(plans.back()));
     }
-    auto carve = [&](char* base, std::vector<void*>* cptr, std::vector<float*>* sptr, sdf::FusedJob** jobs_d,
-                     sdf::FusedRot** rots_d, sdf::RotInput** rin_d, void** prep, void** fused) {
+    auto grouped = [&](int j) { return sdf::fused_pair_grouped(pairs[j].gf->n[0], pairs[j].gf->n[2] == 1); };
+    auto carve = [&](char* base, std::vector<void*>* cptr, std::vector<float*>* sptr, std::vector<void*>* xptr,
+                     sdf::FusedJob** jobs_d, sdf::FusedRot** rots_d, sdf::RotInput** rin_d, void** prep,
+                     void** fused) {
         Carve cv{base};
         *jobs_d = static_cast<sdf::FusedJob*>(cv.take(sizeof(sdf::FusedJob) * nj));
         *rots_d = static_cast<sdf::FusedRot*>(cv.take(sizeof(sdf::FusedRot) * total_rot));
@@ -398,8 +400,10 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
         for (int j = 0; j < nj; ++j) {
             void* c = cv.take(sizeof(float) * 2 * size_t(gsize(pairs[j].gm)));
             float* sc = static_cast<float*>(cv.take(2 * sizeof(float)));
+            void* x = grouped(j) ? cv.take(sizeof(float) * 2 * size_t(gsize(pairs[j].gf))) : nullptr;
             if (cptr) (*cptr)[j] = c;
             if (sptr) (*sptr)[j] = sc;
+            if (xptr) (*xptr)[j] = x;
         }
         *fused = cv.take(batch_bytes);
         return cv.off;
@@ -408,19 +412,19 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
     sdf::FusedRot* rots_d;
     sdf::RotInput* rin_d;
     void *prep, *fused;
-    const size_t need = carve(nullptr, nullptr, nullptr, &jobs_d, &rots_d, &rin_d, &prep, &fused);
+    const size_t need = carve(nullptr, nullptr, nullptr, nullptr, &jobs_d, &rots_d, &rin_d, &prep, &fused);
     int rc = ensure_ws(ctx, need);
     if (rc) return rc;
-    std::vector<void*> cptr(nj);
+    std::vector<void*> cptr(nj), xptr(nj);
     std::vector<float*> sptr(nj);
-    carve(static_cast<char*>(ctx->ws), &cptr, &sptr, &jobs_d, &rots_d, &rin_d, &prep, &fused);
+    carve(static_cast<char*>(ctx->ws), &cptr, &sptr, &xptr, &jobs_d, &rots_d, &rin_d, &prep, &fused);
     // host tables (pinned staging is unnecessary: these are a few KB and copied synchronously)
     std::vector<sdf::FusedJob> jobs_h(nj);
     std::vector<sdf::RotInput> rin_h;
     rin_h.reserve(size_t(total_rot));
     for (int jj : order) {
         const PairIn& p = pairs[jj];
-        jobs_h[jj] = sdf::FusedJob{cptr[jj], p.spec, sptr[jj], static_cast<float*>(p.score), p.t,
+        jobs_h[jj] = sdf::FusedJob{cptr[jj], xptr[jj] ? xptr[jj] : p.spec, sptr[jj], static_cast<float*>(p.score), p.t,
                                    static_cast<float*>(p.nbhd), p.refined, p.gm->n[0], p.gf->n[2] == 1 ? 1 : 0};
         for (int64_t r = 0; r < p.n_rot; ++r) {
             sdf::RotInput ri;
@@ -457,6 +461,10 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
                     sdf::launch_coef<float>(pairs[j].rho_m, static_cast<const float*>(pairs[j].w_m),
                                             gsize(pairs[j].gm), cptr[j], s),
                     "coefficients");
+    for (int j = 0; j < nj; ++j)
+        if (xptr[j])
+            SDF_TRY_HIP(ctx, sdf::launch_spec_pair_group(pairs[j].spec, xptr[j], pairs[j].gf->n[0], s),
+                        "spectrum column order");
     SDF_TRY_HIP(ctx, sdf::launch_fused_prep(jobs_d, nj, prep, s), "fixed-point scale");
 
     sdf::KernelTimer* kt = ctx->opt_profile ? &ctx->prof : nullptr;

@@ -177,6 +177,27 @@ struct SlabLayout {
     static constexpr int kShift = kFast ? N / 2 : 0;
 };
 
+// Pair-grouped column order (3D grids, N = 64 and 128).  Position p = 16 b + i
+// holds kx = 8 b + i for i < 8 and kx = -(8 b + i - 8) mod N for i >= 8,
+// except p = 8, which holds N / 2.  Every column's negative then sits in the
+// same aligned block of 16 (at p ^ 8, or at p itself for kx = 0 and N / 2),
+// so a pencil tile of row ky and its partner tile of row -ky cover the same
+// aligned 128-byte segments.
+template <int N>
+__host__ __device__ __forceinline__ int col_pos(int kx) {
+    if (kx == N / 2) return 8;
+    if (kx < N / 2) return 16 * (kx >> 3) + (kx & 7);
+    const int m = N - kx;
+    return 16 * (m >> 3) + 8 + (m & 7);
+}
+template <int N>
+__host__ __device__ __forceinline__ int col_kx(int p) {
+    const int b = p >> 4, i = p & 15;
+    if (i < 8) return 8 * b + i;
+    if (p == 8) return N / 2;
+    return N - (8 * b + i - 8);
+}
+
 __device__ __forceinline__ int fixed_rpi(float v) {
     // round to nearest (halves up) in one instruction
     int r;
@@ -364,7 +385,7 @@ __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory")
 // clears the LDS words it read for the next item.
 template <int N>
 __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const cf* __restrict__ tw, float inv,
-                                                    cf* __restrict__ out) {
+                                                    cf* __restrict__ out, bool grouped) {
     using L = SlabLayout<N>;
     constexpr int R1 = N / 8;
     constexpr int NB = N / 8;   // radix-8 butterflies per line
@@ -434,7 +455,7 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
             for (int r = 0; r < 8; ++r) {
                 const int ky = jj + NB * r;
                 const float sg = ((x + ky) & 1) ? -1.f : 1.f;
-                out[ky * N + x] = u[r] * sg;
+                out[ky * N + (grouped ? col_pos<N>(x) : x)] = u[r] * sg;
                 slab[ky * RS + x] = mk(0.f, 0.f);
             }
         }
@@ -475,7 +496,7 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
         cf* out = slabs + (int64_t(rot) * nz + z) * N * N;
         const float inv = jb.scale[1];
         if constexpr (L::kFast) {
-            slab_fft_store_fast<N>(acc, tw, inv, out);
+            slab_fft_store_fast<N>(acc, tw, inv, out, planar == 0);
         } else {
             // planes -> interleaved complex, in place: read everything, then write
             cf* slab = reinterpret_cast<cf*>(acc);
@@ -522,6 +543,17 @@ constexpr int pencil_jobs() {
     return (N / 2 - 1) * (N / W) + 2 * ((N / 2 + 1 + W - 1) / W);
 }
 
+// pair-grouped layout: rows ky = 0 .. N/2 (each with its partner row -ky),
+// every aligned 16-position block
+template <int N>
+constexpr int pencil_jobs_grouped() {
+    return (N / 2 + 1) * (N / 16);
+}
+template <int N>
+__device__ __forceinline__ PencilJob pencil_job_grouped(int j) {
+    return PencilJob{j / (N / 16), (j % (N / 16)) * 16};
+}
+
 // Fast pencil pass for NZ = N = 8 R1 (R1 = 8 or 16).  LDS holds the NL
 // lines of the item at row stride NL + 8 (element kz of line l at
 // kz (NL + 8) + l).
@@ -546,7 +578,10 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     const int kyt[2] = {job.ky, (N - job.ky) % N};
-    auto kx_of = [&](int tt, int cc) { return tt == 0 ? job.x0 + cc : (N - job.x0 - cc) % N; };
+    // both tiles cover positions x0 .. x0 + 15 of the pair-grouped order; the
+    // partner of position x0 + cc is x0 + (cc ^ 8), or itself for kx = 0, N/2
+    auto kx_of = [&](int, int cc) { return job.x0 + cc; };
+    auto partner = [&](int cc) { return (job.x0 == 0 && (cc & 7) == 0) ? cc : (cc ^ 8); };
     // line l = ((r & 1) GR + (r >> 1) 2 + tile) W + cc
     auto line_rot = [](int l) {
         const int q = l / W;
@@ -594,8 +629,9 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
     for (int u = t; u < (GR / 2) * W * N; u += kPencilBlock) {
         const int cc = u % W, kz = (u / W) % N, p = u / (W * N);
         const int mkz = (N - kz) % N;
-        const int a0 = (2 * p) * W + cc, a1 = (2 * p + 1) * W + cc;
-        const int b0 = (GR + 2 * p) * W + cc, b1 = (GR + 2 * p + 1) * W + cc;
+        const int pc = partner(cc);
+        const int a0 = (2 * p) * W + cc, a1 = (2 * p + 1) * W + pc;
+        const int b0 = (GR + 2 * p) * W + cc, b1 = (GR + 2 * p + 1) * W + pc;
         const cf ya0 = buf[kz * NLP + a0], ya1 = buf[mkz * NLP + a1];
         const cf yb0 = buf[kz * NLP + b0], yb1 = buf[mkz * NLP + b1];
         const cf ha = (ya0 + conj(ya1)) * 0.5f;
@@ -654,11 +690,12 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
     if constexpr (NZ > 1) fill_twiddles<float, NZ>(tw);
     auto line_of = [](int r, int t, int cc) { return ((r & 1) * GR + (r >> 1) * 2 + t) * W + cc; };
     const int ngroups = (n_rot + GR - 1) / GR;
-    const int items = pencil_jobs<N>() * ngroups;
+    const int items = (kFast ? pencil_jobs_grouped<N>() : pencil_jobs<N>()) * ngroups;
     const int npair = (n_rot + 1) / 2;
+    constexpr int njobs = kFast ? pencil_jobs_grouped<N>() : pencil_jobs<N>();
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        const PencilJob job = pencil_job<N>(item % pencil_jobs<N>());
-        const int g0 = (item / pencil_jobs<N>()) * GR;  // first rotation of the group
+        const PencilJob job = kFast ? pencil_job_grouped<N>(item % njobs) : pencil_job<N>(item % njobs);
+        const int g0 = (item / njobs) * GR;  // first rotation of the group
         const int kyt[2] = {job.ky, (N - job.ky) % N};
         auto kx_of = [&](int t, int cc) { return t == 0 ? job.x0 + cc : (N - job.x0 - cc) % N; };
         __syncthreads();  // previous item done with buf / spec_of
@@ -786,7 +823,7 @@ __device__ __forceinline__ void take(float v, int i, float& bv, int& bi) {
 template <int N>
 __device__ __forceinline__ void islab_fft_argmax_fast(const cf* __restrict__ src, cf* __restrict__ slab,
                                                       const cf* __restrict__ tw, int zoff, float& va, int& ia,
-                                                      float& vb, int& ib) {
+                                                      float& vb, int& ib, bool grouped) {
     constexpr int R1 = N / 8;
     constexpr int NB = N / 8;
     constexpr int RS = N + 4;  // padded row stride (complex entries)
@@ -797,7 +834,7 @@ __device__ __forceinline__ void islab_fft_argmax_fast(const cf* __restrict__ src
     if (on) {
         cf v[R1];
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = src[(jb + 8 * r) * N + x];
+        for (int r = 0; r < R1; ++r) v[r] = src[(jb + 8 * r) * N + (grouped ? col_pos<N>(x) : x)];
         dftR<float, 1, R1>(v);
 #pragma unroll
         for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + x] = v[r];
@@ -868,7 +905,7 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
         const int zoff = z * N * N;
         __syncthreads();
         if constexpr (kFast) {
-            islab_fft_argmax_fast<N>(src, slab, tw, zoff, va, ia, vb, ib);
+            islab_fft_argmax_fast<N>(src, slab, tw, zoff, va, ia, vb, ib, nz == N);
         } else {
             stage_to_lds<N * N / 2, kSlabBlock>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
             __syncthreads();
@@ -956,12 +993,15 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
     const bool imag = rot & 1;
     const int xs[3] = {(tx + N - 1) % N, tx, (tx + 1) % N};
     const int ys[3] = {(ty + N - 1) % N, ty, (ty + 1) % N};
-    // inner sums along x: two threads per row ky, each half of the row
+    // inner sums along x: two threads per row ky, each half of the row's
+    // stored positions
+    const bool grouped = nz == N && (N == 64 || N == 128);
     for (int w = threadIdx.x; w < 2 * N; w += kFinishBlock) {
         const int ky = w >> 1, half = w & 1;
         double ar[3] = {0, 0, 0}, ai[3] = {0, 0, 0};
-        for (int kx = half * (N / 2); kx < (half + 1) * (N / 2); ++kx) {
-            const cf v = sl[ky * N + kx];
+        for (int px = half * (N / 2); px < (half + 1) * (N / 2); ++px) {
+            const cf v = sl[ky * N + px];
+            const int kx = grouped ? col_kx<N>(px) : px;
             const double vr = v.re, vi = v.im;
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
@@ -1105,7 +1145,8 @@ hipError_t fused_impl(const FusedPlan& fp, const FusedRot* rots, int n_rot, cons
                            dim3(kSlabBlock), 0, s, rots, jobs, n_rot, fp.planar ? 1 : 0, L.slabs);
     }
     const int gr = fp.pencil_group;
-    const int items2 = pencil_jobs<N>() * ((n_rot + gr - 1) / gr);
+    const int items2 = (fused_pair_grouped(N, fp.planar) ? pencil_jobs_grouped<N>() : pencil_jobs<N>()) *
+                       ((n_rot + gr - 1) / gr);
     const dim3 g2{persistent_grid(items2, fp.max_wgs * (gr == 2 ? 2 : 1)), 1u, 1u};
     {
         TimerScope ts(kt, "pencil", s);
@@ -1176,6 +1217,27 @@ __global__ void fill_random_kernel(cf* __restrict__ p, int64_t n, uint32_t seed,
 size_t fused_workspace_bytes(const FusedPlan& fp) { return fused_layout(fp, nullptr).total; }
 
 size_t fused_prep_scratch_bytes(int n_jobs) { return align256(sizeof(float) * kPrepBlocks * size_t(n_jobs)); }
+
+template <int N>
+__global__ void spec_pair_group_kernel(const cf* __restrict__ in, cf* __restrict__ out) {
+    const int64_t rows = int64_t(N) * N;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < rows * N; i += int64_t(gridDim.x) * blockDim.x) {
+        const int p = int(i % N);
+        out[i] = in[i - p + col_kx<N>(p)];
+    }
+}
+
+hipError_t launch_spec_pair_group(const void* spec, void* out, int N, hipStream_t s) {
+    const cf* in = static_cast<const cf*>(spec);
+    cf* o = static_cast<cf*>(out);
+    if (N == 128)
+        hipLaunchKernelGGL(spec_pair_group_kernel<128>, dim3(2048), dim3(256), 0, s, in, o);
+    else if (N == 64)
+        hipLaunchKernelGGL(spec_pair_group_kernel<64>, dim3(1024), dim3(256), 0, s, in, o);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
 
 hipError_t launch_rot_desc(const RotInput* in, int64_t n, FusedRot* out, hipStream_t s) {
     hipLaunchKernelGGL(rot_desc_kernel, dim3(unsigned((n + 63) / 64)), dim3(64), 0, s, in, n, out);
