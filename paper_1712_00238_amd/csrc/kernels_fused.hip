@@ -587,6 +587,24 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
         const int q = l / W;
         return 2 * ((q % GR) / 2) + q / GR;
     };
+    // spectrum values of this thread's pass-B units, requested before the
+    // pass-A loads so both round trips to memory overlap (GR = 2: two units
+    // of 8 values per thread)
+    constexpr int PB = (NL * NB + kPencilBlock - 1) / kPencilBlock;
+    constexpr bool kPre = GR == 2 && PB * kPencilBlock == NL * NB;
+    cf spre[kPre ? PB : 1][8];
+    auto spec_at = [&](int b, int r) {
+        const int l = b % NL, jj = b / NL;
+        const int cc = l % W, tt = (l / W) % 2;
+        const cf* sp = spec_of[line_rot(l)];
+        return sp ? gload(sp, int64_t(jj + NB * r) * N * N + int64_t(kyt[tt]) * N + kx_of(tt, cc)) : mk(0.f, 0.f);
+    };
+    if constexpr (kPre) {
+#pragma unroll
+        for (int m = 0; m < PB; ++m)
+#pragma unroll
+            for (int r = 0; r < 8; ++r) spre[m][r] = spec_at(t + m * kPencilBlock, r);
+    }
     // ---- A
     for (int b = t; b < NL * 8; b += kPencilBlock) {
         const int l = b % NL, j = b / NL;
@@ -607,20 +625,20 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
     }
     __syncthreads();
     // ---- B
-    for (int b = t; b < NL * NB; b += kPencilBlock) {
+#pragma unroll
+    for (int m = 0; m < PB; ++m) {
+        const int b = t + m * kPencilBlock;
+        if (!kPre && b >= NL * NB) break;
         const int l = b % NL, jj = b / NL;
-        const int cc = l % W, tt = (l / W) % 2;
-        const cf* sp = spec_of[line_rot(l)];
         cf u[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) u[r] = buf[(jj + NB * r) * NLP + l];
 #pragma unroll
         for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
         dft8<float, -1>(u);
-        const int64_t col = int64_t(kyt[tt]) * N + kx_of(tt, cc);
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const cf sv = sp ? gload(sp, int64_t(jj + NB * r) * N * N + col) : mk(0.f, 0.f);
+            const cf sv = kPre ? spre[kPre ? m : 0][r] : spec_at(b, r);
             buf[(jj + NB * r) * NLP + l] = u[r] * sv;
         }
     }
@@ -817,11 +835,14 @@ __device__ __forceinline__ void take(float v, int i, float& bv, int& bi) {
 
 // Inverse 2D DFT of one folded slab (N = 8 R1, R1 = 8 or 16) with the
 // per-thread argmax of its real (rotation A) and imaginary (rotation B)
-// parts.  Pass A (radix R1 along y) reads global memory directly; pass B
-// (radix 8) runs in place; along x, 8 lanes own a row for both passes, and
-// the outputs of the last pass go straight to the argmax.
+// parts.  Pass A (radix R1 along y) takes its inputs from registers loaded
+// from global memory one item ahead; pass B (radix 8) runs in place; along x,
+// 8 lanes own a row for both passes, and the outputs of the last pass go
+// straight to the argmax.  `pre` holds this item's pass-A inputs on entry
+// and the next item's (loaded from `next`, if not null) on return: the loads
+// are in flight during the x passes.
 template <int N>
-__device__ __forceinline__ void islab_fft_argmax_fast(const cf* __restrict__ src, cf* __restrict__ slab,
+__device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restrict__ next, cf* __restrict__ slab,
                                                       const cf* __restrict__ tw, int zoff, float& va, int& ia,
                                                       float& vb, int& ib, bool grouped) {
     constexpr int R1 = N / 8;
@@ -832,12 +853,9 @@ __device__ __forceinline__ void islab_fft_argmax_fast(const cf* __restrict__ src
     const int x = t % N, jb = t / N;
     const bool on = jb < 8;
     if (on) {
-        cf v[R1];
+        dftR<float, 1, R1>(pre);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = src[(jb + 8 * r) * N + (grouped ? col_pos<N>(x) : x)];
-        dftR<float, 1, R1>(v);
-#pragma unroll
-        for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + x] = v[r];
+        for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + x] = pre[r];
     }
     __syncthreads();
     if (on) {
@@ -852,6 +870,11 @@ __device__ __forceinline__ void islab_fft_argmax_fast(const cf* __restrict__ src
             dft8<float, 1>(u);
 #pragma unroll
             for (int r = 0; r < 8; ++r) slab[(jj + NB * r) * RS + x] = u[r];
+        }
+        if (next) {
+            const int px = grouped ? col_pos<N>(x) : x;
+#pragma unroll
+            for (int r = 0; r < R1; ++r) pre[r] = next[(jb + 8 * r) * N + px];
         }
     }
     __syncthreads();
@@ -897,15 +920,29 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
     fill_twiddles<float, N>(tw);
     const int npair = (n_rot + 1) / 2;
     const int items = nz * npair;
+    const bool grouped = nz == N;
+    auto src_of = [&](int item) { return packed + (int64_t(item / nz) * nz + item % nz) * N * N; };
+    cf pre[kFast ? N / 8 : 1];
+    if constexpr (kFast) {
+        const int x = threadIdx.x % N, jb = threadIdx.x / N;
+        if (blockIdx.x < items && jb < 8) {
+            const cf* src = src_of(blockIdx.x);
+            const int px = grouped ? col_pos<N>(x) : x;
+#pragma unroll
+            for (int r = 0; r < N / 8; ++r) pre[r] = src[(jb + 8 * r) * N + px];
+        }
+    }
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         const int z = item % nz, pair = item / nz;
-        const cf* src = packed + (int64_t(pair) * nz + z) * N * N;
+        const cf* src = src_of(item);
         float va = -INFINITY, vb = -INFINITY;
         int ia = 0x7fffffff, ib = 0x7fffffff;
         const int zoff = z * N * N;
         __syncthreads();
         if constexpr (kFast) {
-            islab_fft_argmax_fast<N>(src, slab, tw, zoff, va, ia, vb, ib, nz == N);
+            const int nx = item + int(gridDim.x);
+            islab_fft_argmax_fast<N>(pre, nx < items ? src_of(nx) : nullptr, slab, tw, zoff, va, ia, vb, ib,
+                                     grouped);
         } else {
             stage_to_lds<N * N / 2, kSlabBlock>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
             __syncthreads();
