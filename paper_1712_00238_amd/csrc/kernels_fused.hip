@@ -278,11 +278,11 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
     // Walk body lines along the axis ax most aligned with z: for each
     // (k_b1, k_b2) the samples y(ka) = y0 + ka d (d = column ax of the
     // reflected rotation) cross the slab support |z - y_z| < 2 for a short
-    // run of ka; the next coefficient is fetched one step ahead.  A wave
-    // takes an 8 x 8 block of lines (b1 most aligned with x), whose samples
-    // sit at nearby heights and project onto a compact patch of the slab.
-    // Consecutive samples of a line whose stencils share a base are summed
-    // in registers (exact integer sums) and added to LDS once.
+    // run of ka; the next coefficient is fetched one step ahead.  Lines are
+    // taken in 16 x 16 blocks by four waves, each wave a stride-2 8 x 8
+    // sublattice (b1 most aligned with x): its samples sit at nearby heights,
+    // and the stride keeps two lanes from adding to the same LDS word in one
+    // instruction, which the LDS would serialise.
     int ax = 0;
     float best = fabsf(Rp[6]);
     if (fabsf(Rp[7]) > best) { ax = 1; best = fabsf(Rp[7]); }
@@ -296,14 +296,15 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
     const int sax = kstride[ax];
     const float zc = float(z < N / 2 ? z : z - N);  // centred image of this slab
     const int pairs = n_m * n_m;
-    const bool blocks8 = (n_m & 7) == 0;
-    const int nb8 = n_m >> 3;
+    const bool blocks16 = (n_m & 15) == 0;
+    const int nb16 = n_m >> 4;
     for (int pidx = threadIdx.x; pidx < pairs; pidx += kSlabBlock) {
         int i1, i2;
-        if (blocks8) {
+        if (blocks16) {
             const int w = pidx >> 6, l = pidx & 63;
-            i1 = (w % nb8) * 8 + (l & 7);
-            i2 = (w / nb8) * 8 + (l >> 3);
+            const int blk = w >> 2, k = w & 3;
+            i1 = (blk % nb16) * 16 + 2 * (l & 7) + (k & 1);
+            i2 = (blk / nb16) * 16 + 2 * (l >> 3) + (k >> 1);
         } else {
             i1 = pidx % n_m;
             i2 = pidx / n_m;
@@ -323,9 +324,6 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
         if (lo > hi) continue;
         const int k0 = i1 * kstride[b1] + i2 * kstride[b2];
         cf cnext = gload(c, k0 + lo * sax);
-        int vr[16], vi[16];
-        int cx = 0, cy = 0;
-        bool open = false;
         for (int ka = lo; ka <= hi; ++ka) {
             const cf ck = cnext;
             if (ka < hi) cnext = gload(c, k0 + (ka + 1) * sax);
@@ -348,28 +346,17 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
                 xr[a] = ck.re * sw * wx[a];
                 xi[a] = ck.im * sw * wx[a];
             }
-            const int ix = int(fx) - 1, iy = int(fy) - 1;
-            if (!open || ix != cx || iy != cy) {
-                if (open) flush_stencil<N>(acc, cx, cy, vr, vi);
-                open = true;
-                cx = ix;
-                cy = iy;
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    vr[q] = 0;
-                    vi[q] = 0;
-                }
-            }
+            int vr[16], vi[16];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    vr[4 * b + a] += fixed_rpi(xr[a] * wy[b]);
-                    vi[4 * b + a] += fixed_rpi(xi[a] * wy[b]);
+                    vr[4 * b + a] = fixed_rpi(xr[a] * wy[b]);
+                    vi[4 * b + a] = fixed_rpi(xi[a] * wy[b]);
                 }
             }
+            flush_stencil<N>(acc, int(fx) - 1, int(fy) - 1, vr, vi);
         }
-        if (open) flush_stencil<N>(acc, cx, cy, vr, vi);
     }
 }
 
