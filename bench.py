@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--grad-poses", type=int, default=1024)
     ap.add_argument("--grad-steps", type=int, default=5)
     ap.add_argument("--cpu-rotations", type=int, default=12, help="rotations of the oracle timed on the host")
+    ap.add_argument("--protein-rotations", type=int, default=3600,
+                    help="rotations of the protein-like pair scored 64 per launch (0: skip)")
+    ap.add_argument("--uneven-pairs", type=int, default=48,
+                    help="pairs in the multi-pair queue figure, 512 rotations each (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: launch one device copy of known size (counter calibration)")
@@ -283,6 +287,59 @@ def main():
         torch.cuda.synchronize()
         report["pose_grad_evals_per_s"] = B * args.grad_steps / (time.perf_counter() - t0)
         ctx64.close()
+
+        # --- protein-like pair: SDFs from 241k / 57k samples, rotations 64 per launch (graph replay)
+        if args.protein_rotations:
+            pp = C.protein_like(seed=0, n_rot=args.protein_rotations)
+            pf, pm = pp.fixed, pp.moving
+            rf = ctx.sdf_build(pf.samples.q, pf.samples.n, pf.samples.w, pf.grid, pp.params)
+            rm = ctx.sdf_build(pm.samples.q, pm.samples.n, pm.samples.w, pm.grid, pp.params)
+            psp = ctx.spectrum(rf, pf.grid)
+            pw = torch.ones(rm.shape, dtype=torch.float32, device=dev)
+            ctx.set_option("batch", 64)
+            pout = ctx.score_rotations(psp, pf.grid, rm, pw, pm.grid, pp.quats)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                pout = ctx.score_rotations(psp, pf.grid, rm, pw, pm.grid, pp.quats, out=pout)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 3
+            report["protein_like"] = {"rotations": len(pp.quats), "batch": 64, "graph": bool(args.graph),
+                                      "rotations_per_s": round(len(pp.quats) / dt, 1),
+                                      "samples": [pf.samples.count, pm.samples.count]}
+            ctx.set_option("batch", args.batch)
+            del rf, rm, psp, pw, pout
+
+        # --- uneven multi-pair queue: pairs cycle through the three grid classes
+        # the uneven batch picks by extent (128^3 / 64^3, 96^3 / 48^3, 64^3 / 32^3);
+        # seeded random fields, since the work does not depend on the values
+        if args.uneven_pairs:
+            from workloads import rotations as wrot
+            classes = [(128, 64), (96, 48), (64, 32)]
+            gen = torch.Generator(device=dev).manual_seed(11)
+            jobs = []
+            for i in range(args.uneven_pairs):
+                n, nm = classes[i % 3]
+                gfix = C.GridSpec((n, n, n), (0.0, 0.0, 0.0), 1.0)
+                gmov = C.body_grid(nm, (0.0, 0.0, 0.0), 1.0)
+                jobs.append({"spec": torch.randn((n, n, n), dtype=torch.complex64, device=dev, generator=gen) * 1e-3,
+                             "g_fixed": gfix,
+                             "rho_moving": torch.randn((nm, nm, nm), dtype=torch.complex64, device=dev, generator=gen),
+                             "w_moving": torch.ones((nm, nm, nm), dtype=torch.float32, device=dev),
+                             "g_moving": gmov, "quats": wrot.uniform_quaternions(512, 5000 + i)})
+            ctx.set_option("autotune", 1)
+            ctx.score_pairs(jobs)  # tunes the two smaller classes, captures the graph
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(2):
+                ctx.score_pairs(jobs)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / 2
+            total = 512 * len(jobs)
+            report["uneven_batch"] = {"pairs": len(jobs), "rotations": total,
+                                      "rotations_per_s": round(total / dt, 1),
+                                      "classes": ["128^3/64^3", "96^3/48^3", "64^3/32^3"]}
+            del jobs
         ctx.close()
 
     line = {"metric": "rotations scored/sec at 128^3 (FP32 fused path); FP64 path and pose-gradient evals/sec "
@@ -303,6 +360,8 @@ def main():
             "sdf_build_fixed_ms": round(report["sdf_build_fixed_ms"], 3),
             "sdf_build_fixed_pairs_per_s": report["sdf_build_fixed_pairs_per_s"],
             "spectrum_ms": round(report["spectrum_ms"], 4),
+            "protein_like": report.get("protein_like"),
+            "uneven_batch": report.get("uneven_batch"),
             "kernels": report["kernels"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pair, args.cpu_rotations)
