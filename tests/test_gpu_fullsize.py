@@ -177,3 +177,36 @@ def test_protein_like_end_to_end_fp32():
         out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats)
         s, t, ref = (out[k].cpu().numpy() for k in ("score", "t", "refined"))
     check_against_golden(gold, s, t, ref, "protein fp32")
+
+
+def test_protein_like_pose_gradients_fp32():
+    """Refinement gradients on the protein-like pair: 32 poses perturbed from
+    the top oracle peaks.  The FP32 adjoint kernel (FP64 pose accumulation),
+    on GPU-built SDFs, against the oracle's analytic gradient (1e-4 of the
+    pose's largest component) and against the oracle's central differences
+    with h = 1e-3 (1e-3 of the largest component, plus the difference's own
+    truncation error, which the oracle's analytic gradient measures)."""
+    import torch
+    from paper_1712_00238_amd.api import Context
+    path = os.path.join(GOLDEN, "protein_like_grad_seed0.txt")
+    if not os.path.exists(path):
+        pytest.skip("protein_like_grad_seed0.txt not generated")
+    a = np.loadtxt(path)
+    poses, f_ref, g_ref, g_fd = a[:, 0:7], a[:, 7], a[:, 8:15], a[:, 15:22]
+    pair = C.protein_like(seed=0, n_rot=64)
+    with Context(0, "f32") as ctx:
+        flush_print("protein-like pose gradients fp32, 32 poses")
+        rho_f, rho_m = build_fields_gpu(ctx, pair)
+        w = torch.ones(rho_m.shape, dtype=torch.float32, device=rho_m.device)
+        score, gp, _ = ctx.score_grad(rho_f, pair.fixed.grid, rho_m, w, pair.moving.grid, poses)
+        score, gp = score.cpu().numpy().astype(np.float64), gp.cpu().numpy()
+    scale = np.abs(g_ref).max(axis=1)
+    e_val = np.abs(score - f_ref) / np.abs(f_ref)
+    e_ref = (np.abs(gp - g_ref).max(axis=1)) / scale
+    e_fd = (np.abs(gp - g_fd).max(axis=1)) / scale
+    e_fd_oracle = (np.abs(g_ref - g_fd).max(axis=1)) / scale
+    flush_print("value rel err", e_val.max(), "grad vs oracle", e_ref.max(), "grad vs FD", e_fd.max(),
+                "oracle vs FD", e_fd_oracle.max())
+    assert e_val.max() <= 1e-4
+    assert e_ref.max() <= 1e-4
+    assert np.all(e_fd <= 1e-3 + e_fd_oracle)
