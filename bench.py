@@ -92,6 +92,8 @@ def algorithmic_bytes(kernel: str, nb: int, N: int, n_m: int, planar: bool) -> f
         return pairs * 8.0 * G
     if kernel == "finish":
         return nb * 3 * 8.0 * N * N
+    if kernel == "finish_rot":
+        return nb * (27 * 8.0 + 27 * 4.0 + 3 * 8.0)
     raise KeyError(kernel)
 
 
@@ -216,20 +218,23 @@ def main():
             ctx.score_rotations(spec, fx.grid, rho_m, w, mv.grid, pair.quats, out=out)
         torch.cuda.synchronize()
         kernels = {}
-        for k in ("spread_slab", "pencil", "islab_peak", "finish"):
+        for k in ("spread_slab", "pencil", "islab_peak", "finish", "finish_rot"):
             ms, launches = ctx.kernel_stats(k)
             kernels[k] = {"avg_us": 1e3 * ms / max(launches, 1), "launches": launches,
                           "share": 0.0}
         ctx.set_option("profile", 0)
         tot = sum(v["avg_us"] * v["launches"] for v in kernels.values())
-        nb_full = min(args.batch, n_rot)
+        # one call launches batches of `batch` rotations and a smaller tail batch
+        # (576 = 4 x 128 + 64): bytes and durations are both averaged over that mix
+        sizes = [min(args.batch, n_rot - i) for i in range(0, n_rot, args.batch)]
+        rot_per_launch = n_rot / len(sizes)
         for k, v in kernels.items():
             v["share"] = v["avg_us"] * v["launches"] / tot
-            v["algorithmic_bytes_per_launch"] = algorithmic_bytes(k, nb_full, N, n_m, False)
+            v["algorithmic_bytes_per_launch"] = sum(algorithmic_bytes(k, nb, N, n_m, False) for nb in sizes) / len(sizes)
             v["achieved_GBs"] = v["algorithmic_bytes_per_launch"] / (v["avg_us"] * 1e-6) / 1e9
         dom = max(kernels, key=lambda k: kernels[k]["share"])
         sha = sources_sha()
-        traffic = load_traffic(dom, sha, nb_full)
+        traffic = load_traffic(dom, sha, rot_per_launch)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(kernels[dom]["achieved_GBs"], 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(kernels[dom]["achieved_GBs"] / HBM_PEAK_GBS, 4),
@@ -237,7 +242,7 @@ def main():
                     "algorithmic_bytes_per_launch": kernels[dom]["algorithmic_bytes_per_launch"],
                     "source_sha": sha}
         # whole correlation stage (all four kernels of a batch) against HBM
-        stage_bytes = sum(algorithmic_bytes(k, nb_full, N, n_m, False) for k in kernels)
+        stage_bytes = sum(v["algorithmic_bytes_per_launch"] for v in kernels.values())
         stage_us = sum(v["avg_us"] for v in kernels.values())
         report["stage_GBs"] = stage_bytes / (stage_us * 1e-6) / 1e9
         report["kernels"] = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}

@@ -107,7 +107,7 @@ const char *sdf_last_error(sdf_ctx ctx);
  *   "batch"         rotations per fused launch sequence (even, 2..256; default 64)
  *   "graph"         1: capture each batch's launch sequence in a hipGraph and replay it
  *   "pencil_group"  rotations sharing one spectrum tile in the fused pencil pass (2 or 4)
- *   "profile"       1: time every fused kernel with HIP events (see sdf_ctx_stats)
+ *   "profile"       1: time every fused kernel (see sdf_ctx_stats)
  *   "radix"         FFT radix schedule of the fused kernels (0, 1, 2; e.g. 128 = 8.4.4, 4.4.8, 2.8.8)
  *   "autotune"      1: tune each grid-size class on its first search (see sdf_autotune)
  * With "graph" = 1 the fused launch sequence of a score_rotations call is
@@ -120,10 +120,11 @@ int sdf_ctx_set_option(sdf_ctx ctx, const char *key, int64_t value);
 int sdf_ctx_get_option(sdf_ctx ctx, const char *key, int64_t *value);
 
 /* Kernel timing.  With the option "profile" = 1 every kernel of the fused
- * search is bracketed by HIP events on the caller's stream (graphs are not
- * used meanwhile).  sdf_ctx_stats synchronises on the recorded events and
- * returns the accumulated time and launch count of one kernel
- * ("spread_slab", "pencil", "islab_peak", "finish"; unknown names give 0).
+ * search is launched with a start / stop HIP event pair that its own
+ * dispatch records (the kernel's execution interval; graphs are not used
+ * meanwhile).  sdf_ctx_stats synchronises on the recorded events and returns
+ * the accumulated time and launch count of one kernel ("spread_slab",
+ * "pencil", "islab_peak", "finish", "finish_rot"; unknown names give 0).
  * sdf_ctx_stats_reset clears the totals. */
 int sdf_ctx_stats(sdf_ctx ctx, const char *kernel, double *total_ms, int64_t *launches);
 int sdf_ctx_stats_reset(sdf_ctx ctx);

@@ -36,7 +36,6 @@ struct Profiler : sdf::KernelTimer {
     std::vector<hipEvent_t> pool;
     std::vector<Rec> pending;
     std::map<std::string, std::pair<double, int64_t>> totals;
-    Rec cur;
     bool ok = true;
 
     hipEvent_t get() {
@@ -49,15 +48,11 @@ struct Profiler : sdf::KernelTimer {
         if (hipEventCreate(&e) != hipSuccess) ok = false;
         return e;
     }
-    void begin(const char* name, hipStream_t s) override {
-        cur.name = name;
-        cur.a = get();
-        cur.b = get();
-        if (cur.a) (void)hipEventRecord(cur.a, s);
-    }
-    void end(hipStream_t s) override {
-        if (cur.b) (void)hipEventRecord(cur.b, s);
-        pending.push_back(cur);
+    void events(const char* name, hipEvent_t* start, hipEvent_t* stop) override {
+        Rec r{name, get(), get()};
+        *start = r.a;
+        *stop = r.b;
+        pending.push_back(r);
     }
     void collect() {
         for (Rec& r : pending) {

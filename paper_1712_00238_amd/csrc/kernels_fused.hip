@@ -39,6 +39,8 @@
 // convolution of rho_F with the reflected spread Mr(u) = M_R(-u), i.e. the
 // spread of the samples at -R x_k / h.  So fft(f) = S(k) * fft(Mr)(k) with
 // S = N^-3 fft(rho_F), and the unnormalised inverse FFT gives f directly.
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "fft.hpp"
 #include "launch.hpp"
@@ -1112,16 +1114,17 @@ __global__ void finish_rot_kernel(const double* __restrict__ nbbuf, const FusedR
     }
 }
 
-struct TimerScope {
-    KernelTimer* kt;
-    hipStream_t s;
-    TimerScope(KernelTimer* k, const char* name, hipStream_t st) : kt(k), s(st) {
-        if (kt) kt->begin(name, s);
+// launch, recording the kernel's own start / stop timestamps when timed
+template <typename F, typename... Args>
+void launch_k(KernelTimer* kt, const char* name, F kernel, dim3 grid, dim3 block, hipStream_t s, Args... args) {
+    if (kt) {
+        hipEvent_t a = nullptr, b = nullptr;
+        kt->events(name, &a, &b);
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, a, b, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, s, args...);
     }
-    ~TimerScope() {
-        if (kt) kt->end(s);
-    }
-};
+}
 
 struct FusedLayout {
     cf* slabs;
@@ -1163,46 +1166,31 @@ hipError_t fused_impl(const FusedPlan& fp, const FusedRot* rots, int n_rot, cons
     const int nz = fp.planar ? 1 : N;
     const int npair = (n_rot + 1) / 2;
     const FusedLayout L = fused_layout(fp, ws);
-    {
-        TimerScope ts(kt, "spread_slab", s);
-        hipLaunchKernelGGL((spread_slab_kernel<N, P>), dim3(persistent_grid(nz * n_rot, fp.max_wgs)),
-                           dim3(kSlabBlock), 0, s, rots, jobs, n_rot, fp.planar ? 1 : 0, L.slabs);
-    }
+    launch_k(kt, "spread_slab", spread_slab_kernel<N, P>, dim3(persistent_grid(nz * n_rot, fp.max_wgs)),
+             dim3(kSlabBlock), s, rots, jobs, n_rot, fp.planar ? 1 : 0, L.slabs);
     const int gr = fp.pencil_group;
     const int items2 = (fused_pair_grouped(N, fp.planar) ? pencil_jobs_grouped<N>() : pencil_jobs<N>()) *
                        ((n_rot + gr - 1) / gr);
     const dim3 g2{persistent_grid(items2, fp.max_wgs * (gr == 2 ? 2 : 1)), 1u, 1u};
-    {
-        TimerScope ts(kt, "pencil", s);
-        if (fp.planar) {
-            if (gr == 4)
-                hipLaunchKernelGGL((pencil_kernel<N, 1, 4, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
-                                   L.packed);
-            else
-                hipLaunchKernelGGL((pencil_kernel<N, 1, 2, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
-                                   L.packed);
-        } else {
-            if (gr == 4)
-                hipLaunchKernelGGL((pencil_kernel<N, N, 4, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
-                                   L.packed);
-            else
-                hipLaunchKernelGGL((pencil_kernel<N, N, 2, P>), g2, dim3(kPencilBlock), 0, s, rots, jobs, n_rot, L.slabs,
-                                   L.packed);
-        }
+    const dim3 b2{unsigned(kPencilBlock), 1u, 1u};
+    if (fp.planar) {
+        if (gr == 4)
+            launch_k(kt, "pencil", pencil_kernel<N, 1, 4, P>, g2, b2, s, rots, jobs, n_rot, L.slabs, L.packed);
+        else
+            launch_k(kt, "pencil", pencil_kernel<N, 1, 2, P>, g2, b2, s, rots, jobs, n_rot, L.slabs, L.packed);
+    } else {
+        if (gr == 4)
+            launch_k(kt, "pencil", pencil_kernel<N, N, 4, P>, g2, b2, s, rots, jobs, n_rot, L.slabs, L.packed);
+        else
+            launch_k(kt, "pencil", pencil_kernel<N, N, 2, P>, g2, b2, s, rots, jobs, n_rot, L.slabs, L.packed);
     }
-    {
-        TimerScope ts(kt, "islab_peak", s);
-        hipLaunchKernelGGL((islab_peak_kernel<N, P>), dim3(persistent_grid(nz * npair, fp.max_wgs)), dim3(kSlabBlock),
-                           0, s, L.packed, nz, n_rot, L.pval, L.pidx);
-    }
-    {
-        TimerScope ts(kt, "finish", s);
-        const dim3 g4{unsigned(fp.planar ? 1 : 3), unsigned(n_rot), 1u};
-        hipLaunchKernelGGL(finish_slab_kernel<N>, g4, dim3(kFinishBlock), 0, s, L.packed, nz, L.pval, L.pidx, L.nbbuf,
-                           rots, jobs);
-        hipLaunchKernelGGL(finish_rot_kernel, dim3(unsigned((n_rot + 63) / 64)), dim3(64), 0, s, L.nbbuf, rots, jobs,
-                           n_rot);
-    }
+    launch_k(kt, "islab_peak", islab_peak_kernel<N, P>, dim3(persistent_grid(nz * npair, fp.max_wgs)),
+             dim3(kSlabBlock), s, L.packed, nz, n_rot, L.pval, L.pidx);
+    const dim3 g4{unsigned(fp.planar ? 1 : 3), unsigned(n_rot), 1u};
+    launch_k(kt, "finish", finish_slab_kernel<N>, g4, dim3(kFinishBlock), s, L.packed, nz, L.pval, L.pidx, L.nbbuf,
+             rots, jobs);
+    launch_k(kt, "finish_rot", finish_rot_kernel, dim3(unsigned((n_rot + 63) / 64)), dim3(64), s, L.nbbuf, rots, jobs,
+             n_rot);
     return hipGetLastError();
 }
 

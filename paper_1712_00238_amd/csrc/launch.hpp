@@ -60,9 +60,11 @@ hipError_t launch_real_part(const void* vol, T* out, int64_t count, hipStream_t 
 
 // Optional per-kernel timing hook: begin/end bracket one kernel launch on a
 // stream (implemented with HIP events by the ABI layer).
+// Per-kernel timing: the timer hands out a start / stop event pair that the
+// kernel's own dispatch records (hipExtLaunchKernelGGL), so the interval is
+// the kernel's execution, as a kernel trace reports it.
 struct KernelTimer {
-    virtual void begin(const char* name, hipStream_t s) = 0;
-    virtual void end(hipStream_t s) = 0;
+    virtual void events(const char* name, hipEvent_t* start, hipEvent_t* stop) = 0;
     virtual ~KernelTimer() = default;
 };
 
