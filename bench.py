@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--fp64-rotations", type=int, default=64, help="rotations timed on the plain FP64 path")
     ap.add_argument("--grad-poses", type=int, default=1024)
     ap.add_argument("--grad-steps", type=int, default=5)
-    ap.add_argument("--cpu-rotations", type=int, default=12, help="rotations of the oracle timed on the host")
+    ap.add_argument("--cpu-rotations", type=int, default=2,
+                    help="oracle rotations per host worker in the CPU baseline")
     ap.add_argument("--protein-rotations", type=int, default=3600,
                     help="rotations of the protein-like pair scored 64 per launch (0: skip)")
     ap.add_argument("--uneven-pairs", type=int, default=48,
@@ -113,30 +114,113 @@ def load_traffic(kernel: str, sha: str, rotations: int):
     return k["hbm_bytes_per_rotation"] * rotations
 
 
-def cpu_baseline(pair, n_rot: int):
-    """The FP64 oracle's per-rotation scoring on the host: seeded random
-    complex fields of the workload's shapes (values do not change the work),
-    spread + numpy FFTs + peak, one process."""
+def _oracle_rotations(args):
+    """Worker: score rotations qs with the oracle on seeded fields (fork)."""
     import numpy as np
 
     from oracle import correlate as oc
     from oracle import peak as op
 
+    qs, n, nm = args
     rng = np.random.default_rng(0)
-    n = pair.fixed.grid.n[0]
-    nm = pair.moving.grid.n[0]
     rho_f = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
     c = rng.normal(size=nm ** 3) + 1j * rng.normal(size=nm ** 3)
     t0 = time.perf_counter()
-    for q in pair.quats[:n_rot]:
+    for q in qs:
         vol = oc.score_volume(rho_f, c, q, nm, False)
-        s, _, t = op.peak(vol)
+        _, _, t = op.peak(vol)
         op.subvoxel(op.neighbourhood(vol, t), t)
+    return time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(pair, per_worker: int):
+    """The FP64 oracle's per-rotation scoring on the host (spread, numpy FFT
+    pair, peak, sub-voxel) on seeded random complex fields of the workload's
+    shapes (values do not change the work): rotation-parallel over the cores
+    this process may use (at most 16), `per_worker` rotations per worker,
+    plus one worker alone for the single-core rate."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+
+    n = pair.fixed.grid.n[0]
+    nm = pair.moving.grid.n[0]
+    avail = len(os.sched_getaffinity(0))
+    workers = max(1, min(16, avail))
+    qs = pair.quats
+    t0 = time.perf_counter()
+    single = _oracle_rotations((qs[:per_worker], n, nm))
+    single_rate = per_worker / single
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        chunks = [(qs[(i * per_worker) % len(qs):][:per_worker], n, nm) for i in range(workers)]
+        list(ex.map(_oracle_rotations, chunks))
+    wall = time.perf_counter() - t0
+    total = workers * per_worker
+    return {"value": total / wall, "unit": "rotations/s", "cores": workers, "kind": "oracle",
+            "sample": f"{total} of {len(qs)} rotations at {n}^3 / {nm}^3 (FP64 spread, numpy FFT pair, peak, "
+                      f"sub-voxel), {workers} processes x {per_worker} rotations, {wall:.1f} s wall; "
+                      f"host: {cpu_model()}, {avail} cores available",
+            "single_core_value": single_rate}
+
+
+def cpu_extras(pair):
+    """Oracle SDF build pairs/s (C, OpenMP) and pose-gradient evaluations/s
+    (numpy, one process) on bounded samples of the workload."""
+    import numpy as np
+
+    from oracle import grad as og
+    from oracle import sdf as osdf
+    from oracle import spread as osp
+
+    fx = pair.fixed
+    rng = np.random.default_rng(1)
+    nodes = fx.grid.node_positions()[rng.choice(fx.grid.size, size=20000, replace=False)]
+    t0 = time.perf_counter()
+    osdf.sdf_points(fx.samples, nodes, pair.params)
     dt = time.perf_counter() - t0
-    threads = 1
-    return {"value": n_rot / dt, "unit": "rotations/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_rot} of {len(pair.quats)} rotations at {n}^3 / {nm}^3 (FP64 spread, numpy FFT pair, "
-                      f"peak, sub-voxel), {dt:.1f} s"}
+    pairs_per_s = len(nodes) * fx.samples.count / dt
+    n, nm = fx.grid.n[0], pair.moving.grid.n[0]
+    rho_f = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
+    rho_m = rng.normal(size=(nm, nm, nm)) + 1j * rng.normal(size=(nm, nm, nm))
+    c = rho_m.reshape(-1)
+    xb = osp.body_positions(nm)
+    t0 = time.perf_counter()
+    for b in range(2):
+        og.pose_value_and_grad(rho_f, c, rho_m, xb, np.array([3.3, -2.1, 0.7]) * (b + 1), pair.quats[b])
+    g = 2 / (time.perf_counter() - t0)
+    return {"sdf_build_pairs_per_s": pairs_per_s, "sdf_build_threads": int(os.environ.get("OMP_NUM_THREADS", "0")) or
+            len(os.sched_getaffinity(0)), "sdf_sample": f"20000 nodes x {fx.samples.count} samples",
+            "grad_evals_per_s": g, "grad_sample": "2 poses, one process"}
+
+
+def copy_bandwidth(dev) -> float:
+    """Device-to-device copy of 1 GiB, read + write bytes per second."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / 5
+    del a, b
+    return 2.0 * n * 4 / sec
 
 
 def main():
@@ -245,6 +329,24 @@ def main():
         stage_bytes = sum(v["algorithmic_bytes_per_launch"] for v in kernels.values())
         stage_us = sum(v["avg_us"] for v in kernels.values())
         report["stage_GBs"] = stage_bytes / (stage_us * 1e-6) / 1e9
+        # whole correlation stage per rotation (spread, FFTs, product, peak) over the
+        # timed calls, against the model of a minimal three-pass design (slab R + W,
+        # pencil R + spectrum R + W, inverse slab R: 6 N^3 x 8 B), against the HBM
+        # bytes the counters measured, and against a measured device copy
+        sec_per_rot = ms_per_step * 1e-3 / n_rot
+        model = 6.0 * N ** 3 * 8.0
+        tr = [load_traffic(k, sha, 1.0) for k in ("spread_slab", "pencil", "islab_peak", "finish")]
+        counter = sum(tr) if all(v is not None for v in tr) else None
+        copy_bps = copy_bandwidth(dev)
+        report["correlation_stage"] = {
+            "model_bytes_per_rotation": model,
+            "achieved_model_GBs": round(model / sec_per_rot / 1e9, 1),
+            "frac_model": round(model / sec_per_rot / (HBM_PEAK_GBS * 1e9), 4),
+            "counter_bytes_per_rotation": counter,
+            "achieved_counter_GBs": None if counter is None else round(counter / sec_per_rot / 1e9, 1),
+            "frac_counter": None if counter is None else round(counter / sec_per_rot / (HBM_PEAK_GBS * 1e9), 4),
+            "copy_GBs": round(copy_bps / 1e9, 1),
+            "frac_model_of_copy": round(model / sec_per_rot / copy_bps, 4)}
         report["kernels"] = {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                              for k, v in kernels.items()}
 
@@ -362,6 +464,7 @@ def main():
             "pose_grad_evals_per_s": round(report["pose_grad_evals_per_s"], 1),
             "fp32_vs_fp64": report["fp32_vs_fp64"],
             "stage_GBs": round(report["stage_GBs"], 1),
+            "correlation_stage": report["correlation_stage"],
             "sdf_build_fixed_ms": round(report["sdf_build_fixed_ms"], 3),
             "sdf_build_fixed_pairs_per_s": report["sdf_build_fixed_pairs_per_s"],
             "spectrum_ms": round(report["spectrum_ms"], 4),
@@ -370,6 +473,7 @@ def main():
             "kernels": report["kernels"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pair, args.cpu_rotations)
+        line["cpu_oracle_extras"] = cpu_extras(pair)
     print(json.dumps(line), flush=True)
 
 
