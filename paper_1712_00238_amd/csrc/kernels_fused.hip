@@ -161,10 +161,12 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 // Slab layouts.  Generic sizes keep the interleaved complex N x N slab and
 // two N x N integer planes over the same bytes, with periodic wrap of the
 // stencil.  N = 64 and 128 use a padded row layout: row y holds the re plane
-// (N ints), the im plane (N ints) and 8 pad ints, so the complex row that
-// replaces it after conversion has N + 4 entries and consecutive rows start
-// 8 banks apart (unpadded rows put every row on the same banks and double the
-// scatter's conflict stalls).  Positions are stored shifted by N / 2 in x and y,
+// (N ints), the im plane (N ints) and 16 pad ints (unpadded rows put every
+// row on the same banks and double the scatter's conflict stalls).  The
+// complex row that replaces it after conversion has N + 8 entries, entry e
+// at e + e / 16, so that the radix-16 pass along x, which writes 16
+// consecutive entries per lane, does not put the 8 lanes of a row on the
+// same banks.  Positions are stored shifted by N / 2 in x and y,
 // which the fitting rule for the rotated body box keeps inside [0, N), so no
 // index wraps and the 16 stencil addresses of a sample are one base plus
 // constant offsets.  The shift multiplies the slab's 2D DFT by (-1)^(kx+ky),
@@ -172,7 +174,7 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 template <int N>
 struct SlabLayout {
     static constexpr bool kFast = N == 64 || N == 128;
-    static constexpr int kRowInts = kFast ? 2 * N + 8 : N;   // ints per accumulation row
+    static constexpr int kRowInts = kFast ? 2 * N + 16 : N;  // ints per accumulation row
     static constexpr int kImOff = kFast ? N : N * N;          // im plane offset (ints)
     static constexpr int kInts = kFast ? N * kRowInts : 2 * N * N;
     static constexpr int kRowCf = kRowInts / 2;                // complex stride after conversion (fast)
@@ -379,6 +381,7 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
     constexpr int R1 = N / 8;
     constexpr int NB = N / 8;   // radix-8 butterflies per line
     constexpr int RS = L::kRowCf;
+    auto px = [](int e) { return e + (e >> 4); };
     cf* slab = reinterpret_cast<cf*>(acc);
     // opaque copy of the thread index: keeps the compiler from hoisting this
     // phase's ~60 address registers out of the item loop, where they would
@@ -397,19 +400,19 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
             compiler_fence();
             dftR<float, -1, R1>(v);
 #pragma unroll
-            for (int r = 0; r < R1; ++r) slab[y * RS + j * R1 + r] = v[r];
+            for (int r = 0; r < R1; ++r) slab[y * RS + px(j * R1 + r)] = v[r];
             compiler_fence();
 #pragma unroll
             for (int m = 0; m < NB / 8; ++m) {
                 const int jj = j + 8 * m;  // k = jj
                 cf u[8];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + jj + NB * r];
+                for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + px(jj + NB * r)];
 #pragma unroll
                 for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
                 dft8<float, -1>(u);
 #pragma unroll
-                for (int r = 0; r < 8; ++r) slab[y * RS + jj + NB * r] = u[r];
+                for (int r = 0; r < 8; ++r) slab[y * RS + px(jj + NB * r)] = u[r];
             }
         }
     }
@@ -420,13 +423,13 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
         cf v[R1];
         if (on) {
 #pragma unroll
-            for (int r = 0; r < R1; ++r) v[r] = slab[(jb + 8 * r) * RS + x];
+            for (int r = 0; r < R1; ++r) v[r] = slab[(jb + 8 * r) * RS + px(x)];
             dftR<float, -1, R1>(v);
         }
         __syncthreads();
         if (on) {
 #pragma unroll
-            for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + x] = v[r];
+            for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + px(x)] = v[r];
         }
         __syncthreads();
     }
@@ -436,7 +439,7 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
             const int jj = jb + 8 * m;
             cf u[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + x];
+            for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + px(x)];
 #pragma unroll
             for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
             dft8<float, -1>(u);
@@ -445,7 +448,8 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
                 const int ky = jj + NB * r;
                 const float sg = ((x + ky) & 1) ? -1.f : 1.f;
                 out[ky * N + (grouped ? col_pos<N>(x) : x)] = u[r] * sg;
-                slab[ky * RS + x] = mk(0.f, 0.f);
+                slab[ky * RS + px(x)] = mk(0.f, 0.f);
+                if (x < N / 16) slab[ky * RS + 17 * x + 16] = mk(0.f, 0.f);  // the gap entries
             }
         }
     }
@@ -836,7 +840,11 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
                                                       float& vb, int& ib, bool grouped) {
     constexpr int R1 = N / 8;
     constexpr int NB = N / 8;
-    constexpr int RS = N + 4;  // padded row stride (complex entries)
+    // row entry e at e + e / 16: the radix-16 pass along x writes 16
+    // consecutive entries per lane, which without the gap would put the 8
+    // lanes of a row on the same banks
+    constexpr int RS = N + N / 16 + 4;  // padded row stride (complex entries)
+    auto px = [](int e) { return e + (e >> 4); };
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     const int x = t % N, jb = t / N;
@@ -844,7 +852,7 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
     if (on) {
         dftR<float, 1, R1>(pre);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + x] = pre[r];
+        for (int r = 0; r < R1; ++r) slab[(jb * R1 + r) * RS + px(x)] = pre[r];
     }
     __syncthreads();
     if (on) {
@@ -853,12 +861,12 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
             const int jj = jb + 8 * m;
             cf u[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + x];
+            for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + px(x)];
 #pragma unroll
             for (int r = 1; r < 8; ++r) u[r] = u[r] * conj(tw[r * jj]);
             dft8<float, 1>(u);
 #pragma unroll
-            for (int r = 0; r < 8; ++r) slab[(jj + NB * r) * RS + x] = u[r];
+            for (int r = 0; r < 8; ++r) slab[(jj + NB * r) * RS + px(x)] = u[r];
         }
         if (next) {
             const int px = grouped ? col_pos<N>(x) : x;
@@ -871,18 +879,18 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
     if (y < N) {
         cf v[R1];
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = slab[y * RS + j + 8 * r];
+        for (int r = 0; r < R1; ++r) v[r] = slab[y * RS + px(j + 8 * r)];
         compiler_fence();
         dftR<float, 1, R1>(v);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) slab[y * RS + j * R1 + r] = v[r];
+        for (int r = 0; r < R1; ++r) slab[y * RS + px(j * R1 + r)] = v[r];
         compiler_fence();
 #pragma unroll
         for (int m = 0; m < NB / 8; ++m) {
             const int jj = j + 8 * m;
             cf u[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + jj + NB * r];
+            for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + px(jj + NB * r)];
 #pragma unroll
             for (int r = 1; r < 8; ++r) u[r] = u[r] * conj(tw[r * jj]);
             dft8<float, 1>(u);
@@ -902,7 +910,7 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
                                                                 float* __restrict__ pval, int* __restrict__ pidx) {
     using Plan = typename FusedRadix<N, P>::type;
     constexpr bool kFast = SlabLayout<N>::kFast;
-    __shared__ cf slab[kFast ? N * (N + 4) : N * N];
+    __shared__ cf slab[kFast ? N * (N + N / 16 + 4) : N * N];
     __shared__ cf tw[N];
     __shared__ float rv[2][kSlabBlock / 64];
     __shared__ int ri[2][kSlabBlock / 64];
