@@ -426,6 +426,8 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
             for (int a = 0; a < 4; ++a) ri.q[a] = p.quats[4 * r + a];
             ri.job = jj;
             ri.local = int(r);
+            ri.n_m = p.gm->n[0];
+            ri.N = p.gf->n[2] == 1 ? 0 : p.gf->n[0];
             rin_h.push_back(ri);
         }
     }

@@ -122,7 +122,24 @@ __global__ void rot_desc_kernel(const RotInput* __restrict__ in, int64_t n, Fuse
     for (int a = 0; a < 9; ++a) o.R[a] = float(m[a]);
     o.job = r.job;
     o.local = r.local;
-    o.pad = 0;
+    if (r.N > 0) {
+        // heights of the reflected body nodes -R (k - n_m/2), k in [0, n_m)^3;
+        // a slab at centred height zc receives a sample iff |zc - y_z| < 2.
+        // The 1e-3 margin covers the FP32 positions the spread kernel forms.
+        const double lo = -0.5 * r.n_m, hi = 0.5 * r.n_m - 1.0;
+        double zmin = 0.0, zmax = 0.0;
+        for (int b = 0; b < 3; ++b) {
+            const double a = -m[6 + b];
+            zmin += fmin(a * lo, a * hi);
+            zmax += fmax(a * lo, a * hi);
+        }
+        const int zl = int(floor(zmin - 2.0 - 1e-3)), zh = int(ceil(zmax + 2.0 + 1e-3));
+        o.zlo = short(zl < -r.N / 2 ? -r.N / 2 : zl);
+        o.zhi = short(zh > r.N / 2 - 1 ? r.N / 2 - 1 : zh);
+    } else {
+        o.zlo = 0;
+        o.zhi = 0;
+    }
     out[i] = o;
 }
 
@@ -478,6 +495,8 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
         const int rot = item / nz;
         const int z = (item % nz + 53 * (rot % nz)) % nz;
         const FusedRot fr = rots[rot];
+        const int zc = z < N / 2 ? z : z - N;
+        if (nz > 1 && (zc < fr.zlo || zc > fr.zhi)) continue;  // uniform: the slab is zero and is not written
         const FusedJob jb = jobs[fr.job];
         __syncthreads();  // previous item done with the slab
         if constexpr (!L::kFast) {
@@ -561,7 +580,8 @@ __device__ __forceinline__ PencilJob pencil_job_grouped(int j) {
 template <int N, int GR>
 __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict__ slabs, cf* __restrict__ packed,
                                                  cf* __restrict__ buf, const cf* __restrict__ tw,
-                                                 const cf* const* spec_of, const PencilJob job, int g0) {
+                                                 const cf* const* spec_of, const int (*zr_of)[2], const PencilJob job,
+                                                 int g0) {
     constexpr int W = pencil_width<N>();
     constexpr int NL = 2 * W * GR;
     constexpr int NLP = NL + 8;
@@ -602,12 +622,18 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
     for (int b = t; b < NL * 8; b += kPencilBlock) {
         const int l = b % NL, j = b / NL;
         const int cc = l % W, tt = (l / W) % 2;
-        const int rot = g0 + line_rot(l);
+        const int lr = line_rot(l);
+        const int rot = g0 + lr;
         cf v[R1];
         if (rot < n_rot) {
+            // slabs outside the rotation's range were never written: zeros
+            const int zlo = zr_of[lr][0], zhi = zr_of[lr][1];
             const cf* src = slabs + int64_t(rot) * G + int64_t(kyt[tt]) * N + kx_of(tt, cc);
 #pragma unroll
-            for (int r = 0; r < R1; ++r) v[r] = src[int64_t(j + 8 * r) * N * N];
+            for (int r = 0; r < R1; ++r) {
+                const int kz = j + 8 * r, zc = kz < N / 2 ? kz : kz - N;
+                v[r] = (zc >= zlo && zc <= zhi) ? src[int64_t(kz) * N * N] : mk(0.f, 0.f);
+            }
             dftR<float, -1, R1>(v);
         } else {
 #pragma unroll
@@ -697,6 +723,7 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
     __shared__ cf buf[kFast ? NZ * (NL + 8) : NZ * NL];
     __shared__ cf tw[NZ > 1 ? NZ : 1];
     __shared__ const cf* spec_of[GR];
+    __shared__ int zr_of[GR][2];  // slab range [zlo, zhi] of each rotation of the group
     const int64_t G = int64_t(N) * N * NZ;
     if constexpr (NZ > 1) fill_twiddles<float, NZ>(tw);
     auto line_of = [](int r, int t, int cc) { return ((r & 1) * GR + (r >> 1) * 2 + t) * W + cc; };
@@ -713,10 +740,12 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
         if (threadIdx.x < GR) {
             const int rot = g0 + threadIdx.x;
             spec_of[threadIdx.x] = rot < n_rot ? static_cast<const cf*>(jobs[rots[rot].job].spec) : nullptr;
+            zr_of[threadIdx.x][0] = rot < n_rot ? (NZ > 1 ? int(rots[rot].zlo) : 0) : 1;
+            zr_of[threadIdx.x][1] = rot < n_rot ? (NZ > 1 ? int(rots[rot].zhi) : 0) : 0;
         }
+        __syncthreads();  // spec_of / zr_of visible
         if constexpr (kFast) {
-            __syncthreads();
-            pencil_item_fast<N, GR>(n_rot, slabs, packed, buf, tw, spec_of, job, g0);
+            pencil_item_fast<N, GR>(n_rot, slabs, packed, buf, tw, spec_of, zr_of, job, g0);
             continue;
         }
         // load both tiles of every rotation of the group (zeros for missing
@@ -734,7 +763,9 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
                 const int r = i / (W * NZ * 2);
                 const int rot = g0 + r;
                 v[p] = mk(0.f, 0.f);
-                if ((TOT % kPencilBlock == 0 || i < TOT) && rot < n_rot)
+                const int zc = kz < NZ / 2 ? kz : kz - NZ;
+                const bool reached = NZ == 1 || (zc >= zr_of[r][0] && zc <= zr_of[r][1]);
+                if ((TOT % kPencilBlock == 0 || i < TOT) && rot < n_rot && reached)
                     v[p] = slabs[int64_t(rot) * G + (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)];
             }
 #pragma unroll

@@ -82,18 +82,24 @@ struct FusedJob {
     int planar;          // 1: n_m^2 x 1 body box
 };
 // One rotation of the search, device-resident: FP32 matrix, owning pair,
-// index of the rotation within that pair's outputs.
+// index of the rotation within that pair's outputs, and the range of centred
+// slab heights [zlo, zhi] that the rotated body box can reach (slabs outside
+// it are identically zero: the spread kernel does not write them and the
+// pencil kernel reads zeros instead).
 struct FusedRot {
     float R[9];
     int job;
     int local;
-    int pad;
+    short zlo, zhi;
 };
-// Host-side input of one rotation: FP64 quaternion, pair, local index.
+// Host-side input of one rotation: FP64 quaternion, pair, local index, and
+// the body box and grid sizes that bound its slab range.
 struct RotInput {
     double q[4];
     int job;
     int local;
+    int n_m;
+    int N;      // fixed grid size; 0 for a planar pair (one slab, always reached)
 };
 struct FusedPlan {
     int N;
