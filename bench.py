@@ -76,19 +76,38 @@ def copy_mode():
     print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "launches": 3}))
 
 
-def algorithmic_bytes(kernel: str, nb: int, N: int, n_m: int, planar: bool) -> float:
+def reach_fraction(quats, n_m: int, N: int) -> float:
+    """Mean fraction of the N slab heights that a rotated n_m^3 body box and
+    its B-spline support can reach (the bound the rotation descriptors carry):
+    the other slabs are identically zero and are neither written nor read."""
+    import numpy as np
+    q = np.asarray(quats, dtype=np.float64)
+    q = q / np.linalg.norm(q, axis=1, keepdims=True)
+    w, x, y, z = q.T
+    row_z = np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], axis=1)
+    a = -row_z
+    lo, hi = -0.5 * n_m, 0.5 * n_m - 1.0
+    zmin = np.minimum(a * lo, a * hi).sum(axis=1)
+    zmax = np.maximum(a * lo, a * hi).sum(axis=1)
+    zl = np.maximum(np.floor(zmin - 2.0 - 1e-3), -N // 2)
+    zh = np.minimum(np.ceil(zmax + 2.0 + 1e-3), N // 2 - 1)
+    return float(np.mean(zh - zl + 1) / N)
+
+
+def algorithmic_bytes(kernel: str, nb: int, N: int, n_m: int, planar: bool, reach: float = 1.0) -> float:
     """Bytes a kernel must move per launch of nb rotations (complex64 = 8 B):
-    spread_slab reads each rotation's samples once and writes its slab grid;
-    pencil reads every slab grid, the spectrum once, and writes the folded
-    grid of each rotation pair; islab_peak reads the folded grids."""
+    spread_slab reads each rotation's coefficients once and writes the slabs
+    its body box reaches (fraction `reach`); pencil reads those slabs, the
+    spectrum once, and writes the folded grid of each rotation pair;
+    islab_peak reads the folded grids."""
     nz = 1 if planar else N
     G = N * N * nz
     K = n_m * n_m * (1 if planar else n_m)
     pairs = (nb + 1) // 2
     if kernel == "spread_slab":
-        return nb * (8.0 * K + 8.0 * G)
+        return nb * (8.0 * K + 8.0 * G * reach)
     if kernel == "pencil":
-        return nb * 8.0 * G + 8.0 * G + pairs * 8.0 * G
+        return nb * 8.0 * G * reach + 8.0 * G + pairs * 8.0 * G
     if kernel == "islab_peak":
         return pairs * 8.0 * G
     if kernel == "finish":
@@ -312,9 +331,12 @@ def main():
         # (576 = 4 x 128 + 64): bytes and durations are both averaged over that mix
         sizes = [min(args.batch, n_rot - i) for i in range(0, n_rot, args.batch)]
         rot_per_launch = n_rot / len(sizes)
+        reach = reach_fraction(pair.quats, n_m, N)
+        report["slab_reach"] = round(reach, 4)
         for k, v in kernels.items():
             v["share"] = v["avg_us"] * v["launches"] / tot
-            v["algorithmic_bytes_per_launch"] = sum(algorithmic_bytes(k, nb, N, n_m, False) for nb in sizes) / len(sizes)
+            v["algorithmic_bytes_per_launch"] = sum(algorithmic_bytes(k, nb, N, n_m, False, reach)
+                                                    for nb in sizes) / len(sizes)
             v["achieved_GBs"] = v["algorithmic_bytes_per_launch"] / (v["avg_us"] * 1e-6) / 1e9
         dom = max(kernels, key=lambda k: kernels[k]["share"])
         sha = sources_sha()
@@ -465,6 +487,7 @@ def main():
             "fp32_vs_fp64": report["fp32_vs_fp64"],
             "stage_GBs": round(report["stage_GBs"], 1),
             "correlation_stage": report["correlation_stage"],
+            "slab_reach": report["slab_reach"],
             "sdf_build_fixed_ms": round(report["sdf_build_fixed_ms"], 3),
             "sdf_build_fixed_pairs_per_s": report["sdf_build_fixed_pairs_per_s"],
             "spectrum_ms": round(report["spectrum_ms"], 4),
