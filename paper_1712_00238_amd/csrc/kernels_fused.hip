@@ -409,11 +409,19 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
         const int y = t / 8, j = t % 8;
         if (y < N) {
             cf v[R1];
+            int any = 0;
 #pragma unroll
             for (int r = 0; r < R1; ++r) {
                 const int x = j + 8 * r;
-                v[r] = mk(float(acc[y * L::kRowInts + x]) * inv, float(acc[y * L::kRowInts + L::kImOff + x]) * inv);
+                const int a = acc[y * L::kRowInts + x], b = acc[y * L::kRowInts + L::kImOff + x];
+                any |= a | b;
+                v[r] = mk(float(a) * inv, float(b) * inv);
             }
+            // A row the scatter did not touch transforms to zeros, which the
+            // LDS already holds (integer 0 and float +0 share their bits):
+            // the 8 lanes of such a row skip both x passes.
+            const uint64_t touched = __ballot(any != 0);
+            if (((touched >> ((threadIdx.x & 63) & ~7)) & 0xffull) == 0) goto x_done;
             compiler_fence();
             dftR<float, -1, R1>(v);
 #pragma unroll
@@ -433,6 +441,7 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
             }
         }
     }
+x_done:
     __syncthreads();
     const int x = t % N, jb = t / N;
     const bool on = jb < 8;
@@ -916,20 +925,26 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
 #pragma unroll
         for (int r = 0; r < R1; ++r) slab[y * RS + px(j * R1 + r)] = v[r];
         compiler_fence();
+        cf u[NB / 8][8];
 #pragma unroll
         for (int m = 0; m < NB / 8; ++m) {
             const int jj = j + 8 * m;
-            cf u[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + px(jj + NB * r)];
+            for (int r = 0; r < 8; ++r) u[m][r] = slab[y * RS + px(jj + NB * r)];
 #pragma unroll
-            for (int r = 1; r < 8; ++r) u[r] = u[r] * conj(tw[r * jj]);
-            dft8<float, 1>(u);
+            for (int r = 1; r < 8; ++r) u[m][r] = u[m][r] * conj(tw[r * jj]);
+            dft8<float, 1>(u[m]);
+        }
+        // visit the outputs in increasing index (x = j + 8 m + NB r): a strict
+        // comparison then keeps the lowest index among equal values
+        const int row = zoff + y * N + j;
 #pragma unroll
-            for (int r = 0; r < 8; ++r) {
-                const int idx = zoff + y * N + jj + NB * r;
-                take(u[r].re, idx, va, ia);
-                take(u[r].im, idx, vb, ib);
+        for (int r = 0; r < 8; ++r) {
+#pragma unroll
+            for (int m = 0; m < NB / 8; ++m) {
+                const int idx = row + 8 * m + NB * r;
+                if (u[m][r].re > va) { va = u[m][r].re; ia = idx; }
+                if (u[m][r].im > vb) { vb = u[m][r].im; ib = idx; }
             }
         }
     }
