@@ -108,7 +108,8 @@ const char *sdf_last_error(sdf_ctx ctx);
  *   "graph"         1: capture each batch's launch sequence in a hipGraph and replay it
  *   "pencil_group"  rotations sharing one spectrum tile in the fused pencil pass (2 or 4)
  *   "profile"       1: time every fused kernel (see sdf_ctx_stats)
- *   "radix"         FFT radix schedule of the fused kernels (0, 1, 2; e.g. 128 = 8.4.4, 4.4.8, 2.8.8)
+ *   "radix"         FFT radix schedule of the fused kernels for N = 8, 16, 32, 96 (0, 1, 2;
+ *                   e.g. 96 = 8.4.3, 3.4.8, 4.8.3); N = 64 and 128 use fixed two-pass transforms
  *   "autotune"      1: tune each grid-size class on its first search (see sdf_autotune)
  * With "graph" = 1 the fused launch sequence of a score_rotations call is
  * captured once and replayed while the buffers, shapes and stream stay the
@@ -210,7 +211,8 @@ int score_pairs(sdf_ctx ctx, const sdf_pair_job *jobs, int64_t n_jobs, sdf_strea
 
 /* Autotuner for the fused FP32 search of one grid-size class (N, planar,
  * N_M): times every candidate plan (rotations per batch in {32, 64, 128},
- * rotations per pencil block in {2, 4}, three FFT radix schedules) on
+ * rotations per pencil block in {2, 4}, three FFT radix schedules for the
+ * sizes that use them; N = 64 and 128 use fixed two-pass transforms) on
  * synthetic inputs, rejects candidates whose peaks differ from the plain
  * multi-pass path by more than 1e-4 of the largest score on a probe set, and
  * keeps the fastest for this context (option "autotune" = 1 runs this on the

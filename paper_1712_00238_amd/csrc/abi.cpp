@@ -624,7 +624,9 @@ int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std:
     bool first = true;
     for (int batch : {32, 64, 128}) {
         for (int group : {2, 4}) {
-            for (int radix : {0, 1, 2}) {
+            // N = 64 and 128 use fixed two-pass transforms: the schedule does not apply
+            const int n_radix = (N == 64 || N == 128) ? 1 : 3;
+            for (int radix = 0; radix < n_radix; ++radix) {
                 ctx->opt_batch = batch;
                 ctx->opt_pencil_group = group;
                 ctx->opt_radix = radix;
