@@ -173,7 +173,12 @@ def test_score_volume_direct_sum_tiny(ctxs):
 
 @pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("n,nm,planar,nrot,batch", [(16, 6, False, 7, 4), (32, 14, False, 5, 2), (32, 19, True, 9, 4),
-                                                    (8, 2, False, 3, 2), (96, 8, False, 3, 2)])
+                                                    (8, 2, False, 3, 2), (96, 8, False, 3, 2), (16, 6, False, 1, 2),
+                                                    # the two-pass sizes: 3D with ragged, odd batches, planar
+                                                    (64, 24, False, 7, 4), (64, 30, True, 5, 4),
+                                                    # largest body boxes the fitting rule admits (stencil at the
+                                                    # edge of the unwrapped slab; 71 is odd: generic lane map)
+                                                    (64, 34, False, 3, 2), (128, 71, False, 2, 2)])
 def test_score_rotations_peaks_f32(ctxs, path, n, nm, planar, nrot, batch):
     ctx = ctxs["f32"]
     ctx.set_option("path", path)
