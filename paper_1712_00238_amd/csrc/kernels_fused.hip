@@ -586,11 +586,24 @@ __device__ __forceinline__ PencilJob pencil_job_grouped(int j) {
 //  I  inverse radix-R1 and radix-8 passes over the Z lines, 8 lines per
 //     wave (no block barrier between them), the last pass writing global
 //     memory.
+// The spectrum values of a thread's pass-B units (GR = 2: two units of 8
+// values) are kept in registers: they are requested before the pass-A loads
+// so both round trips to memory overlap, and consecutive items of a block
+// that share the pencil job and the spectra reuse them.
+template <int N, int GR>
+struct PencilSpec {
+    static constexpr int NL = 2 * pencil_width<N>() * GR;
+    static constexpr int NB = N / 8;
+    static constexpr int PB = (NL * NB + kPencilBlock - 1) / kPencilBlock;
+    static constexpr bool kKeep = GR == 2 && PB * kPencilBlock == NL * NB;
+    static constexpr int kRows = kKeep ? PB : 1;
+};
+
 template <int N, int GR>
 __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict__ slabs, cf* __restrict__ packed,
                                                  cf* __restrict__ buf, const cf* __restrict__ tw,
                                                  const cf* const* spec_of, const int (*zr_of)[2], const PencilJob job,
-                                                 int g0) {
+                                                 int g0, cf (&spre)[PencilSpec<N, GR>::kRows][8], bool reload) {
     constexpr int W = pencil_width<N>();
     constexpr int NL = 2 * W * GR;
     constexpr int NLP = NL + 8;
@@ -609,12 +622,8 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
         const int q = l / W;
         return 2 * ((q % GR) / 2) + q / GR;
     };
-    // spectrum values of this thread's pass-B units, requested before the
-    // pass-A loads so both round trips to memory overlap (GR = 2: two units
-    // of 8 values per thread)
-    constexpr int PB = (NL * NB + kPencilBlock - 1) / kPencilBlock;
-    constexpr bool kPre = GR == 2 && PB * kPencilBlock == NL * NB;
-    cf spre[kPre ? PB : 1][8];
+    constexpr int PB = PencilSpec<N, GR>::PB;
+    constexpr bool kPre = PencilSpec<N, GR>::kKeep;
     auto spec_at = [&](int b, int r) {
         const int l = b % NL, jj = b / NL;
         const int cc = l % W, tt = (l / W) % 2;
@@ -622,10 +631,12 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
         return sp ? gload(sp, int64_t(jj + NB * r) * N * N + int64_t(kyt[tt]) * N + kx_of(tt, cc)) : mk(0.f, 0.f);
     };
     if constexpr (kPre) {
+        if (reload) {
 #pragma unroll
-        for (int m = 0; m < PB; ++m)
+            for (int m = 0; m < PB; ++m)
 #pragma unroll
-            for (int r = 0; r < 8; ++r) spre[m][r] = spec_at(t + m * kPencilBlock, r);
+                for (int r = 0; r < 8; ++r) spre[m][r] = spec_at(t + m * kPencilBlock, r);
+        }
     }
     // ---- A
     for (int b = t; b < NL * 8; b += kPencilBlock) {
@@ -721,7 +732,7 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
 
 // Work item = (pencil tile pair, group of GR rotations).  NZ = N (3D) or 1 (planar).
 template <int N, int NZ, int GR, int P>
-__global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __restrict__ rots,
+__global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot* __restrict__ rots,
                                                               const FusedJob* __restrict__ jobs, int n_rot,
                                                               const cf* __restrict__ slabs,
                                                               cf* __restrict__ packed) {
@@ -740,9 +751,22 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
     const int items = (kFast ? pencil_jobs_grouped<N>() : pencil_jobs<N>()) * ngroups;
     const int npair = (n_rot + 1) / 2;
     constexpr int njobs = kFast ? pencil_jobs_grouped<N>() : pencil_jobs<N>();
-    for (int item = blockIdx.x; item < items; item += gridDim.x) {
-        const PencilJob job = kFast ? pencil_job_grouped<N>(item % njobs) : pencil_job<N>(item % njobs);
-        const int g0 = (item / njobs) * GR;  // first rotation of the group
+    // The two-pass path gives each block a contiguous run of items, item =
+    // job * ngroups + group, so consecutive items share the pencil job and
+    // the spectrum values kept in registers; the generic path strides.
+    const int per = (items + int(gridDim.x) - 1) / int(gridDim.x);
+    const int ibeg = kFast ? int(blockIdx.x) * per : int(blockIdx.x);
+    const int iend = kFast ? (ibeg + per < items ? ibeg + per : items) : items;
+    const int istep = kFast ? 1 : int(gridDim.x);
+    cf spre[kFast ? PencilSpec<N, GR>::kRows : 1][8];
+    int prev_job = -1;
+    const cf* prev_spec[GR];
+#pragma unroll
+    for (int k = 0; k < GR; ++k) prev_spec[k] = nullptr;
+    for (int item = ibeg; item < iend; item += istep) {
+        const int jobi = kFast ? item / ngroups : item % njobs;
+        const PencilJob job = kFast ? pencil_job_grouped<N>(jobi) : pencil_job<N>(jobi);
+        const int g0 = (kFast ? item % ngroups : item / njobs) * GR;  // first rotation of the group
         const int kyt[2] = {job.ky, (N - job.ky) % N};
         auto kx_of = [&](int t, int cc) { return t == 0 ? job.x0 + cc : (N - job.x0 - cc) % N; };
         __syncthreads();  // previous item done with buf / spec_of
@@ -754,7 +778,14 @@ __global__ __launch_bounds__(kPencilBlock) void pencil_kernel(const FusedRot* __
         }
         __syncthreads();  // spec_of / zr_of visible
         if constexpr (kFast) {
-            pencil_item_fast<N, GR>(n_rot, slabs, packed, buf, tw, spec_of, zr_of, job, g0);
+            bool reload = jobi != prev_job;
+#pragma unroll
+            for (int k = 0; k < GR; ++k) {
+                reload = reload || spec_of[k] != prev_spec[k];
+                prev_spec[k] = spec_of[k];
+            }
+            prev_job = jobi;
+            pencil_item_fast<N, GR>(n_rot, slabs, packed, buf, tw, spec_of, zr_of, job, g0, spre, reload);
             continue;
         }
         // load both tiles of every rotation of the group (zeros for missing
