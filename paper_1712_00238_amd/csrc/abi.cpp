@@ -384,6 +384,17 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
         batch_bytes = std::max(batch_bytes, sdf::fused_workspace_bytes(plans.back()));
     }
     auto grouped = [&](int j) { return sdf::fused_pair_grouped(pairs[j].gf->n[0], pairs[j].gf->n[2] == 1); };
+    // one reordered spectrum copy per distinct spectrum (pairs may share the fixed part)
+    std::vector<int> xsrc(nj, -1);
+    for (int j = 0; j < nj; ++j) {
+        if (!grouped(j)) continue;
+        xsrc[j] = j;
+        for (int i = 0; i < j; ++i)
+            if (xsrc[i] == i && pairs[i].spec == pairs[j].spec && pairs[i].gf->n[0] == pairs[j].gf->n[0]) {
+                xsrc[j] = i;
+                break;
+            }
+    }
     auto carve = [&](char* base, std::vector<void*>* cptr, std::vector<float*>* sptr, std::vector<void*>* xptr,
                      sdf::FusedJob** jobs_d, sdf::FusedRot** rots_d, sdf::RotInput** rin_d, void** prep,
                      void** fused) {
@@ -395,11 +406,14 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
         for (int j = 0; j < nj; ++j) {
             void* c = cv.take(sizeof(float) * 2 * size_t(gsize(pairs[j].gm)));
             float* sc = static_cast<float*>(cv.take(2 * sizeof(float)));
-            void* x = grouped(j) ? cv.take(sizeof(float) * 2 * size_t(gsize(pairs[j].gf))) : nullptr;
+            void* x = xsrc[j] == j ? cv.take(sizeof(float) * 2 * size_t(gsize(pairs[j].gf))) : nullptr;
             if (cptr) (*cptr)[j] = c;
             if (sptr) (*sptr)[j] = sc;
             if (xptr) (*xptr)[j] = x;
         }
+        if (xptr)
+            for (int j = 0; j < nj; ++j)
+                if (xsrc[j] >= 0 && xsrc[j] != j) (*xptr)[j] = (*xptr)[xsrc[j]];
         *fused = cv.take(batch_bytes);
         return cv.off;
     };
@@ -459,7 +473,7 @@ int fused_pairs(sdf_ctx ctx, const std::vector<PairIn>& pairs, hipStream_t s) {
                                             gsize(pairs[j].gm), cptr[j], s),
                     "coefficients");
     for (int j = 0; j < nj; ++j)
-        if (xptr[j])
+        if (xsrc[j] == j)
             SDF_TRY_HIP(ctx, sdf::launch_spec_pair_group(pairs[j].spec, xptr[j], pairs[j].gf->n[0], s),
                         "spectrum column order");
     SDF_TRY_HIP(ctx, sdf::launch_fused_prep(jobs_d, nj, prep, s), "fixed-point scale");

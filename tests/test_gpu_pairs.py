@@ -69,6 +69,34 @@ def test_score_pairs_mixed_sizes_match_oracle(ctx32, batch, group):
         ctx.set_option("pencil_group", 2)
 
 
+def test_score_pairs_shared_spectrum_two_pass_sizes(ctx32):
+    """One receptor against several ligands at 64^3 (the two-pass size whose
+    fused kernels take the spectrum in pair-grouped column order, copied once
+    per distinct spectrum), mixed with another 64^3 receptor and a 32^3 pair."""
+    ctx = ctx32
+    gf, _, rho_f, _, _ = rand_case(64, 8, False, 301)
+    spec = ctx.spectrum(rho_f, gf)
+    gf2, _, rho_f2, _, _ = rand_case(64, 8, False, 302)
+    spec2 = ctx.spectrum(rho_f2, gf2)
+    cases = []
+    for i, (fixed, nm, nrot) in enumerate([((gf, rho_f, spec), 20, 3), ((gf, rho_f, spec), 28, 2),
+                                           ((gf2, rho_f2, spec2), 16, 3), ((gf, rho_f, spec), 12, 1)]):
+        _, gm, _, rho_m, w = rand_case(64, nm, False, 310 + i)
+        cases.append((fixed, gm, rho_m, w, wr.uniform_quaternions(nrot, 320 + i)))
+    g32, gm32, rho32, rm32, w32 = rand_case(32, 14, False, 330)
+    cases.append(((g32, rho32, ctx.spectrum(rho32, g32)), gm32, rm32, w32, wr.uniform_quaternions(2, 331)))
+    jobs = [{"spec": f[2], "g_fixed": f[0], "rho_moving": rm, "w_moving": w, "g_moving": gm, "quats": q}
+            for f, gm, rm, w, q in cases]
+    flush_print("score_pairs shared spectrum", len(jobs), "jobs")
+    outs = ctx.score_pairs(jobs)
+    for (f, gm, rm, w, quats), out in zip(cases, outs):
+        c = oc.moving_coefficients(rm, w)
+        s = out["score"].cpu().numpy()
+        for r, q in enumerate(quats):
+            vol = oc.score_volume(f[1], c, q, gm.n[0], False)
+            assert abs(s[r] - vol.max()) <= 2e-5 * np.abs(vol).max()
+
+
 def test_score_pairs_rejects_a_bad_job(ctx32):
     from paper_1712_00238_amd._lib import SdfError
     gf, gm, rho_f, rho_m, w = rand_case(16, 6, False, 1)
