@@ -178,8 +178,9 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 // Slab layouts.  Generic sizes keep the interleaved complex N x N slab and
 // two N x N integer planes over the same bytes, with periodic wrap of the
 // stencil.  N = 64 and 128 use a padded row layout: row y holds the re plane
-// (N ints), the im plane (N ints) and 16 pad ints (unpadded rows put every
-// row on the same banks and double the scatter's conflict stalls).  The
+// (N ints), the im plane (N ints) and 24 pad ints, so consecutive rows start
+// 24 banks apart (unpadded rows put every row on the same banks and double
+// the scatter's conflict stalls).  The
 // complex row that replaces it after conversion has N + 8 entries, entry e
 // at e + e / 16, so that the radix-16 pass along x, which writes 16
 // consecutive entries per lane, does not put the 8 lanes of a row on the
@@ -191,7 +192,7 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 template <int N>
 struct SlabLayout {
     static constexpr bool kFast = N == 64 || N == 128;
-    static constexpr int kRowInts = kFast ? 2 * N + 16 : N;  // ints per accumulation row
+    static constexpr int kRowInts = kFast ? 2 * N + 24 : N;  // ints per accumulation row
     static constexpr int kImOff = kFast ? N : N * N;          // im plane offset (ints)
     static constexpr int kInts = kFast ? N * kRowInts : 2 * N * N;
     static constexpr int kRowCf = kRowInts / 2;                // complex stride after conversion (fast)
@@ -300,10 +301,12 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
     // (k_b1, k_b2) the samples y(ka) = y0 + ka d (d = column ax of the
     // reflected rotation) cross the slab support |z - y_z| < 2 for a short
     // run of ka; the next coefficient is fetched one step ahead.  Lines are
-    // taken in 16 x 16 blocks by four waves, each wave a stride-2 8 x 8
-    // sublattice (b1 most aligned with x): its samples sit at nearby heights,
-    // and the stride keeps two lanes from adding to the same LDS word in one
-    // instruction, which the LDS would serialise.
+    // taken in 16 x 16 blocks by four waves: a wave covers 8 rows of the
+    // block (b2) and every other line along b1 (the axis most aligned with
+    // x), offset by one on alternate rows.  Its samples sit at nearby
+    // heights; the stride keeps two lanes from adding to the same LDS word in
+    // one instruction, which the LDS would serialise, and the row offset
+    // spreads the lanes over odd and even banks.
     int ax = 0;
     float best = fabsf(Rp[6]);
     if (fabsf(Rp[7]) > best) { ax = 1; best = fabsf(Rp[7]); }
@@ -324,8 +327,9 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
         if (blocks16) {
             const int w = pidx >> 6, l = pidx & 63;
             const int blk = w >> 2, k = w & 3;
-            i1 = (blk % nb16) * 16 + 2 * (l & 7) + (k & 1);
-            i2 = (blk / nb16) * 16 + 2 * (l >> 3) + (k >> 1);
+            const int row = (l >> 3) + 8 * (k >> 1);  // 0 .. 15 within the block
+            i2 = (blk / nb16) * 16 + row;
+            i1 = (blk % nb16) * 16 + 2 * (l & 7) + ((row + k) & 1);
         } else {
             i1 = pidx % n_m;
             i2 = pidx / n_m;
