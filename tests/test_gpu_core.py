@@ -272,6 +272,50 @@ def test_score_grad_matches_oracle(ctxs, dtype, planar):
     assert np.allclose(to_np(s2), score, rtol=1e-6, atol=1e-6 * np.abs(score).max())
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_autograd_function_pose_and_weight_paths(ctxs, dtype):
+    """sdf_score through torch.autograd: with only the poses requiring a
+    gradient, forward computes the pose derivatives and backward scales them;
+    with the weights requiring one too, backward re-runs the kernel with the
+    incoming gradient.  Both against direct score_grad calls."""
+    import torch
+    from paper_1712_00238_amd.autograd import sdf_score
+    ctx = ctxs[dtype]
+    real = torch.float64 if dtype == "f64" else torch.float32
+    cplx = torch.complex128 if dtype == "f64" else torch.complex64
+    dev = torch.device("cuda")
+    gf, gm, rho_f, rho_m, w = small_case(16, 6, False, 77)
+    rng = np.random.default_rng(4)
+    B = 6
+    poses = np.concatenate([rng.uniform(0, 16, size=(B, 3)), wr.uniform_quaternions(B, 8)], axis=1)
+    rf = torch.as_tensor(rho_f, dtype=cplx, device=dev)
+    rm = torch.as_tensor(rho_m, dtype=cplx, device=dev)
+    g = torch.as_tensor(rng.normal(size=B), dtype=real, device=dev)
+    # poses only
+    p = torch.tensor(poses, dtype=torch.float64, device=dev, requires_grad=True)
+    wt = torch.as_tensor(w, dtype=real, device=dev)
+    s = sdf_score(p, wt, ctx, rf, gf, rm, gm)
+    (s * g).sum().backward()
+    s_ref, gp_ref, _ = ctx.score_grad(rf, gf, rm, wt, gm, poses, want_pose=True)
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    assert torch.allclose(s, s_ref, rtol=tol, atol=tol * float(s_ref.abs().max()))
+    gexp = gp_ref * g.double()[:, None]
+    assert torch.allclose(p.grad, gexp, rtol=1e-9, atol=1e-9 * float(gexp.abs().max()))
+    # poses and weights
+    p2 = torch.tensor(poses, dtype=torch.float64, device=dev, requires_grad=True)
+    w2 = torch.as_tensor(w, dtype=real, device=dev).clone().requires_grad_(True)
+    (sdf_score(p2, w2, ctx, rf, gf, rm, gm) * g).sum().backward()
+    _, gp2, gw2 = ctx.score_grad(rf, gf, rm, wt, gm, poses, want_pose=True, want_w=True, grad_scale=g.double())
+    assert torch.allclose(p2.grad, gp2 * g.double()[:, None], rtol=1e-9, atol=1e-9 * float(gexp.abs().max()))
+    assert torch.allclose(w2.grad, gw2, rtol=tol, atol=tol * float(gw2.abs().max()))
+    if dtype == "f64":
+        # central differences of the whole function, poses and weights
+        p3 = torch.tensor(poses[:2], dtype=torch.float64, device=dev, requires_grad=True)
+        w3 = torch.as_tensor(w, dtype=real, device=dev).clone().requires_grad_(True)
+        assert torch.autograd.gradcheck(lambda a, b: sdf_score(a, b, ctx, rf, gf, rm, gm), (p3, w3),
+                                        eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
 # ----------------------------------------------------------------------------- end to end, planar
 
 def test_peg_in_hole_end_to_end_f64(ctxs):
