@@ -1019,8 +1019,8 @@ int score_grad(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, cons
     const bool planar = g_fixed->n[2] == 1;
     const int N = g_fixed->n[0], nm = g_moving->n[0];
     const bool want_w = grad_w != nullptr;
-    size_t need = ctx->dtype == SDF_F64 ? sdf::grad_workspace_bytes<double>(B, nm, planar, want_w)
-                                        : sdf::grad_workspace_bytes<float>(B, nm, planar, want_w);
+    size_t need = ctx->dtype == SDF_F64 ? sdf::grad_workspace_bytes<double>(B, N, nm, planar, want_w)
+                                        : sdf::grad_workspace_bytes<float>(B, N, nm, planar, want_w);
     rc = ensure_ws(ctx, need);
     if (rc) return rc;
     hipError_t e;

@@ -1,17 +1,22 @@
 // Pose value and adjoint for gradient-based refinement of placements.
 //
 //   f(t, q) = Re sum_k c_k Phi(R x_k / h + t),  Phi(y) = sum_p rho_F(p) B3(p - y),
-//   df/dt   = Re sum_k c_k grad Phi(y_k),
-//   df/dR   = G = sum_k Re(c_k grad Phi(y_k)) (x_k / h)^T,  df/dq = G : dR/dq,
+//   df/dt   = Re sum_k c_k grad Phi(y_k)                      (g_k = Re c_k grad Phi(y_k)),
+//   df/dq   from the torque tau = sum_k (R x_k / h) x g_k:    for a unit quaternion u the
+//             rotated point moves by 2 vec(e_c u*) x (R x) + (radial part) along u_c,
+//             so df/du_c = 2 vec(e_c u*) . tau on the tangent space of |u| = 1,
 //   df/dw_k = sum_b s_b Re(rho_M(x_k) Phi_b(y_k)).
 //
-// Block (sample tile, pose tile): each thread owns a few body samples and
-// walks the poses of the tile, gathering the 4^3 stencil of rho_F around
-// each moved sample (the stencil weights are recomputed here, never stored).
-// Per pose the 13 sums (f, df/dt, G) are accumulated in FP64 and reduced
-// per block into partials; a second kernel reduces the partials per pose and
-// applies the quaternion chain rule in FP64.  Per-sample weight gradients
-// stay in registers across the pose tile and are written once per tile.
+// Block (sample tile, pose tile): threads own body samples and walk the poses
+// of the tile, gathering the 4^3 stencil of rho_F around each moved sample
+// (the stencil weights are recomputed here, never stored).  Per pose the 7
+// sums (f, df/dt, tau) are accumulated in FP64 and reduced per block into
+// partials; a second kernel reduces the partials per pose and applies the
+// quaternion chain rule in FP64.  Per-sample weight gradients stay in
+// registers across the pose tile and are written once per tile.
+#include <algorithm>
+#include <type_traits>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -23,7 +28,7 @@ constexpr int kGBlock = 256;
 constexpr int kSPT = 4;                        // samples per thread
 constexpr int kSamplesPerBlock = kGBlock * kSPT;
 constexpr int kPosesPerBlock = 16;
-constexpr int kNAcc = 13;  // f, dt[3], G[9]
+constexpr int kNAcc = 7;  // f, dt[3], tau[3]
 
 __device__ __forceinline__ void quat_rot(const double* q, double r[9]) {
     double w = q[0], x = q[1], y = q[2], z = q[3];
@@ -55,8 +60,8 @@ __global__ __launch_bounds__(kGBlock) void grad_tile_kernel(const cplx<T>* __res
                                                             const double* __restrict__ poses, int64_t B,
                                                             const double* __restrict__ gscale,
                                                             double* __restrict__ part, int nsb,
-                                                            T* __restrict__ wpart, int want_w) {
-    const int sb = blockIdx.x, pb = blockIdx.y;
+                                                            T* __restrict__ wpart, int want_w, int pb0) {
+    const int sb = blockIdx.x, pb = pb0 + int(blockIdx.y);
     const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
     const int nz = planar ? 1 : N;
     const T half = T(0.5) * T(n_m);
@@ -155,16 +160,15 @@ __global__ __launch_bounds__(kGBlock) void grad_tile_kernel(const cplx<T>* __res
                 acc[1] += g0;
                 acc[2] += g1;
                 acc[3] += g2;
-                const double x0 = double(xb[s][0]), x1 = double(xb[s][1]), x2 = double(xb[s][2]);
-                acc[4] += g0 * x0;
-                acc[5] += g0 * x1;
-                acc[6] += g0 * x2;
-                acc[7] += g1 * x0;
-                acc[8] += g1 * x1;
-                acc[9] += g1 * x2;
-                acc[10] += g2 * x0;
-                acc[11] += g2 * x1;
-                acc[12] += g2 * x2;
+                // rotated body position R x (without t) and torque (R x) x g
+                double wv[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    wv[a] = double(r[3 * a]) * double(xb[s][0]) + double(r[3 * a + 1]) * double(xb[s][1]) +
+                            double(r[3 * a + 2]) * double(xb[s][2]);
+                acc[4] += wv[1] * g2 - wv[2] * g1;
+                acc[5] += wv[2] * g0 - wv[0] * g2;
+                acc[6] += wv[0] * g1 - wv[1] * g0;
                 if (want_w) gw[s] += T(sc) * (rm[s] * phi).re;
             }
         }
@@ -189,6 +193,223 @@ __global__ __launch_bounds__(kGBlock) void grad_tile_kernel(const cplx<T>* __res
     }
 }
 
+// Sum of v over each row of 16 lanes, left in every lane of the row (DPP
+// quad permutations and row rotations; no LDS traffic).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double row16_sum(double v) {
+    v += dpp_f64<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x124>(v);  // row_ror 4
+    v += dpp_f64<0x128>(v);  // row_ror 8
+    return v;
+}
+
+// 3D FP32 variant with the fixed field staged in LDS.  Block (8 x 8 x 8
+// sample tile, pose tile), one sample per thread.  Per pose the block loads
+// into LDS the box of rho_F cells that the tile's 4^3 stencils can touch:
+// the tile's corners bound its moved positions (widened by 1e-3 cell, far
+// above the FP32 rounding of a moved position), so the stencil floors span at
+// most ceil(7 |row of R|_1) + 1 <= 14 values and the box is at most 17 cells
+// per axis.  The box has fixed pitches (17 cells per row, 300 per plane; the
+// plane pitch spreads the stencil gathers over the LDS banks), so the 64
+// stencil reads of a sample sit at constant offsets from one address.
+// Staging gives each wave three box rows per load instruction (51 lanes,
+// row and plane on the scalar unit) and issues all of a wave's loads before
+// its LDS stores.
+constexpr int kBoxTile = 8;
+constexpr int kBoxBlock = kBoxTile * kBoxTile * kBoxTile;
+constexpr int kBoxWaves = kBoxBlock / 64;
+constexpr int kBoxMax = 17;
+constexpr int kBoxRow = 17;
+constexpr int kBoxPlane = 300;
+constexpr int kBoxCells = kBoxPlane * kBoxMax;
+constexpr int kBoxSlotRows = 3;                                            // rows per wave load
+constexpr int kBoxSlots = kBoxMax * ((kBoxMax + kBoxSlotRows - 1) / kBoxSlotRows);
+constexpr int kBoxStage = (kBoxSlots + kBoxWaves - 1) / kBoxWaves;         // loads per lane
+constexpr int kBoxPoses = 16;
+constexpr float kBoxMargin = 1e-3f;
+static_assert(kBoxRow >= kBoxMax && kBoxPlane >= kBoxRow * kBoxMax, "box pitches");
+static_assert(kBoxRow * kBoxSlotRows <= 64, "staging rows per wave");
+
+template <bool GRAD>
+__global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float>* __restrict__ rho_f, int N,
+                                                                const cplx<float>* __restrict__ rho_m,
+                                                                const float* __restrict__ w_m, int n_m,
+                                                                const double* __restrict__ poses, int64_t B,
+                                                                const double* __restrict__ gscale,
+                                                                double* __restrict__ part, int nsb,
+                                                                float* __restrict__ wpart, int want_w, int pb0) {
+    __shared__ cplx<float> box[kBoxCells];
+    __shared__ double red[kBoxBlock / 16][kNAcc];
+    const int sb = blockIdx.x, pb = pb0 + int(blockIdx.y);
+    const int nt = (n_m + kBoxTile - 1) / kBoxTile;
+    const int t0x = (sb % nt) * kBoxTile, t0y = ((sb / nt) % nt) * kBoxTile, t0z = (sb / (nt * nt)) * kBoxTile;
+    const int64_t K = int64_t(n_m) * n_m * n_m;
+    const float half = 0.5f * float(n_m);
+    // this thread's sample
+    const int i = t0x + (threadIdx.x & 7), j = t0y + ((threadIdx.x >> 3) & 7), k = t0z + (threadIdx.x >> 6);
+    const bool ok = i < n_m && j < n_m && k < n_m;
+    const int64_t ks = ok ? (int64_t(k) * n_m + j) * n_m + i : 0;
+    const float xb0 = float(i) - half, xb1 = float(j) - half, xb2 = float(k) - half;
+    const cplx<float> rm = ok ? rho_m[ks] : mk(0.f, 0.f);
+    const cplx<float> ck = rm * (ok ? w_m[ks] : 0.f);
+    float gw = 0.f;
+    // body-coordinate range of the tile (clipped to the body box)
+    const float xlo[3] = {float(t0x) - half, float(t0y) - half, float(t0z) - half};
+    const float xhi[3] = {float(min(t0x + kBoxTile, n_m) - 1) - half, float(min(t0y + kBoxTile, n_m) - 1) - half,
+                          float(min(t0z + kBoxTile, n_m) - 1) - half};
+    const int lane = threadIdx.x & 63;
+    const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    // staging lane roles: row j_s of a slot of three rows, cell cx_s of the row
+    const int js = lane / kBoxRow, cxs = lane - js * kBoxRow;
+    const int64_t b0 = int64_t(pb) * kBoxPoses;
+    for (int pi = 0; pi < kBoxPoses; ++pi) {
+        const int64_t b = b0 + pi;
+        if (b >= B) break;  // uniform across the block
+        const double* pose = poses + 7 * b;
+        double r64[9];
+        quat_rot(pose + 3, r64);
+        float r[9];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) r[a] = float(r64[a]);
+        int tint[3], lo[3], ext[3];
+        float tfr[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double ti = floor(pose[a]);
+            tint[a] = int(ti);
+            tfr[a] = float(pose[a] - ti);
+            float ymin = tfr[a], ymax = tfr[a];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float u = r[3 * a + c] * xlo[c], v = r[3 * a + c] * xhi[c];
+                ymin += fminf(u, v);
+                ymax += fmaxf(u, v);
+            }
+            const int fmin = int(floorf(ymin - kBoxMargin));
+            lo[a] = __builtin_amdgcn_readfirstlane(fmin - 1 + tint[a]);
+            ext[a] = __builtin_amdgcn_readfirstlane(int(floorf(ymax + kBoxMargin)) - fmin + 4);
+        }
+        // stage the box
+        {
+            const int wx = wrap(lo[0], N), wy = __builtin_amdgcn_readfirstlane(wrap(lo[1], N)),
+                      wz = __builtin_amdgcn_readfirstlane(wrap(lo[2], N));
+            const int nts = (ext[1] + kBoxSlotRows - 1) / kBoxSlotRows, nslot = ext[2] * nts;
+            int gx = wx + cxs;
+            gx -= gx >= N ? N : 0;
+            const bool lane_ok = js < kBoxSlotRows && cxs < ext[0];
+            cplx<float> v[kBoxStage];
+#pragma unroll
+            for (int m = 0; m < kBoxStage; ++m) {
+                const int s = wid + m * kBoxWaves;
+                v[m] = mk(0.f, 0.f);
+                if (s < nslot) {
+                    const int cz = s / nts, cy = (s - cz * nts) * kBoxSlotRows + js;
+                    int gz = wz + cz;
+                    gz -= gz >= N ? N : 0;
+                    int gy = wy + cy;
+                    gy -= gy >= N ? N : 0;
+                    if (lane_ok && cy < ext[1]) v[m] = rho_f[(int64_t(gz) * N + gy) * N + gx];
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < kBoxStage; ++m) {
+                const int s = wid + m * kBoxWaves;
+                if (s < nslot) {
+                    const int cz = s / nts, cy = (s - cz * nts) * kBoxSlotRows + js;
+                    if (lane_ok && cy < ext[1]) box[cz * kBoxPlane + cy * kBoxRow + cxs] = v[m];
+                }
+            }
+        }
+        __syncthreads();
+        const double sc = gscale ? gscale[b] : 1.0;
+        double acc[kNAcc];
+#pragma unroll
+        for (int a = 0; a < kNAcc; ++a) acc[a] = 0.0;
+        if (ok) {
+            float wgt[3][4], dw[3][4], wv[3];
+            int lb[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                wv[a] = r[3 * a] * xb0 + r[3 * a + 1] * xb1 + r[3 * a + 2] * xb2;
+                const float y = tfr[a] + wv[a];
+                const float fl = floorf(y);
+                lb[a] = int(fl) + tint[a] - 1 - lo[a];  // in [0, ext - 4]
+                bspline3_weights(y - fl, wgt[a]);
+                if (GRAD) bspline3_dweights(y - fl, dw[a]);
+            }
+            const cplx<float>* base = box + lb[2] * kBoxPlane + lb[1] * kBoxRow + lb[0];
+            // separable contraction: x, then y, then z
+            cplx<float> phi = mk(0.f, 0.f), gx = phi, gy = phi, gz = phi;
+#pragma unroll 1
+            for (int cz = 0; cz < 4; ++cz) {
+                float wz = wgt[2][0], dz = GRAD ? dw[2][0] : 0.f;
+#pragma unroll
+                for (int q = 1; q < 4; ++q)
+                    if (cz == q) {
+                        wz = wgt[2][q];
+                        if (GRAD) dz = dw[2][q];
+                    }
+                const cplx<float>* plane = base + cz * kBoxPlane;
+                cplx<float> ay = mk(0.f, 0.f), by = ay, cy_ = ay;
+#pragma unroll
+                for (int cy = 0; cy < 4; ++cy) {
+                    cplx<float> rx = mk(0.f, 0.f), rdx = rx;
+#pragma unroll
+                    for (int cx = 0; cx < 4; ++cx) {
+                        const cplx<float> v = plane[cy * kBoxRow + cx];
+                        rx = rx + v * wgt[0][cx];
+                        if (GRAD) rdx = rdx + v * dw[0][cx];
+                    }
+                    ay = ay + rx * wgt[1][cy];
+                    if (GRAD) {
+                        by = by + rdx * wgt[1][cy];
+                        cy_ = cy_ + rx * dw[1][cy];
+                    }
+                }
+                phi = phi + ay * wz;
+                if (GRAD) {
+                    gx = gx + by * wz;
+                    gy = gy + cy_ * wz;
+                    gz = gz + ay * dz;
+                }
+            }
+            acc[0] = double((ck * phi).re);
+            if (GRAD) {
+                const double g0 = double((ck * gx).re), g1 = double((ck * gy).re), g2 = double((ck * gz).re);
+                const double w0 = double(wv[0]), w1 = double(wv[1]), w2 = double(wv[2]);
+                acc[1] = g0;
+                acc[2] = g1;
+                acc[3] = g2;
+                acc[4] = w1 * g2 - w2 * g1;
+                acc[5] = w2 * g0 - w0 * g2;
+                acc[6] = w0 * g1 - w1 * g0;
+                if (want_w) gw += float(sc) * (rm * phi).re;
+            }
+        }
+        // block reduction: rows of 16 lanes (DPP), then 32 row sums per value
+        const int nacc = GRAD ? kNAcc : 1;
+#pragma unroll
+        for (int a = 0; a < nacc; ++a) {
+            const double v = row16_sum(acc[a]);
+            if ((lane & 15) == 0) red[wid * 4 + (lane >> 4)][a] = v;
+        }
+        __syncthreads();  // also: every thread is done reading the box
+        if (threadIdx.x < nacc) {
+            double v = 0.0;
+#pragma unroll
+            for (int rw = 0; rw < kBoxBlock / 16; ++rw) v += red[rw][threadIdx.x];
+            part[(b * nsb + sb) * kNAcc + threadIdx.x] = v;
+        }
+    }
+    if (GRAD && want_w && ok) wpart[int64_t(pb) * K + ks] = gw;
+}
+
 // Per pose: reduce the sample-tile partials, apply the chain rule through
 // R(q / |q|) (FP64), write the score and the 7 pose derivatives.
 template <typename T, bool GRAD>
@@ -206,15 +427,13 @@ __global__ void grad_finish_kernel(const double* __restrict__ part, int nsb, con
     const double* q = poses + 7 * b + 3;
     const double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     const double w = q[0] / nq, x = q[1] / nq, y = q[2] / nq, z = q[3] / nq;
-    // dR_ab / du_c, u = q / |q|, c = (w, x, y, z)
-    const double d[9][4] = {{0, 0, -4 * y, -4 * z},          {-2 * z, 2 * y, 2 * x, -2 * w},
-                            {2 * y, 2 * z, 2 * w, 2 * x},    {2 * z, 2 * y, 2 * x, 2 * w},
-                            {0, -4 * x, 0, -4 * z},          {-2 * x, -2 * w, 2 * z, 2 * y},
-                            {-2 * y, 2 * z, -2 * w, 2 * x},  {2 * x, 2 * w, 2 * z, 2 * y},
-                            {0, -4 * x, -4 * y, 0}};
-    double gu[4] = {0, 0, 0, 0};
-    for (int ab = 0; ab < 9; ++ab)
-        for (int c = 0; c < 4; ++c) gu[c] += acc[4 + ab] * d[ab][c];
+    // df/du_c = 2 vec(e_c u*) . tau (plus a radial part that the projection
+    // below removes), u = (w, x, y, z):
+    //   vec(1 u*) = (-x, -y, -z), vec(i u*) = (w, z, -y),
+    //   vec(j u*) = (-z, w, x),   vec(k u*) = (y, -x, w)
+    const double om[4][3] = {{-x, -y, -z}, {w, z, -y}, {-z, w, x}, {y, -x, w}};
+    double gu[4];
+    for (int c = 0; c < 4; ++c) gu[c] = 2.0 * (om[c][0] * acc[4] + om[c][1] * acc[5] + om[c][2] * acc[6]);
     // d/dq = (I - u u^T) / |q| applied to d/du
     const double u[4] = {w, x, y, z};
     const double ug = u[0] * gu[0] + u[1] * gu[1] + u[2] * gu[2] + u[3] * gu[3];
@@ -236,11 +455,30 @@ __global__ void wsum_kernel(const T* __restrict__ wpart, int npb, int64_t K, T* 
 
 }  // namespace
 
+// the LDS-staged kernel serves 3D FP32 poses; FP64 and planar use the tile kernel
 template <typename T>
-size_t grad_workspace_bytes(int64_t B, int n_m, bool planar, bool want_w) {
+bool use_box(bool planar, int N) {
+    return std::is_same<T, float>::value && !planar && N >= kBoxMax;
+}
+
+template <typename T>
+void grad_tiles(int64_t B, int N, int n_m, bool planar, int64_t* nsb, int64_t* npb) {
     const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
-    const int64_t nsb = (K + kSamplesPerBlock - 1) / kSamplesPerBlock;
-    const int64_t npb = (B + kPosesPerBlock - 1) / kPosesPerBlock;
+    if (use_box<T>(planar, N)) {
+        const int64_t nt = (n_m + kBoxTile - 1) / kBoxTile;
+        *nsb = nt * nt * nt;
+        *npb = (B + kBoxPoses - 1) / kBoxPoses;
+    } else {
+        *nsb = (K + kSamplesPerBlock - 1) / kSamplesPerBlock;
+        *npb = (B + kPosesPerBlock - 1) / kPosesPerBlock;
+    }
+}
+
+template <typename T>
+size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, bool want_w) {
+    const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
+    int64_t nsb, npb;
+    grad_tiles<T>(B, N, n_m, planar, &nsb, &npb);
     size_t bytes = size_t(B * nsb * kNAcc) * sizeof(double);
     bytes = (bytes + 255) / 256 * 256;
     if (want_w) bytes += size_t(npb * K) * sizeof(T);
@@ -252,22 +490,39 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
                              const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w,
                              const double* grad_scale, void* ws, hipStream_t s) {
     const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
-    const int nsb = int((K + kSamplesPerBlock - 1) / kSamplesPerBlock);
-    const int npb = int((B + kPosesPerBlock - 1) / kPosesPerBlock);
+    int64_t nsb64, npb64;
+    grad_tiles<T>(B, N, n_m, planar, &nsb64, &npb64);
+    const int nsb = int(nsb64), npb = int(npb64);
     double* part = static_cast<double*>(ws);
     size_t off = size_t(B * nsb * kNAcc) * sizeof(double);
     off = (off + 255) / 256 * 256;
     T* wpart = reinterpret_cast<T*>(static_cast<char*>(ws) + off);
     const bool grad = grad_pose != nullptr || grad_w != nullptr;
-    const dim3 grid{unsigned(nsb), unsigned(npb), 1u};
     const auto* rf = static_cast<const cplx<T>*>(rho_f);
     const auto* rm = static_cast<const cplx<T>*>(rho_m);
-    if (grad)
-        hipLaunchKernelGGL((grad_tile_kernel<T, true>), grid, dim3(kGBlock), 0, s, rf, N, planar ? 1 : 0, rm, w_m, n_m,
-                           poses, B, grad_scale, part, nsb, wpart, grad_w ? 1 : 0);
-    else
-        hipLaunchKernelGGL((grad_tile_kernel<T, false>), grid, dim3(kGBlock), 0, s, rf, N, planar ? 1 : 0, rm, w_m,
-                           n_m, poses, B, grad_scale, part, nsb, wpart, 0);
+    const int ww = grad_w ? 1 : 0;
+    // pose tiles run in launches of at most 65535 along grid y
+    for (int pb0 = 0; pb0 < npb; pb0 += 65535) {
+        const dim3 grid{unsigned(nsb), unsigned(std::min(npb - pb0, 65535)), 1u};
+        if constexpr (std::is_same<T, float>::value) {
+            if (use_box<T>(planar, N)) {
+                if (grad)
+                    hipLaunchKernelGGL((grad_box_kernel<true>), grid, dim3(kBoxBlock), 0, s, rf, N, rm, w_m, n_m, poses,
+                                       B, grad_scale, part, nsb, wpart, ww, pb0);
+                else
+                    hipLaunchKernelGGL((grad_box_kernel<false>), grid, dim3(kBoxBlock), 0, s, rf, N, rm, w_m, n_m,
+                                       poses, B, grad_scale, part, nsb, wpart, 0, pb0);
+            }
+        }
+        if (!use_box<T>(planar, N)) {
+            if (grad)
+                hipLaunchKernelGGL((grad_tile_kernel<T, true>), grid, dim3(kGBlock), 0, s, rf, N, planar ? 1 : 0, rm,
+                                   w_m, n_m, poses, B, grad_scale, part, nsb, wpart, ww, pb0);
+            else
+                hipLaunchKernelGGL((grad_tile_kernel<T, false>), grid, dim3(kGBlock), 0, s, rf, N, planar ? 1 : 0, rm,
+                                   w_m, n_m, poses, B, grad_scale, part, nsb, wpart, 0, pb0);
+        }
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g2(unsigned((B + 127) / 128));
@@ -284,8 +539,8 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
     return e;
 }
 
-template size_t grad_workspace_bytes<float>(int64_t, int, bool, bool);
-template size_t grad_workspace_bytes<double>(int64_t, int, bool, bool);
+template size_t grad_workspace_bytes<float>(int64_t, int, int, bool, bool);
+template size_t grad_workspace_bytes<double>(int64_t, int, int, bool, bool);
 template hipError_t launch_score_grad<float>(const void*, int, bool, const void*, const float*, int, const double*,
                                              int64_t, float*, double*, float*, const double*, void*, hipStream_t);
 template hipError_t launch_score_grad<double>(const void*, int, bool, const void*, const double*, int, const double*,

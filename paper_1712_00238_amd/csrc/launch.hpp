@@ -134,7 +134,7 @@ size_t topk_workspace_bytes(int64_t n);
 
 // ---- score_grad
 template <typename T>
-size_t grad_workspace_bytes(int64_t B, int n_m, bool planar, bool want_w);
+size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, bool want_w);
 template <typename T>
 hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* rho_m, const T* w_m, int n_m,
                              const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w,
