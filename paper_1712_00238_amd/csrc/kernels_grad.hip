@@ -236,11 +236,53 @@ constexpr float kBoxMargin = 1e-3f;
 static_assert(kBoxRow >= kBoxMax && kBoxPlane >= kBoxRow * kBoxMax, "box pitches");
 static_assert(kBoxRow * kBoxSlotRows <= 64, "staging rows per wave");
 
+// Per-pose constants of the box kernel, computed once per pose: R in FP32,
+// t split into floor and fraction, and the offsets of the moved 8^3 tile's
+// bounding box from its moved corner, sum_c min(0, 7 R_ac) and
+// sum_c max(0, 7 R_ac).
+struct BoxPose {
+    float r[9];
+    float tfr[3];
+    int tint[3];
+    float dmin[3];
+    float dmax[3];
+    float pad[3];
+};
+static_assert(sizeof(BoxPose) == 96, "BoxPose layout");
+
+__global__ void box_pose_kernel(const double* __restrict__ poses, int64_t B, BoxPose* __restrict__ out) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double* pose = poses + 7 * b;
+    double r64[9];
+    quat_rot(pose + 3, r64);
+    BoxPose P;
+#pragma unroll
+    for (int a = 0; a < 9; ++a) P.r[a] = float(r64[a]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double ti = floor(pose[a]);
+        P.tint[a] = int(ti);
+        P.tfr[a] = float(pose[a] - ti);
+        float lo = 0.f, hi = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float e = float(kBoxTile - 1) * P.r[3 * a + c];
+            lo += fminf(e, 0.f);
+            hi += fmaxf(e, 0.f);
+        }
+        P.dmin[a] = lo;
+        P.dmax[a] = hi;
+        P.pad[a] = 0.f;
+    }
+    out[b] = P;
+}
+
 template <bool GRAD>
 __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float>* __restrict__ rho_f, int N,
                                                                 const cplx<float>* __restrict__ rho_m,
                                                                 const float* __restrict__ w_m, int n_m,
-                                                                const double* __restrict__ poses, int64_t B,
+                                                                const BoxPose* __restrict__ bpose, int64_t B,
                                                                 const double* __restrict__ gscale,
                                                                 double* __restrict__ part, int nsb,
                                                                 float* __restrict__ wpart, int want_w, int pb0) {
@@ -259,10 +301,9 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
     const cplx<float> rm = ok ? rho_m[ks] : mk(0.f, 0.f);
     const cplx<float> ck = rm * (ok ? w_m[ks] : 0.f);
     float gw = 0.f;
-    // body-coordinate range of the tile (clipped to the body box)
-    const float xlo[3] = {float(t0x) - half, float(t0y) - half, float(t0z) - half};
-    const float xhi[3] = {float(min(t0x + kBoxTile, n_m) - 1) - half, float(min(t0y + kBoxTile, n_m) - 1) - half,
-                          float(min(t0z + kBoxTile, n_m) - 1) - half};
+    // body coordinates of the tile corner (a clipped tile keeps the full
+    // tile's bounds, which contain its samples)
+    const float xlo0 = float(t0x) - half, xlo1 = float(t0y) - half, xlo2 = float(t0z) - half;
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     // staging lane roles: row j_s of a slot of three rows, cell cx_s of the row
@@ -271,37 +312,30 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
     for (int pi = 0; pi < kBoxPoses; ++pi) {
         const int64_t b = b0 + pi;
         if (b >= B) break;  // uniform across the block
-        const double* pose = poses + 7 * b;
-        double r64[9];
-        quat_rot(pose + 3, r64);
-        float r[9];
-#pragma unroll
-        for (int a = 0; a < 9; ++a) r[a] = float(r64[a]);
+        const BoxPose& P = bpose[b];
+        float r[9], tfr[3];
         int tint[3], lo[3], ext[3];
-        float tfr[3];
+#pragma unroll
+        for (int a = 0; a < 9; ++a) r[a] = P.r[a];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const double ti = floor(pose[a]);
-            tint[a] = int(ti);
-            tfr[a] = float(pose[a] - ti);
-            float ymin = tfr[a], ymax = tfr[a];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float u = r[3 * a + c] * xlo[c], v = r[3 * a + c] * xhi[c];
-                ymin += fminf(u, v);
-                ymax += fmaxf(u, v);
-            }
-            const int fmin = int(floorf(ymin - kBoxMargin));
+            tint[a] = P.tint[a];
+            tfr[a] = P.tfr[a];
+            const float y0 = tfr[a] + r[3 * a] * xlo0 + r[3 * a + 1] * xlo1 + r[3 * a + 2] * xlo2;
+            const int fmin = int(floorf(y0 + P.dmin[a] - kBoxMargin));
             lo[a] = __builtin_amdgcn_readfirstlane(fmin - 1 + tint[a]);
-            ext[a] = __builtin_amdgcn_readfirstlane(int(floorf(ymax + kBoxMargin)) - fmin + 4);
+            ext[a] = __builtin_amdgcn_readfirstlane(int(floorf(y0 + P.dmax[a] + kBoxMargin)) - fmin + 4);
         }
-        // stage the box
+        // stage the box: slot s holds rows 3 q .. 3 q + 2 of plane cz, with
+        // s = cz nts + q; lane = 17 j + cx covers row 3 q + j, cell cx
         {
-            const int wx = wrap(lo[0], N), wy = __builtin_amdgcn_readfirstlane(wrap(lo[1], N)),
-                      wz = __builtin_amdgcn_readfirstlane(wrap(lo[2], N));
+            const unsigned Nu = unsigned(N);
+            const unsigned wx = unsigned(wrap(lo[0], N)), wy = __builtin_amdgcn_readfirstlane(wrap(lo[1], N)),
+                           wz = __builtin_amdgcn_readfirstlane(wrap(lo[2], N));
             const int nts = (ext[1] + kBoxSlotRows - 1) / kBoxSlotRows, nslot = ext[2] * nts;
-            int gx = wx + cxs;
-            gx -= gx >= N ? N : 0;
+            const unsigned inv = 65535u / unsigned(nts) + 1u;  // s / nts = (s inv) >> 16 for s < 2^16 / nts
+            unsigned gx = wx + unsigned(cxs);
+            gx = min(gx, gx - Nu);
             const bool lane_ok = js < kBoxSlotRows && cxs < ext[0];
             cplx<float> v[kBoxStage];
 #pragma unroll
@@ -309,20 +343,22 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
                 const int s = wid + m * kBoxWaves;
                 v[m] = mk(0.f, 0.f);
                 if (s < nslot) {
-                    const int cz = s / nts, cy = (s - cz * nts) * kBoxSlotRows + js;
-                    int gz = wz + cz;
-                    gz -= gz >= N ? N : 0;
-                    int gy = wy + cy;
-                    gy -= gy >= N ? N : 0;
-                    if (lane_ok && cy < ext[1]) v[m] = rho_f[(int64_t(gz) * N + gy) * N + gx];
+                    const int cz = int((unsigned(s) * inv) >> 16), q = s - cz * nts;
+                    const int cy = q * kBoxSlotRows + js;
+                    unsigned gz = wz + unsigned(cz);
+                    gz = min(gz, gz - Nu);
+                    unsigned gy = wy + unsigned(cy);
+                    gy = min(gy, gy - Nu);
+                    if (lane_ok && cy < ext[1]) v[m] = rho_f[gz * Nu * Nu + __umul24(gy, Nu) + gx];
                 }
             }
 #pragma unroll
             for (int m = 0; m < kBoxStage; ++m) {
                 const int s = wid + m * kBoxWaves;
                 if (s < nslot) {
-                    const int cz = s / nts, cy = (s - cz * nts) * kBoxSlotRows + js;
-                    if (lane_ok && cy < ext[1]) box[cz * kBoxPlane + cy * kBoxRow + cxs] = v[m];
+                    const int cz = int((unsigned(s) * inv) >> 16), q = s - cz * nts;
+                    if (lane_ok && q * kBoxSlotRows + js < ext[1])
+                        box[cz * kBoxPlane + q * (kBoxSlotRows * kBoxRow) + lane] = v[m];
                 }
             }
         }
@@ -458,7 +494,7 @@ __global__ void wsum_kernel(const T* __restrict__ wpart, int npb, int64_t K, T* 
 // the LDS-staged kernel serves 3D FP32 poses; FP64 and planar use the tile kernel
 template <typename T>
 bool use_box(bool planar, int N) {
-    return std::is_same<T, float>::value && !planar && N >= kBoxMax;
+    return std::is_same<T, float>::value && !planar && N >= kBoxMax && N <= 1024;
 }
 
 template <typename T>
@@ -481,7 +517,8 @@ size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, bool want_w)
     grad_tiles<T>(B, N, n_m, planar, &nsb, &npb);
     size_t bytes = size_t(B * nsb * kNAcc) * sizeof(double);
     bytes = (bytes + 255) / 256 * 256;
-    if (want_w) bytes += size_t(npb * K) * sizeof(T);
+    if (want_w) bytes += (size_t(npb * K) * sizeof(T) + 255) / 256 * 256;
+    if (use_box<T>(planar, N)) bytes += size_t(B) * sizeof(BoxPose);
     return bytes + 256;
 }
 
@@ -497,6 +534,13 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
     size_t off = size_t(B * nsb * kNAcc) * sizeof(double);
     off = (off + 255) / 256 * 256;
     T* wpart = reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+    if (grad_w) off += (size_t(npb64 * K) * sizeof(T) + 255) / 256 * 256;
+    BoxPose* bpose = reinterpret_cast<BoxPose*>(static_cast<char*>(ws) + off);
+    if (use_box<T>(planar, N)) {
+        hipLaunchKernelGGL(box_pose_kernel, dim3(unsigned((B + 127) / 128)), dim3(128), 0, s, poses, B, bpose);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     const bool grad = grad_pose != nullptr || grad_w != nullptr;
     const auto* rf = static_cast<const cplx<T>*>(rho_f);
     const auto* rm = static_cast<const cplx<T>*>(rho_m);
@@ -507,11 +551,11 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
         if constexpr (std::is_same<T, float>::value) {
             if (use_box<T>(planar, N)) {
                 if (grad)
-                    hipLaunchKernelGGL((grad_box_kernel<true>), grid, dim3(kBoxBlock), 0, s, rf, N, rm, w_m, n_m, poses,
+                    hipLaunchKernelGGL((grad_box_kernel<true>), grid, dim3(kBoxBlock), 0, s, rf, N, rm, w_m, n_m, bpose,
                                        B, grad_scale, part, nsb, wpart, ww, pb0);
                 else
                     hipLaunchKernelGGL((grad_box_kernel<false>), grid, dim3(kBoxBlock), 0, s, rf, N, rm, w_m, n_m,
-                                       poses, B, grad_scale, part, nsb, wpart, 0, pb0);
+                                       bpose, B, grad_scale, part, nsb, wpart, 0, pb0);
             }
         }
         if (!use_box<T>(planar, N)) {
