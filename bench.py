@@ -421,8 +421,12 @@ def main():
         if args.protein_rotations:
             pp = C.protein_like(seed=0, n_rot=args.protein_rotations)
             pf, pm = pp.fixed, pp.moving
+            b0, b1, b2 = ev(), ev(), ev()
+            b0.record(stream)
             rf = ctx.sdf_build(pf.samples.q, pf.samples.n, pf.samples.w, pf.grid, pp.params)
+            b1.record(stream)
             rm = ctx.sdf_build(pm.samples.q, pm.samples.n, pm.samples.w, pm.grid, pp.params)
+            b2.record(stream)
             psp = ctx.spectrum(rf, pf.grid)
             pw = torch.ones(rm.shape, dtype=torch.float32, device=dev)
             ctx.set_option("batch", 64)
@@ -433,9 +437,12 @@ def main():
                 pout = ctx.score_rotations(psp, pf.grid, rm, pw, pm.grid, pp.quats, out=pout)
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t0) / 3
+            build_ms = [b0.elapsed_time(b1), b1.elapsed_time(b2)]
             report["protein_like"] = {"rotations": len(pp.quats), "batch": 64, "graph": bool(args.graph),
                                       "rotations_per_s": round(len(pp.quats) / dt, 1),
-                                      "samples": [pf.samples.count, pm.samples.count]}
+                                      "samples": [pf.samples.count, pm.samples.count],
+                                      "sdf_build_ms": [round(x, 2) for x in build_ms],
+                                      "end_to_end_ms": round(sum(build_ms) + 1e3 * dt, 2)}
             ctx.set_option("batch", args.batch)
             del rf, rm, psp, pw, pout
 

@@ -35,19 +35,30 @@ struct __align__(4 * sizeof(T)) v4 {
     T x, y, z, w;
 };
 
+// FP32 uses the hardware approximations directly (about 1 ulp each):
+// v_rsq_f32 (live pairs have d^2 >= xi_floor^2, far from denormals),
+// v_exp_f32 on a base-2 argument of magnitude below about 7, and v_rcp_f32.
+// FP64 uses the correctly rounded library functions.
 template <typename T>
 __device__ __forceinline__ T fast_rsqrt(T x);
 template <>
-__device__ __forceinline__ float fast_rsqrt<float>(float x) { return rsqrtf(x); }
+__device__ __forceinline__ float fast_rsqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <>
 __device__ __forceinline__ double fast_rsqrt<double>(double x) { return rsqrt(x); }
 
 template <typename T>
-__device__ __forceinline__ T dev_exp(T x);
+__device__ __forceinline__ T dev_exp2(T x);
 template <>
-__device__ __forceinline__ float dev_exp<float>(float x) { return expf(x); }
+__device__ __forceinline__ float dev_exp2<float>(float x) { return __builtin_amdgcn_exp2f(x); }
 template <>
-__device__ __forceinline__ double dev_exp<double>(double x) { return exp(x); }
+__device__ __forceinline__ double dev_exp2<double>(double x) { return exp2(x); }
+
+template <typename T>
+__device__ __forceinline__ T dev_rcp(T x);
+template <>
+__device__ __forceinline__ float dev_rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double dev_rcp<double>(double x) { return 1.0 / x; }
 
 // brick of nodes handled by one block
 struct Brick {
@@ -109,7 +120,8 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
     const T r2lo = T(r2max64 * (1.0 - 1e-4)), r2hi = T(r2max64 * (1.0 + 1e-4));
     const T xi_abs = T(xi_abs64);
     const T inv_xi = T(1.0 / xi_abs64);
-    const T inv2s2 = T(0.5 / (prm.sigma * prm.sigma));
+    // exp(-x^2 / (2 sigma^2)) = 2^(-x^2 log2(e) / (2 sigma^2))
+    const T inv2s2 = T(0.5 * 1.4426950408889634 / (prm.sigma * prm.sigma));
     const T im_sign = pmc > 0 ? T(-2) : T(2);  // P = (1 - r^2) -+ 2 i r
     const T prx = T(rx), pry = T(ry), prz = T(rz);
     T acc_re = T(0), acc_im = T(0);
@@ -143,10 +155,10 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                     const T r = eta * inv_xi;
                     const T cos_t = (dx * nv.x + dy * nv.y + dz * nv.z) * inv_eta;
                     const T x = r - T(1);
-                    const T G = dev_exp(-x * x * inv2s2);
+                    const T G = dev_exp2(-x * x * inv2s2);
                     const T rr = r * r;
                     const T den = T(1) + rr;
-                    const T coef = s.w * cos_t * G / (den * den);
+                    const T coef = s.w * cos_t * G * dev_rcp(den * den);
                     acc_re += coef * (T(1) - rr);
                     acc_im += coef * (im_sign * r);
                 }
