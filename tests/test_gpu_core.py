@@ -272,6 +272,42 @@ def test_score_grad_matches_oracle(ctxs, dtype, planar):
     assert np.allclose(to_np(s2), score, rtol=1e-6, atol=1e-6 * np.abs(score).max())
 
 
+@pytest.mark.parametrize("n,nm,B", [(32, 13, 37), (24, 16, 16), (17, 8, 5)])
+def test_score_grad_lds_box_kernel(ctxs, n, nm, B):
+    """3D FP32 poses on grids of N >= 17 run the kernel that stages a box of
+    rho_F per 8^3 sample tile in LDS.  Clipped tiles (N_M = 13), full tiles,
+    the smallest grid it serves, a pose count ragged against its 16-pose tile,
+    translations outside [0, N) so that boxes wrap around the periodic grid,
+    and both the pose and the weight gradients, against the oracle."""
+    ctx = ctxs["f32"]
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, False, 90 + n)
+    rng = np.random.default_rng(n + nm)
+    t = rng.uniform(-n, 2 * n, size=(B, 3))
+    q = wr.uniform_quaternions(B, 31 + nm) * rng.uniform(0.6, 1.4, size=(B, 1))
+    q[0] = [1.0, 0.0, 0.0, 0.0]  # identity: the box spans exactly the tile
+    q[1 % B] = [0.5, 0.5, 0.5, 0.5]  # a rotation with |row of R|_1 = 1
+    poses = np.concatenate([t, q], axis=1)
+    gs = rng.normal(size=B)
+    flush_print("score_grad box", n, nm, B)
+    score, gp, gw = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=True, want_w=True, grad_scale=gs)
+    score, gp, gw = to_np(score), to_np(gp), to_np(gw).reshape(-1)
+    c = oc.moving_coefficients(rho_m, w)
+    xb = osp.body_positions(nm, False)
+    gw_ref = np.zeros(len(xb))
+    for b in range(B):
+        f, dt, dq, dw = og.pose_value_and_grad(rho_f, c, rho_m, xb, poses[b, :3], poses[b, 3:])
+        g_ref = np.concatenate([dt, dq])
+        assert abs(score[b] - f) <= 2e-4 * max(1.0, abs(f)), (b, score[b], f)
+        assert np.max(np.abs(gp[b] - g_ref)) <= 2e-4 * max(1.0, np.max(np.abs(g_ref))), (b, gp[b], g_ref)
+        gw_ref += gs[b] * dw
+    assert np.max(np.abs(gw - gw_ref)) <= 2e-4 * max(1.0, np.max(np.abs(gw_ref)))
+    s2, _, _ = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=False)
+    assert np.allclose(to_np(s2), score, rtol=1e-6, atol=1e-6 * np.abs(score).max())
+    # pose derivatives alone (no weight gradient) match the combined call
+    _, gp3, _ = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=True)
+    assert np.allclose(to_np(gp3), gp, rtol=1e-6, atol=1e-6 * np.abs(gp).max())
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_autograd_function_pose_and_weight_paths(ctxs, dtype):
     """sdf_score through torch.autograd: with only the poses requiring a
