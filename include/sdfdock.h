@@ -149,7 +149,10 @@ int sdf_ctx_stats_reset(sdf_ctx ctx);
  * contact-ball test of samples within 1e-4 of its radius) are taken in FP64;
  * the kernel sum runs in the context's precision.  rho_out: complex,
  * g->n[0]*n[1]*n[2].  g, p: host structs.  Any grid shape is accepted.
- * Errors: SDF_EINVAL (null pointer, n <= 0, bad grid, invalid params). */
+ * The samples are put in Morton order in the context's workspace (about
+ * 70 bytes per sample), which the next call of any entry point may reuse.
+ * Errors: SDF_EINVAL (null pointer, n <= 0 or n > 2^30, bad grid, invalid
+ * params), SDF_ENOMEM (workspace). */
 int sdf_build(sdf_ctx ctx, const void *q, const void *nrm, const void *w, int64_t n,
               const sdf_grid *g, const sdf_params *p, void *rho_out, sdf_stream stream);
 

@@ -807,6 +807,7 @@ int sdf_build(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_
               const sdf_params* p, void* rho_out, sdf_stream stream) {
     if (!q || !nrm || !w || !rho_out) return fail(ctx, SDF_EINVAL, "NULL array");
     if (n <= 0) return fail(ctx, SDF_EINVAL, "sample count must be > 0");
+    if (n > (int64_t(1) << 30)) return fail(ctx, SDF_EINVAL, "sample count must be <= 2^30");
     int rc = check_grid(ctx, g, "grid");
     if (rc) return rc;
     rc = check_params(ctx, p);
@@ -819,8 +820,12 @@ int sdf_build(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_
     const double* qd = static_cast<const double*>(q);
     const double* nd = static_cast<const double*>(nrm);
     const double* wd = static_cast<const double*>(w);
-    hipError_t e = ctx->dtype == SDF_F64 ? sdf::launch_sdf_build<double>(qd, nd, wd, n, desc(g), pd, rho_out, s)
-                                         : sdf::launch_sdf_build<float>(qd, nd, wd, n, desc(g), pd, rho_out, s);
+    ctx->fused_cache_valid = false;  // the Morton-ordered samples share the workspace
+    rc = ensure_ws(ctx, sdf::sdf_build_workspace_bytes(n));
+    if (rc) return rc;
+    hipError_t e = ctx->dtype == SDF_F64
+                       ? sdf::launch_sdf_build<double>(qd, nd, wd, n, desc(g), pd, rho_out, ctx->ws, s)
+                       : sdf::launch_sdf_build<float>(qd, nd, wd, n, desc(g), pd, rho_out, ctx->ws, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "sdf_build");
     return SDF_OK;
 }

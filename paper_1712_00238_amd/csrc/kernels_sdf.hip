@@ -2,24 +2,37 @@
 //
 // One thread per grid node; a block covers a compact 8 x 8 x 4 brick of
 // nodes (16 x 16 in the plane) so that positions relative to the brick's
-// corner are small.  Boundary samples stream through LDS in tiles that every
-// thread reads by broadcast.
+// corner are small.  Boundary samples stream through LDS in tiles of 256
+// that every thread reads by broadcast.
 //
-// Pass 1 finds the nearest sample, its membership sign and the distance
-// floor test.  These are discrete decisions, taken in FP64 from FP64 sample
-// positions in both precisions, so the classification of every node is the
-// one an FP64 evaluation makes.
+// The samples are first put in Morton order (a stable radix sort of their
+// quantised positions), so a tile of 256 consecutive samples covers a
+// compact patch of the boundary, and every tile gets an FP64 bounding box.
+// A brick then visits only the tiles that can matter to it:
+//   pass 1: tiles whose box lies within U of the brick, where U is the least,
+//           over all tiles, of the largest brick-to-tile-box distance (every
+//           node of the brick has a sample within U);
+//   pass 2: tiles whose box lies within (1 + eps) max xi_abs of the brick.
+// Both bounds are conservative, so the nodes see exactly the samples they
+// would see in a scan of all samples.
+//
+// Pass 1 finds the nearest sample (lowest original index on exact ties),
+// its membership sign and the distance floor test.  These are discrete
+// decisions, taken in FP64 from FP64 sample positions in both precisions,
+// so the classification of every node is the one an FP64 evaluation makes.
 //
 // Pass 2 sums the kernel over the samples inside the eps-approximate contact
-// ball, in the context's precision T, on brick-relative coordinates.  A
-// sample whose squared distance lies within 1e-4 (relative) of the ball's
-// squared radius is re-tested in FP64.
+// ball, in the context's precision T, on brick-relative coordinates, in
+// Morton order.  A sample whose squared distance lies within 1e-4 (relative)
+// of the ball's squared radius is re-tested in FP64.
 //
 // With r = eta / |xi| the kernel of eq. 15 on zeta = xi + i eta reduces to
 //   phi = lambda / (2 pi sigma xi^2) * G(r) * P(r) / (1 + r^2)^2,
 //   G = exp(-(r - 1)^2 / (2 sigma^2)),  P = (1 - i r)^2 outside, (1 + i r)^2 inside,
 // so a pair costs one reciprocal square root, one exponential and one
 // reciprocal, with no trigonometric calls.
+#include <hipcub/hipcub.hpp>
+
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -66,14 +79,60 @@ struct Brick {
 };
 __host__ __device__ inline Brick brick_shape(int nz) { return nz == 1 ? Brick{16, 16, 1} : Brick{8, 8, 4}; }
 
+// Samples in Morton order with per-tile bounding boxes.
+struct SampleTiles {
+    const double* qs;   // positions, n x 3
+    const double* wn;   // w_j n_j, n x 3
+    const int* js;      // original index of each sample
+    const double* box;  // per tile of kSdfTile samples: lo x, y, z, hi x, y, z
+    int64_t ntile;
+};
+
+__device__ __forceinline__ double box_dmin2(const double bl[3], const double bh[3], const double* __restrict__ t) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double d = fmax(0.0, fmax(t[a] - bh[a], bl[a] - t[3 + a]));
+        s += d * d;
+    }
+    return s;
+}
+__device__ __forceinline__ double box_dmax2(const double bl[3], const double bh[3], const double* __restrict__ t) {
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double d = fmax(fabs(t[3 + a] - bl[a]), fabs(bh[a] - t[a]));
+        s += d * d;
+    }
+    return s;
+}
+
+template <bool MAX>
+__device__ __forceinline__ double block_reduce(double v, double* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off);
+        v = MAX ? fmax(v, o) : fmin(v, o);
+    }
+    __syncthreads();  // red is free
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    v = red[0];
+#pragma unroll
+    for (int wv = 1; wv < kSdfBlock / 64; ++wv) v = MAX ? fmax(v, red[wv]) : fmin(v, red[wv]);
+    return v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __restrict__ q,
-                                                              const double* __restrict__ nrm,
-                                                              const double* __restrict__ w, int64_t ns, GridDesc g,
-                                                              ParamDesc prm, cplx<T>* __restrict__ out) {
+                                                              const double* __restrict__ nrm, SampleTiles st,
+                                                              int64_t ns, GridDesc g, ParamDesc prm,
+                                                              cplx<T>* __restrict__ out) {
     __shared__ v4<double> sq[2 * kSdfTile];  // pass 1: (qx, qy, qz, -); pass 2: reused as two T tiles
-    v4<T>* sq2 = reinterpret_cast<v4<T>*>(sq);             // (qx, qy, qz, w) relative to the brick
-    v4<T>* sn2 = reinterpret_cast<v4<T>*>(sq) + kSdfTile;  // (nx, ny, nz, 0)
+    __shared__ int sidx[kSdfTile];           // pass 1: original index; pass 2: Morton index
+    __shared__ int tflag[kSdfBlock];         // tiles of the current chunk that the brick visits
+    __shared__ double red[kSdfBlock / 64];
+    v4<T>* sq2 = reinterpret_cast<v4<T>*>(sq);             // (qx, qy, qz, -) relative to the brick
+    v4<T>* sn2 = reinterpret_cast<v4<T>*>(sq) + kSdfTile;  // w (nx, ny, nz), -
 
     const Brick br = brick_shape(g.nz);
     const int nbx = (g.nx + br.bx - 1) / br.bx, nby = (g.ny + br.by - 1) / br.by;
@@ -86,81 +145,113 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
     const double cx = g.ox + g.h * i0, cy = g.oy + g.h * j0, cz = g.oz + g.h * k0;
     const double rx = g.h * li, ry = g.h * lj, rz = g.h * lk;
     const double px = cx + rx, py = cy + ry, pz = cz + rz;
+    // box of the brick's nodes inside the grid
+    const double bl[3] = {cx, cy, cz};
+    const double bh[3] = {cx + g.h * (min(br.bx, g.nx - i0) - 1), cy + g.h * (min(br.by, g.ny - j0) - 1),
+                          cz + g.h * (min(br.bz, g.nz - k0) - 1)};
 
-    // ---- pass 1 (FP64): nearest sample, lowest index on exact ties
+    // ---- pass 1 (FP64): nearest sample, lowest original index on exact ties
+    double u2 = INFINITY;
+    for (int64_t t = threadIdx.x; t < st.ntile; t += kSdfBlock) u2 = fmin(u2, box_dmax2(bl, bh, st.box + 6 * t));
+    u2 = block_reduce<false>(u2, red) * (1.0 + 1e-9);
     double best = INFINITY;
-    int64_t jbest = 0;
-    for (int64_t t0 = 0; t0 < ns; t0 += kSdfTile) {
-        const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+    int jbest = 0;
+    for (int64_t c0 = 0; c0 < st.ntile; c0 += kSdfBlock) {
+        const int64_t tc = c0 + threadIdx.x;
+        __syncthreads();  // the previous chunk is done with tflag, sq and sidx
+        tflag[threadIdx.x] = tc < st.ntile && box_dmin2(bl, bh, st.box + 6 * tc) <= u2;
         __syncthreads();
-        for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
-            const int64_t s = t0 + a;
-            sq[a] = v4<double>{q[3 * s], q[3 * s + 1], q[3 * s + 2], 0.0};
-        }
-        __syncthreads();
+        const int nchunk = int(st.ntile - c0 < kSdfBlock ? st.ntile - c0 : kSdfBlock);
+        for (int kk = 0; kk < nchunk; ++kk) {
+            if (!tflag[kk]) continue;  // uniform across the block
+            const int64_t t0 = (c0 + kk) * kSdfTile;
+            const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+            __syncthreads();
+            for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
+                const int64_t s = t0 + a;
+                sq[a] = v4<double>{st.qs[3 * s], st.qs[3 * s + 1], st.qs[3 * s + 2], 0.0};
+                sidx[a] = st.js[s];
+            }
+            __syncthreads();
 #pragma unroll 4
-        for (int a = 0; a < cnt; ++a) {
-            const v4<double> s = sq[a];
-            const double dx = px - s.x, dy = py - s.y, dz = pz - s.z;
-            const double d2 = dx * dx + dy * dy + dz * dz;
-            if (d2 < best) {
-                best = d2;
-                jbest = t0 + a;
+            for (int a = 0; a < cnt; ++a) {
+                const v4<double> s = sq[a];
+                const double dx = px - s.x, dy = py - s.y, dz = pz - s.z;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                const int jj = sidx[a];
+                if (d2 < best || (d2 == best && jj < jbest)) {
+                    best = d2;
+                    jbest = jj;
+                }
             }
         }
     }
-    const double dot = (px - q[3 * jbest]) * nrm[3 * jbest] + (py - q[3 * jbest + 1]) * nrm[3 * jbest + 1] +
-                       (pz - q[3 * jbest + 2]) * nrm[3 * jbest + 2];
+    const int64_t jb = jbest;
+    const double dot = (px - q[3 * jb]) * nrm[3 * jb] + (py - q[3 * jb + 1]) * nrm[3 * jb + 1] +
+                       (pz - q[3 * jb + 2]) * nrm[3 * jb + 2];
     const int pmc = dot > 0.0 ? 1 : (dot < 0.0 ? -1 : 0);
     const double xi_abs64 = sqrt(best);
     const bool live = valid && pmc != 0 && xi_abs64 >= prm.xi_floor;
 
     // ---- pass 2 (T): truncated kernel sum over the contact ball
     const double r2max64 = (1.0 + prm.eps) * (1.0 + prm.eps) * best;
+    const double r2brick = block_reduce<true>(live ? r2max64 : -1.0, red) * (1.0 + 1e-9);
     const T r2lo = T(r2max64 * (1.0 - 1e-4)), r2hi = T(r2max64 * (1.0 + 1e-4));
-    const T xi_abs = T(xi_abs64);
     const T inv_xi = T(1.0 / xi_abs64);
-    // exp(-x^2 / (2 sigma^2)) = 2^(-x^2 log2(e) / (2 sigma^2))
-    const T inv2s2 = T(0.5 * 1.4426950408889634 / (prm.sigma * prm.sigma));
-    const T im_sign = pmc > 0 ? T(-2) : T(2);  // P = (1 - r^2) -+ 2 i r
+    // exp(-(r - 1)^2 / (2 sigma^2)) = 2^(-u^2) with u = (r - 1) gs,
+    // gs = sqrt(log2(e) / 2) / sigma, and u = eta (gs / xi) - gs
+    const double gs64 = std::sqrt(0.5 * 1.4426950408889634) / prm.sigma;
+    const T gs = T(gs64), inv_xi_gs = T(gs64 / xi_abs64);
+    const T im_sign = pmc > 0 ? T(-2) : T(2);  // P = (1 - r^2) -+ 2 i r, applied once per node
     const T prx = T(rx), pry = T(ry), prz = T(rz);
     T acc_re = T(0), acc_im = T(0);
-    (void)xi_abs;
-    // a block whose nodes are all dead still runs the loop for its barriers
-    for (int64_t t0 = 0; t0 < ns; t0 += kSdfTile) {
-        const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
-        __syncthreads();
-        for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
-            const int64_t s = t0 + a;
-            sq2[a] = v4<T>{T(q[3 * s] - cx), T(q[3 * s + 1] - cy), T(q[3 * s + 2] - cz), T(w[s])};
-            sn2[a] = v4<T>{T(nrm[3 * s]), T(nrm[3 * s + 1]), T(nrm[3 * s + 2]), T(0)};
-        }
-        __syncthreads();
-        if (live) {
-#pragma unroll 4
-            for (int a = 0; a < cnt; ++a) {
-                const v4<T> s = sq2[a];
-                const T dx = prx - s.x, dy = pry - s.y, dz = prz - s.z;
-                const T d2 = dx * dx + dy * dy + dz * dz;
-                bool in = d2 <= r2lo;
-                if (!in && d2 <= r2hi) {  // near the sphere: decide in FP64
-                    const int64_t sj = t0 + a;
-                    const double ex = px - q[3 * sj], ey = py - q[3 * sj + 1], ez = pz - q[3 * sj + 2];
-                    in = ex * ex + ey * ey + ez * ez <= r2max64;
+    if (r2brick >= 0.0) {  // uniform: some node of the brick is live
+        for (int64_t c0 = 0; c0 < st.ntile; c0 += kSdfBlock) {
+            const int64_t tc = c0 + threadIdx.x;
+            __syncthreads();
+            tflag[threadIdx.x] = tc < st.ntile && box_dmin2(bl, bh, st.box + 6 * tc) <= r2brick;
+            __syncthreads();
+            const int nchunk = int(st.ntile - c0 < kSdfBlock ? st.ntile - c0 : kSdfBlock);
+            for (int kk = 0; kk < nchunk; ++kk) {
+                if (!tflag[kk]) continue;  // uniform across the block
+                const int64_t t0 = (c0 + kk) * kSdfTile;
+                const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+                __syncthreads();
+                for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
+                    const int64_t s = t0 + a;
+                    sq2[a] = v4<T>{T(st.qs[3 * s] - cx), T(st.qs[3 * s + 1] - cy), T(st.qs[3 * s + 2] - cz), T(0)};
+                    sn2[a] = v4<T>{T(st.wn[3 * s]), T(st.wn[3 * s + 1]), T(st.wn[3 * s + 2]), T(0)};
+                    sidx[a] = int(s);
                 }
-                if (in) {
-                    const v4<T> nv = sn2[a];
-                    const T inv_eta = fast_rsqrt(d2);
-                    const T eta = d2 * inv_eta;
-                    const T r = eta * inv_xi;
-                    const T cos_t = (dx * nv.x + dy * nv.y + dz * nv.z) * inv_eta;
-                    const T x = r - T(1);
-                    const T G = dev_exp2(-x * x * inv2s2);
-                    const T rr = r * r;
-                    const T den = T(1) + rr;
-                    const T coef = s.w * cos_t * G * dev_rcp(den * den);
-                    acc_re += coef * (T(1) - rr);
-                    acc_im += coef * (im_sign * r);
+                __syncthreads();
+                if (live) {
+#pragma unroll 4
+                    for (int a = 0; a < cnt; ++a) {
+                        const v4<T> s = sq2[a];
+                        const T dx = prx - s.x, dy = pry - s.y, dz = prz - s.z;
+                        const T d2 = dx * dx + dy * dy + dz * dz;
+                        bool in = d2 <= r2lo;
+                        if (!in && d2 <= r2hi) {  // near the sphere: decide in FP64
+                            const int64_t sj = sidx[a];
+                            const double ex = px - st.qs[3 * sj], ey = py - st.qs[3 * sj + 1],
+                                         ez = pz - st.qs[3 * sj + 2];
+                            in = ex * ex + ey * ey + ez * ez <= r2max64;
+                        }
+                        if (in) {
+                            const v4<T> nv = sn2[a];
+                            const T inv_eta = fast_rsqrt(d2);
+                            const T eta = d2 * inv_eta;
+                            const T r = eta * inv_xi;
+                            const T wcos = (dx * nv.x + dy * nv.y + dz * nv.z) * inv_eta;
+                            const T u = eta * inv_xi_gs - gs;
+                            const T G = dev_exp2(-u * u);
+                            const T rr = r * r;
+                            const T den = T(1) + rr;
+                            const T coef = wcos * G * dev_rcp(den * den);
+                            acc_re += coef * (T(1) - rr);
+                            acc_im += coef * r;
+                        }
+                    }
                 }
             }
         }
@@ -170,28 +261,146 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
         if (live) {
             const double lam = pmc > 0 ? prm.lambda1 : -prm.lambda2;
             const T scale = T(lam / (2.0 * 3.14159265358979323846 * prm.sigma * best));
-            res = mk(acc_re * scale, acc_im * scale);
+            res = mk(acc_re * scale, acc_im * (im_sign * scale));
         }
         out[(int64_t(k) * g.ny + j) * g.nx + i] = res;
     }
 }
 
+// ---- Morton order and tile boxes
+__device__ __forceinline__ unsigned spread10(unsigned x) {
+    x &= 0x3ffu;
+    x = (x | (x << 16)) & 0x030000ffu;
+    x = (x | (x << 8)) & 0x0300f00fu;
+    x = (x | (x << 4)) & 0x030c30c3u;
+    x = (x | (x << 2)) & 0x09249249u;
+    return x;
+}
+
+// 10 bits per axis over the grid's box widened by 4 h (outside samples clamp)
+__global__ void morton_key_kernel(const double* __restrict__ q, int64_t n, double ox, double oy, double oz,
+                                  double inv_cell, unsigned* __restrict__ key, int* __restrict__ val) {
+    const int64_t jx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (jx >= n) return;
+    const double o[3] = {ox, oy, oz};
+    unsigned c[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double f = (q[3 * jx + a] - o[a]) * inv_cell;
+        c[a] = !(f > 0.0) ? 0u : (f >= 1023.0 ? 1023u : unsigned(f));
+    }
+    key[jx] = spread10(c[0]) | (spread10(c[1]) << 1) | (spread10(c[2]) << 2);
+    val[jx] = int(jx);
+}
+
+__global__ void sample_gather_kernel(const double* __restrict__ q, const double* __restrict__ nrm,
+                                     const double* __restrict__ w, const int* __restrict__ order, int64_t n,
+                                     double* __restrict__ qs, double* __restrict__ wn) {
+    const int64_t ix = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (ix >= n) return;
+    const int64_t s = order[ix];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        qs[3 * ix + a] = q[3 * s + a];
+        wn[3 * ix + a] = w[s] * nrm[3 * s + a];
+    }
+}
+
+__global__ void tile_box_kernel(const double* __restrict__ qs, int64_t n, int64_t ntile, double* __restrict__ box) {
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= ntile) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    const int64_t e = (t + 1) * kSdfTile < n ? (t + 1) * kSdfTile : n;
+    for (int64_t s = t * kSdfTile; s < e; ++s)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fmin(lo[a], qs[3 * s + a]);
+            hi[a] = fmax(hi[a], qs[3 * s + a]);
+        }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        box[6 * t + a] = lo[a];
+        box[6 * t + 3 + a] = hi[a];
+    }
+}
+
+// workspace carve-up (256-byte aligned pieces)
+struct SdfWs {
+    size_t keys_in, vals_in, keys_out, vals_out, qs, wn, box, temp, temp_bytes, total;
+};
+inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+inline SdfWs sdf_ws_layout(int64_t n) {
+    SdfWs L{};
+    size_t temp_bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, static_cast<const unsigned*>(nullptr),
+                                             static_cast<unsigned*>(nullptr), static_cast<const int*>(nullptr),
+                                             static_cast<int*>(nullptr), int(n), 0, 30);
+    const int64_t ntile = (n + kSdfTile - 1) / kSdfTile;
+    size_t off = 0;
+    L.keys_in = off;
+    off += al256(size_t(n) * 4);
+    L.vals_in = off;
+    off += al256(size_t(n) * 4);
+    L.keys_out = off;
+    off += al256(size_t(n) * 4);
+    L.vals_out = off;
+    off += al256(size_t(n) * 4);
+    L.qs = off;
+    off += al256(size_t(n) * 24);
+    L.wn = off;
+    off += al256(size_t(n) * 24);
+    L.box = off;
+    off += al256(size_t(ntile) * 48);
+    L.temp = off;
+    L.temp_bytes = temp_bytes;
+    off += al256(temp_bytes);
+    L.total = off;
+    return L;
+}
+
 }  // namespace
+
+size_t sdf_build_workspace_bytes(int64_t ns) { return sdf_ws_layout(ns).total; }
 
 template <typename T>
 hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
-                            const ParamDesc& p, void* rho_out, hipStream_t s) {
+                            const ParamDesc& p, void* rho_out, void* ws, hipStream_t s) {
+    const SdfWs L = sdf_ws_layout(ns);
+    char* base = static_cast<char*>(ws);
+    auto* keys_in = reinterpret_cast<unsigned*>(base + L.keys_in);
+    auto* vals_in = reinterpret_cast<int*>(base + L.vals_in);
+    auto* keys_out = reinterpret_cast<unsigned*>(base + L.keys_out);
+    auto* vals_out = reinterpret_cast<int*>(base + L.vals_out);
+    auto* qs = reinterpret_cast<double*>(base + L.qs);
+    auto* wn = reinterpret_cast<double*>(base + L.wn);
+    auto* box = reinterpret_cast<double*>(base + L.box);
+    const int64_t ntile = (ns + kSdfTile - 1) / kSdfTile;
+    const unsigned gb = unsigned((ns + 255) / 256);
+    const double ext = g.h * (std::max(g.nx, std::max(g.ny, g.nz)) + 8);
+    hipLaunchKernelGGL(morton_key_kernel, dim3(gb), dim3(256), 0, s, q, ns, g.ox - 4 * g.h, g.oy - 4 * g.h,
+                       g.oz - 4 * g.h, 1024.0 / ext, keys_in, vals_in);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t temp_bytes = L.temp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(base + L.temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, int(ns),
+                                           0, 30, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sample_gather_kernel, dim3(gb), dim3(256), 0, s, q, n, w, vals_out, ns, qs, wn);
+    hipLaunchKernelGGL(tile_box_kernel, dim3(unsigned((ntile + 63) / 64)), dim3(64), 0, s, qs, ns, ntile, box);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const SampleTiles st{qs, wn, vals_out, box, ntile};
     const Brick br = brick_shape(g.nz);
     const int64_t blocks = int64_t((g.nx + br.bx - 1) / br.bx) * ((g.ny + br.by - 1) / br.by) *
                            ((g.nz + br.bz - 1) / br.bz);
-    hipLaunchKernelGGL(sdf_build_kernel<T>, dim3(unsigned(blocks)), dim3(kSdfBlock), 0, s, q, n, w, ns, g, p,
+    hipLaunchKernelGGL(sdf_build_kernel<T>, dim3(unsigned(blocks)), dim3(kSdfBlock), 0, s, q, n, st, ns, g, p,
                        static_cast<cplx<T>*>(rho_out));
     return hipGetLastError();
 }
 
 template hipError_t launch_sdf_build<float>(const double*, const double*, const double*, int64_t, const GridDesc&,
-                                            const ParamDesc&, void*, hipStream_t);
+                                            const ParamDesc&, void*, void*, hipStream_t);
 template hipError_t launch_sdf_build<double>(const double*, const double*, const double*, int64_t, const GridDesc&,
-                                             const ParamDesc&, void*, hipStream_t);
+                                             const ParamDesc&, void*, void*, hipStream_t);
 
 }  // namespace sdf

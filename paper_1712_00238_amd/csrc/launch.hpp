@@ -18,9 +18,10 @@ struct ParamDesc {
 };
 
 // ---- skeletal density (sdf_build): FP64 samples, output in T
+size_t sdf_build_workspace_bytes(int64_t ns);
 template <typename T>
 hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
-                            const ParamDesc& p, void* rho_out, hipStream_t s);
+                            const ParamDesc& p, void* rho_out, void* ws, hipStream_t s);
 
 // ---- rotations: quaternions (FP64, device) -> R (FP64 and cast to T), n x 9 row-major
 template <typename T>
