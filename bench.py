@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--autotune", type=int, default=1, help="tune batch, pencil group and radix schedule first")
     ap.add_argument("--fp64-rotations", type=int, default=64, help="rotations timed on the plain FP64 path")
+    ap.add_argument("--direct-rotations", type=int, default=32,
+                    help="top rotations rescored by the windowless reference search")
     ap.add_argument("--grad-poses", type=int, default=1024)
     ap.add_argument("--grad-steps", type=int, default=5)
     ap.add_argument("--cpu-rotations", type=int, default=2,
@@ -396,6 +398,36 @@ def main():
                                   "same_t_frac": float(np.mean(np.all(t32[:k] == t64, axis=1))),
                                   "same_best": bool(int(np.argmax(s32[:k])) == int(np.argmax(s64)))}
 
+        # --- what the spreading window changes: the top rotations rescored by the
+        # reference search that builds the turned part's SDF on the body box and
+        # places it without a window (same FP32 context and spectrum)
+        if args.direct_rotations:
+            top = np.argsort(-s32, kind="stable")[:args.direct_rotations]
+            qd = pair.quats[top]
+            ctx.score_rotations_direct(spec, fx.grid, mv.samples.q, mv.samples.n, mv.samples.w, mv.grid,
+                                       pair.params, qd[:1])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            od_ = ctx.score_rotations_direct(spec, fx.grid, mv.samples.q, mv.samples.n, mv.samples.w, mv.grid,
+                                             pair.params, qd)
+            torch.cuda.synchronize()
+            d_rps = len(qd) / (time.perf_counter() - t0)
+            sd = od_["score"].cpu().numpy().astype(np.float64)
+            td = od_["t"].cpu().numpy()
+            sw = s32[top]
+            rank_w = np.argsort(np.argsort(-sw)); rank_d = np.argsort(np.argsort(-sd))
+            spearman = 1.0 - 6.0 * float(np.sum((rank_w - rank_d) ** 2)) / (len(sw) * (len(sw) ** 2 - 1))
+            dt = np.abs(t32[top].astype(np.int64) - td.astype(np.int64))
+            dt = np.minimum(dt, 128 - dt)  # periodic
+            report["window_effect"] = {
+                "rotations": int(len(qd)), "direct_rotations_per_s": round(d_rps, 1),
+                "median_rel_peak_diff": float(np.median(np.abs(sw - sd) / np.abs(sd))),
+                "max_rel_peak_diff": float(np.max(np.abs(sw - sd) / np.abs(sd))),
+                "same_t_frac": float(np.mean(np.all(dt == 0, axis=1))),
+                "max_t_shift": int(dt.max()),
+                "same_best": bool(int(np.argmax(sw)) == int(np.argmax(sd))),
+                "spearman": round(spearman, 4)}
+
         # --- pose-gradient evaluations: forward + backward through the adjoint kernel
         B = args.grad_poses
         top = ctx.topk(out["score"], min(n_rot, B)).long()
@@ -492,6 +524,7 @@ def main():
             "fp64_rotations_per_s": round(report["fp64_rotations_per_s"], 1),
             "pose_grad_evals_per_s": round(report["pose_grad_evals_per_s"], 1),
             "fp32_vs_fp64": report["fp32_vs_fp64"],
+            "window_effect": report.get("window_effect"),
             "stage_GBs": round(report["stage_GBs"], 1),
             "correlation_stage": report["correlation_stage"],
             "slab_reach": report["slab_reach"],

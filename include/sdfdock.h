@@ -233,6 +233,29 @@ int score_volume(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
                  const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
                  const double *quats, int64_t n_rot, void *vol_out, sdf_stream stream);
 
+/* Reference search without the spreading window (eq. 8 by covariance,
+ * rho(p, tau S) = rho(tau^-1 p, S)).  For each rotation R the moving part's
+ * boundary samples are turned about its body-box centre c = o_M + h N_M / 2
+ * (q -> c + R (q - c), n -> R n, in FP64; a planar box keeps c_z = o_M,z), its
+ * SDF is built on the body-box nodes as sdf_build does, and the node values
+ * times w_node sit on the fixed grid at the integer offsets k - N_M / 2, with
+ * no window and no resampling:
+ *   f(R, t) = sum_k w_node rho_R(x_k) rho_F((x_k / h + t) mod N),  score Re f.
+ * The correlation, peak, 27-neighbourhood and sub-voxel refinement follow as
+ * in score_rotations (same outputs and layouts).  q, nrm, w, n, p: the moving
+ * part's boundary samples and SDF parameters as for sdf_build (device,
+ * FP64).  N_M must be even.  O(N_M^3 n) per rotation: a reference that
+ * measures what the B-spline window of score_rotations changes, not a fast
+ * path.  The rotated samples, the box SDF and one correlation grid live in
+ * the context's workspace.
+ * Errors: SDF_EINVAL (null pointer, bad grids or params, odd N_M, n <= 0 or
+ * n > 2^30, non-finite w_node), SDF_ENOMEM, SDF_EHIP. */
+int score_rotations_direct(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
+                           const void *q, const void *nrm, const void *w, int64_t n,
+                           const sdf_grid *g_moving, const sdf_params *p, double w_node,
+                           const double *quats, int64_t n_rot, void *peak_score, int32_t *peak_t,
+                           void *peak_nbhd, double *refined_t, sdf_stream stream);
+
 /* The rotated spread M_R on the fixed grid (complex, n_rot x grid size),
  * samples at +R x_k / h (not reflected).  Same constraints. */
 int sdf_spread(sdf_ctx ctx, const sdf_grid *g_fixed, const void *rho_moving, const void *w_moving,

@@ -136,6 +136,33 @@ class Context:
                                              _ptr(out["refined"]), _stream(self.device)))
         return out
 
+    def score_rotations_direct(self, spec, g_fixed, q, n, w, g_moving, params, quats, w_node=None, nbhd=True,
+                               refined=True):
+        """Reference search without the spreading window: per rotation, the
+        SDF of the moving part's turned boundary samples on its body box,
+        placed on the fixed grid at integer offsets.  q, n: (n, 3), w: (n,)
+        boundary samples (FP64); w_node defaults to h^3.  Returns dict(score,
+        t, nbhd, refined) as score_rotations."""
+        qq = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+        n_rot = len(qq)
+        spec = self._dev(spec, self.cplx)
+        qs = self._dev(q, torch.float64)
+        ns = self._dev(n, torch.float64)
+        ws = self._dev(w, torch.float64)
+        out = {"score": torch.empty(n_rot, dtype=self.real, device=self.device),
+               "t": torch.empty((n_rot, 3), dtype=torch.int32, device=self.device),
+               "nbhd": torch.empty((n_rot, 27), dtype=self.real, device=self.device) if nbhd else None,
+               "refined": torch.empty((n_rot, 3), dtype=torch.float64, device=self.device) if refined else None}
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        p = _lib.make_params(params)
+        wn = float(g_moving.h ** 3) if w_node is None else float(w_node)
+        self._check(self.lib.score_rotations_direct(self.handle, _ptr(spec), ctypes.byref(gf), _ptr(qs), _ptr(ns),
+                                                    _ptr(ws), int(ws.numel()), ctypes.byref(gm), ctypes.byref(p), wn,
+                                                    qq.ctypes.data_as(ctypes.c_void_p), n_rot, _ptr(out["score"]),
+                                                    _ptr(out["t"]), _ptr(out["nbhd"]), _ptr(out["refined"]),
+                                                    _stream(self.device)))
+        return out
+
     def score_pairs(self, jobs, nbhd=True, refined=True):
         """Many pairs in one call.  ``jobs``: sequence of dicts with keys spec,
         g_fixed, rho_moving, w_moving, g_moving, quats.  Returns one output

@@ -701,6 +701,68 @@ int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std:
 
 // =====================================================================  ABI
 
+// Direct reference path: per rotation, SDF of the turned boundary samples on
+// the body box, placed on the fixed grid without a window, then the plain
+// path's transform, product, inverse and peak.
+template <typename T>
+int direct_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const double* q, const double* nrm,
+                const double* w, int64_t ns, const sdf_grid* gm, const sdf_params* p, double w_node,
+                const double* quats, int64_t n_rot, void* score, int32_t* t, void* nbhd, double* refined,
+                hipStream_t s) {
+    ctx->fused_cache_valid = false;
+    const int N = gf->n[0];
+    const bool planar = gf->n[2] == 1;
+    const int nm = gm->n[0];
+    const int64_t K = gsize(gm), G = gsize(gf);
+    const int nparts = sdf::peak_parts<T>(N, planar);
+    const size_t sdf_ws = sdf::sdf_build_workspace_bytes(ns);
+    Carve cv{nullptr};
+    cv.take(sizeof(double) * 4 * n_rot);
+    cv.take(sizeof(double) * 9 * n_rot);
+    cv.take(sizeof(T) * 9 * n_rot);
+    cv.take(sizeof(double) * 3 * ns);
+    cv.take(sizeof(double) * 3 * ns);
+    cv.take(2 * sizeof(T) * K);
+    cv.take(2 * sizeof(T) * G);
+    cv.take(sizeof(T) * nparts);
+    cv.take(sizeof(int) * nparts);
+    cv.take(sdf_ws);
+    int rc = ensure_ws(ctx, cv.off);
+    if (rc) return rc;
+    Carve c2{static_cast<char*>(ctx->ws)};
+    double* qd = static_cast<double*>(c2.take(sizeof(double) * 4 * n_rot));
+    double* r64 = static_cast<double*>(c2.take(sizeof(double) * 9 * n_rot));
+    T* RT = static_cast<T*>(c2.take(sizeof(T) * 9 * n_rot));
+    double* qr = static_cast<double*>(c2.take(sizeof(double) * 3 * ns));
+    double* nr = static_cast<double*>(c2.take(sizeof(double) * 3 * ns));
+    void* rho = c2.take(2 * sizeof(T) * K);
+    void* grid = c2.take(2 * sizeof(T) * G);
+    T* pval = static_cast<T*>(c2.take(sizeof(T) * nparts));
+    int* pidx = static_cast<int*>(c2.take(sizeof(int) * nparts));
+    void* wsb = c2.take(sdf_ws);
+    const double c[3] = {gm->origin[0] + 0.5 * gm->h * nm, gm->origin[1] + 0.5 * gm->h * nm,
+                         planar ? gm->origin[2] : gm->origin[2] + 0.5 * gm->h * nm};
+    const sdf::ParamDesc pd{p->lambda1, p->lambda2, p->sigma, p->eps, p->xi_floor};
+    SDF_TRY_HIP(ctx, hipMemcpyAsync(qd, quats, sizeof(double) * 4 * n_rot, hipMemcpyHostToDevice, s),
+                "quaternion upload");
+    SDF_TRY_HIP(ctx, sdf::launch_quat_to_rot<T>(qd, n_rot, r64, RT, s), "rotations");
+    for (int64_t r = 0; r < n_rot; ++r) {
+        SDF_TRY_HIP(ctx, sdf::launch_rotate_samples(q, nrm, ns, r64 + 9 * r, c, qr, nr, s), "rotate samples");
+        SDF_TRY_HIP(ctx, sdf::launch_sdf_build<T>(qr, nr, w, ns, desc(gm), pd, rho, wsb, s), "box sdf");
+        SDF_TRY_HIP(ctx, sdf::launch_zero<T>(grid, G, s), "zero");
+        SDF_TRY_HIP(ctx, sdf::launch_place_direct<T>(rho, nm, planar, T(w_node), N, grid, s), "place");
+        SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, 1, -1, 1.0, s), "forward fft");
+        SDF_TRY_HIP(ctx, sdf::launch_mul_spec<T>(grid, spec, G, 1, s), "spectral product");
+        SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, 1, +1, 1.0, s), "inverse fft");
+        SDF_TRY_HIP(ctx,
+                    sdf::launch_peak<T>(grid, true, N, planar, 1, pval, pidx, nparts, static_cast<T*>(score) + r,
+                                        t + 3 * r, nbhd ? static_cast<T*>(nbhd) + 27 * r : nullptr,
+                                        refined ? refined + 3 * r : nullptr, s),
+                    "peak");
+    }
+    return SDF_OK;
+}
+
 extern "C" {
 
 int sdf_ctx_create(sdf_ctx* out, int device, sdf_dtype dtype, size_t workspace_cap_bytes) {
@@ -943,6 +1005,34 @@ int score_volume(sdf_ctx ctx, const void* spec_fixed, const sdf_grid* g_fixed, c
                                      nullptr, nullptr, nullptr}};
     if (ctx->dtype == SDF_F64) return search_impl<double>(ctx, pairs, Mode::Volume, vol_out, s);
     return search_impl<float>(ctx, pairs, Mode::Volume, vol_out, s);
+}
+
+int score_rotations_direct(sdf_ctx ctx, const void* spec_fixed, const sdf_grid* g_fixed, const void* q,
+                           const void* nrm, const void* w, int64_t n, const sdf_grid* g_moving, const sdf_params* p,
+                           double w_node, const double* quats, int64_t n_rot, void* peak_score, int32_t* peak_t,
+                           void* peak_nbhd, double* refined_t, sdf_stream stream) {
+    if (!spec_fixed || !q || !nrm || !w || !peak_score || !peak_t) return fail(ctx, SDF_EINVAL, "NULL array");
+    if (n <= 0 || n > (int64_t(1) << 30)) return fail(ctx, SDF_EINVAL, "sample count must be in [1, 2^30]");
+    if (!std::isfinite(w_node)) return fail(ctx, SDF_EINVAL, "w_node must be finite");
+    int rc = check_pair(ctx, g_fixed, g_moving, true);
+    if (rc) return rc;
+    if (g_moving->n[0] % 2) return fail(ctx, SDF_EINVAL, "the direct placement needs an even N_M");
+    rc = check_params(ctx, p);
+    if (rc) return rc;
+    rc = check_quats(ctx, quats, n_rot);
+    if (rc) return rc;
+    if (n_rot > (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "n_rot too large");
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const double* qd = static_cast<const double*>(q);
+    const double* nd = static_cast<const double*>(nrm);
+    const double* wd = static_cast<const double*>(w);
+    if (ctx->dtype == SDF_F64)
+        return direct_impl<double>(ctx, spec_fixed, g_fixed, qd, nd, wd, n, g_moving, p, w_node, quats, n_rot,
+                                   peak_score, peak_t, peak_nbhd, refined_t, s);
+    return direct_impl<float>(ctx, spec_fixed, g_fixed, qd, nd, wd, n, g_moving, p, w_node, quats, n_rot, peak_score,
+                              peak_t, peak_nbhd, refined_t, s);
 }
 
 int sdf_spread(sdf_ctx ctx, const sdf_grid* g_fixed, const void* rho_moving, const void* w_moving,

@@ -107,6 +107,39 @@ __global__ void spread_atomic_kernel(const cplx<T>* __restrict__ c, int n_m, int
     }
 }
 
+// ------------------------------------------------------------------ direct reference
+// Boundary samples of the moving part turned about its body-box centre c:
+// q' = c + R (q - c), n' = R n (FP64, R row-major).
+__global__ void rotate_samples_kernel(const double* __restrict__ q, const double* __restrict__ nrm, int64_t ns,
+                                      const double* __restrict__ R, double cx, double cy, double cz,
+                                      double* __restrict__ qo, double* __restrict__ no) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= ns) return;
+    const double d[3] = {q[3 * j] - cx, q[3 * j + 1] - cy, q[3 * j + 2] - cz};
+    const double c[3] = {cx, cy, cz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        qo[3 * j + a] = c[a] + R[3 * a] * d[0] + R[3 * a + 1] * d[1] + R[3 * a + 2] * d[2];
+        no[3 * j + a] = R[3 * a] * nrm[3 * j] + R[3 * a + 1] * nrm[3 * j + 1] + R[3 * a + 2] * nrm[3 * j + 2];
+    }
+}
+
+// Body-box values placed on the fixed grid without a window, reflected as
+// the spread with sign -1 places them: node k (body position k - n_m / 2,
+// n_m even) goes to u = -(k - n_m / 2) mod N.  Distinct nodes land on
+// distinct grid nodes (n_m <= N), so plain stores suffice.
+template <typename T>
+__global__ void place_direct_kernel(const cplx<T>* __restrict__ rho, int n_m, int planar, T w_node, int N,
+                                    cplx<T>* __restrict__ out) {
+    const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    const int h = n_m / 2;
+    const int kx = int(k % n_m), ky = int((k / n_m) % n_m), kz = planar ? h : int(k / (int64_t(n_m) * n_m));
+    const int ux = wrap(h - kx, N), uy = wrap(h - ky, N), uz = planar ? 0 : wrap(h - kz, N);
+    out[(int64_t(uz) * N + uy) * N + ux] = rho[k] * w_node;
+}
+
 // ------------------------------------------------------------------ FFT passes
 constexpr int kFftBlock = 256;
 
@@ -428,10 +461,26 @@ hipError_t launch_real_part(const void* vol, T* out, int64_t count, hipStream_t 
     return hipGetLastError();
 }
 
+hipError_t launch_rotate_samples(const double* q, const double* nrm, int64_t ns, const double* R, const double c[3],
+                                 double* qo, double* no, hipStream_t s) {
+    hipLaunchKernelGGL(rotate_samples_kernel, dim3(unsigned((ns + 255) / 256)), dim3(256), 0, s, q, nrm, ns, R, c[0],
+                       c[1], c[2], qo, no);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_place_direct(const void* rho, int n_m, bool planar, T w_node, int N, void* out, hipStream_t s) {
+    const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
+    hipLaunchKernelGGL(place_direct_kernel<T>, dim3(unsigned((K + 255) / 256)), dim3(256), 0, s,
+                       static_cast<const cplx<T>*>(rho), n_m, planar ? 1 : 0, w_node, N, static_cast<cplx<T>*>(out));
+    return hipGetLastError();
+}
+
 #define SDF_INST(T)                                                                                              \
     template hipError_t launch_quat_to_rot<T>(const double*, int64_t, double*, T*, hipStream_t);                \
     template hipError_t launch_coef<T>(const void*, const T*, int64_t, void*, hipStream_t);                      \
     template hipError_t launch_zero<T>(void*, int64_t, hipStream_t);                                             \
+    template hipError_t launch_place_direct<T>(const void*, int, bool, T, int, void*, hipStream_t);               \
     template hipError_t launch_spread_atomic<T>(const void*, int, bool, const T*, int, T, int, void*,           \
                                                 hipStream_t);                                                    \
     template hipError_t launch_fft3<T>(void*, int, bool, int, int, double, hipStream_t);                         \

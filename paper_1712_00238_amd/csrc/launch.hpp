@@ -35,6 +35,12 @@ hipError_t launch_coef(const void* rho_m, const T* w_m, int64_t count, void* c_o
 // zero `count` complex values
 template <typename T>
 hipError_t launch_zero(void* buf, int64_t count, hipStream_t s);
+// direct reference: boundary samples turned about c (FP64), and body-box
+// values placed on the fixed grid at the reflected integer offsets
+hipError_t launch_rotate_samples(const double* q, const double* nrm, int64_t ns, const double* R, const double c[3],
+                                 double* qo, double* no, hipStream_t s);
+template <typename T>
+hipError_t launch_place_direct(const void* rho, int n_m, bool planar, T w_node, int N, void* out, hipStream_t s);
 // spread samples c (n_m^3 or n_m^2) rotated by R[rot] (sign * R x_k) into grids
 // out[rot], which must be zero.  n_rot rotations, R in T.
 template <typename T>

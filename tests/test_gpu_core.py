@@ -6,8 +6,10 @@ import pytest
 
 from helpers import flush_print, oracle_fields, score_rel_err, sdf_compare
 from oracle import correlate as oc
+from oracle import direct as od
 from oracle import grad as og
 from oracle import peak as op
+from oracle import sdf as osdf
 from oracle import spread as osp
 from workloads import configs as C
 from workloads import rotations as wr
@@ -222,6 +224,53 @@ def test_score_rotations_f64_exact_peaks(ctxs, n, nm, planar, nrot):
         nb0 = op.neighbourhood(vol, t0)
         assert np.allclose(to_np(out["nbhd"])[r], nb0, atol=1e-11 * np.abs(vol).max())
         assert np.allclose(to_np(out["refined"])[r], op.subvoxel(nb0, t0), atol=1e-9)
+
+
+# ----------------------------------------------------------------------------- windowless reference
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["small_3d", "peg_2d"])
+def test_score_rotations_direct_matches_oracle(ctxs, dtype, case):
+    """The reference search without the spreading window (turned boundary
+    samples, box SDF, integer placement) against the oracle's direct volume:
+    peak value, position (near-ties allowed in FP32), 27-neighbourhood and
+    sub-voxel refinement.  The fixed field is the oracle's, shared."""
+    ctx = ctxs[dtype]
+    if case == "small_3d":
+        pair, planar = C.small_3d(seed=1, n=16, n_m=6), False
+        quats = np.concatenate([[[1.0, 0.0, 0.0, 0.0]], wr.uniform_quaternions(3, 21)])
+    else:
+        pair, planar = C.peg_in_hole_2d(seed=0), True
+        quats = wr.planar_rotations(37.0, 3)
+    fx, mv = pair.fixed, pair.moving
+    flush_print("score_rotations_direct", dtype, case)
+    rho_f = osdf.sdf_grid(fx.samples, fx.grid, pair.params)
+    w_node = mv.grid.h ** 3
+    out = ctx.score_rotations_direct(ctx.spectrum(rho_f, fx.grid), fx.grid, mv.samples.q, mv.samples.n,
+                                     mv.samples.w, mv.grid, pair.params, quats, w_node)
+    s, t, nb, rt = (to_np(out[k]) for k in ("score", "t", "nbhd", "refined"))
+    tol = 1e-10 if dtype == "f64" else 1e-4
+    for r, q in enumerate(quats):
+        vol = od.direct_volume(rho_f, mv.samples, mv.grid, pair.params, q, w_node, planar)
+        s0, _, t0 = op.peak(vol)
+        scale = np.abs(vol).max()
+        assert abs(s[r] - s0) <= tol * scale, (r, s[r], s0)
+        if tuple(t[r]) != t0:
+            assert dtype == "f32" and abs(vol[t[r][2], t[r][1], t[r][0]] - s0) <= tol * scale, (r, t[r], t0)
+        nb0 = op.neighbourhood(vol, tuple(t[r]))
+        assert np.max(np.abs(nb[r] - nb0)) <= tol * scale
+        assert np.max(np.abs(rt[r] - op.subvoxel(nb0, tuple(t[r])))) <= (1e-8 if dtype == "f64" else 1e-3)
+
+
+def test_score_rotations_direct_refuses_odd_box(ctxs):
+    from paper_1712_00238_amd._lib import SdfError
+    ctx = ctxs["f32"]
+    pair = C.small_3d(seed=1, n=16, n_m=5)
+    fx, mv = pair.fixed, pair.moving
+    spec = ctx.spectrum(np.zeros((16, 16, 16), dtype=np.complex64), fx.grid)
+    with pytest.raises(SdfError):
+        ctx.score_rotations_direct(spec, fx.grid, mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params,
+                                   np.array([[1.0, 0.0, 0.0, 0.0]]))
 
 
 # ----------------------------------------------------------------------------- top-k
