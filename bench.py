@@ -53,12 +53,16 @@ def parse():
     ap.add_argument("--direct-rotations", type=int, default=32,
                     help="top rotations rescored by the windowless reference search")
     ap.add_argument("--grad-poses", type=int, default=1024)
+    ap.add_argument("--refine-poses", type=int, default=1024,
+                    help="protein-like refinement: poses perturbed from the top peaks (0 skips)")
+    ap.add_argument("--refine-steps", type=int, default=50)
+    ap.add_argument("--refine-lr", type=float, default=0.05)
     ap.add_argument("--grad-steps", type=int, default=5)
     ap.add_argument("--cpu-rotations", type=int, default=2,
                     help="oracle rotations per host worker in the CPU baseline")
     ap.add_argument("--protein-rotations", type=int, default=3600,
                     help="rotations of the protein-like pair scored 64 per launch (0: skip)")
-    ap.add_argument("--uneven-pairs", type=int, default=48,
+    ap.add_argument("--uneven-pairs", type=int, default=256,
                     help="pairs in the multi-pair queue figure, 512 rotations each (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
@@ -475,6 +479,39 @@ def main():
                                       "samples": [pf.samples.count, pm.samples.count],
                                       "sdf_build_ms": [round(x, 2) for x in build_ms],
                                       "end_to_end_ms": round(sum(build_ms) + 1e3 * dt, 2)}
+            # --- differentiable refinement on the protein-like pair: poses from the
+            # top peaks, perturbed by N(0, 2) grid units and N(0, 10 deg), then
+            # gradient ascent on the score through the adjoint kernel
+            if args.refine_poses:
+                B = args.refine_poses
+                topi = ctx.topk(pout["score"], min(len(pp.quats), B)).long()
+                bt = pout["refined"][topi].cpu().numpy()
+                bq = pp.quats[topi.cpu().numpy()]
+                reps = int(math.ceil(B / len(bt)))
+                tt, qq = wr.perturb_poses(np.tile(bt, (reps, 1))[:B], np.tile(bq, (reps, 1))[:B], 2.0, 10.0, 11)
+                rposes = torch.tensor(np.concatenate([tt, qq], axis=1), dtype=torch.float64, device=dev,
+                                      requires_grad=True)
+                ropt = torch.optim.Adam([rposes], lr=args.refine_lr)
+                s_start = None
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for it in range(args.refine_steps):
+                    ropt.zero_grad()
+                    sc = sdf_score(rposes, pw, ctx, rf, pf.grid, rm, pm.grid)
+                    if it == 0:
+                        s_start = sc.detach().double().clone()
+                    (-sc.sum()).backward()
+                    ropt.step()
+                torch.cuda.synchronize()
+                dt_r = time.perf_counter() - t0
+                s_end = ctx.score_grad(rf, pf.grid, rm, pw, pm.grid, rposes.detach(), want_pose=False)[0].double()
+                report["refinement"] = {
+                    "pair": "protein_like", "poses": B, "steps": args.refine_steps, "optimizer": "adam",
+                    "lr": args.refine_lr, "evals_per_s": round(B * args.refine_steps / dt_r, 1),
+                    "mean_score_start": float(s_start.mean()), "mean_score_end": float(s_end.mean()),
+                    "improved_frac": float((s_end > s_start).double().mean()),
+                    "best_peak_score": float(pout["score"].max())}
+                del rposes, ropt
             ctx.set_option("batch", args.batch)
             del rf, rm, psp, pw, pout
 
@@ -532,6 +569,7 @@ def main():
             "sdf_build_fixed_pairs_per_s": report["sdf_build_fixed_pairs_per_s"],
             "spectrum_ms": round(report["spectrum_ms"], 4),
             "protein_like": report.get("protein_like"),
+            "refinement": report.get("refinement"),
             "uneven_batch": report.get("uneven_batch"),
             "kernels": report["kernels"]}
     if not args.no_cpu_baseline:
