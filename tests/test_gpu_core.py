@@ -12,6 +12,7 @@ from oracle import peak as op
 from oracle import sdf as osdf
 from oracle import spread as osp
 from workloads import configs as C
+from workloads import shapes
 from workloads import rotations as wr
 
 pytestmark = pytest.mark.gpu
@@ -61,6 +62,27 @@ def test_sdf_build_small_3d_ragged(ctxs, dtype):
     rho = to_np(ctx.sdf_build(s.q, s.n, s.w, grid, pair.params))
     rel, band = (1e-10, 1e-10) if dtype == "f64" else (2e-5, 2e-5)
     rep = sdf_compare(rho, s, grid, pair.params, rel, band)
+    flush_print(rep)
+    assert rep["ok"], rep
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("count", [1, 256, 257, 700])
+def test_sdf_build_sample_tile_edges(ctxs, dtype, count):
+    """Sample counts at the edges of the 256-sample tiles the build culls by
+    (one sample, one full tile, a one-sample second tile, a ragged third),
+    drawn from a sphere so that many nodes have near-equidistant samples."""
+    ctx = ctxs[dtype]
+    rng = np.random.default_rng(count)
+    v = rng.normal(size=(count, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    s = shapes.PointSamples(4.0 * v + 0.3, v.copy(), np.full(count, 4.0 * np.pi * 16.0 / count))
+    grid = C.GridSpec((14, 13, 12), (-6.5, -6.0, -5.5), 1.0)
+    params = C.SDFParams(xi_floor=0.25)
+    flush_print("sdf_build tile edges", dtype, count)
+    rho = to_np(ctx.sdf_build(s.q, s.n, s.w, grid, params))
+    rel, band = (1e-10, 1e-10) if dtype == "f64" else (2e-5, 2e-5)
+    rep = sdf_compare(rho, s, grid, params, rel, band)
     flush_print(rep)
     assert rep["ok"], rep
 
