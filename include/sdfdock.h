@@ -156,6 +156,30 @@ int sdf_ctx_stats_reset(sdf_ctx ctx);
 int sdf_build(sdf_ctx ctx, const void *q, const void *nrm, const void *w, int64_t n,
               const sdf_grid *g, const sdf_params *p, void *rho_out, sdf_stream stream);
 
+/* Adjoint of sdf_build with respect to its boundary samples (shape
+ * gradients): for a complex cotangent field cot on the grid (context
+ * precision, same layout as rho), the gradients of
+ *   L = Re sum_p cot(p) rho(p)
+ * with respect to the sample positions (grad_q, n x 3), normals (grad_n,
+ * n x 3, unconstrained) and weights (grad_w, n), all FP64 device arrays that
+ * the call overwrites.  The nearest sample, membership and contact ball of
+ * every node are held (the SDF is piecewise smooth; these choices change only
+ * on measure-zero sets).  With A = lambda / (2 pi sigma xi^2), u_j the unit
+ * vector from q_j to the node, c_j = u_j . n_j, r_j = |p - q_j| / xi and
+ * K = G P / (1 + r^2)^2:
+ *   d rho / d w_j = A c_j K(r_j),   d rho / d n_j = A w_j K(r_j) u_j,
+ *   d rho / d q_j = A w_j (-K (n_j - c_j u_j) / |p - q_j| - c_j K'(r_j) u_j / xi)
+ * plus, for the nearest sample, -(d rho / d xi) u* with
+ *   d rho / d xi = -(2 rho + A sum_j w_j c_j K'(r_j) r_j) / xi.
+ * Computed in FP64 in both precisions; sums across node bricks use FP64
+ * atomics, so the last bits may vary between runs.  Same inputs and
+ * constraints as sdf_build; the samples' Morton order lives in the context's
+ * workspace.
+ * Errors: as sdf_build. */
+int sdf_build_adjoint(sdf_ctx ctx, const void *q, const void *nrm, const void *w, int64_t n,
+                      const sdf_grid *g, const sdf_params *p, const void *cot, double *grad_q,
+                      double *grad_n, double *grad_w, sdf_stream stream);
+
 /* Spectrum of the fixed part for the correlation (eq. 8):
  * spec_out(k) = N^-3 * sum_p rho_fixed(p) exp(-2 pi i k.p / N)  (N^-2 in 2D),
  * complex, same layout as the grid.  The grid must be N^3 or N^2 x 1 with N

@@ -17,7 +17,7 @@ SDF_F32, SDF_F64 = 0, 1
 EXPORTS = ["sdf_ctx_create", "sdf_ctx_destroy", "sdf_last_error", "sdf_ctx_set_option", "sdf_ctx_get_option",
            "sdf_ctx_stats", "sdf_ctx_stats_reset",
            "sdf_build", "sdf_spectrum", "score_rotations", "score_pairs", "sdf_autotune", "score_volume",
-           "sdf_spread", "sdf_fft", "sdf_topk", "score_grad", "score_rotations_direct"]
+           "sdf_spread", "sdf_fft", "sdf_topk", "score_grad", "score_rotations_direct", "sdf_build_adjoint"]
 
 
 class SdfGrid(ctypes.Structure):
@@ -63,6 +63,7 @@ def load() -> ctypes.CDLL:
         "sdf_ctx_stats": ([vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], ctypes.c_int),
         "sdf_ctx_stats_reset": ([vp], ctypes.c_int),
         "sdf_build": ([vp, vp, vp, vp, i64, gp, pp, vp, vp], ctypes.c_int),
+        "sdf_build_adjoint": ([vp, vp, vp, vp, i64, gp, pp, vp, vp, vp, vp, vp], ctypes.c_int),
         "sdf_spectrum": ([vp, vp, gp, vp, vp], ctypes.c_int),
         "score_rotations": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "score_rotations_direct": ([vp, vp, gp, vp, vp, vp, i64, gp, pp, ctypes.c_double, vp, i64, vp, vp, vp, vp,

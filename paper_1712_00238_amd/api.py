@@ -106,6 +106,24 @@ class Context:
                                        ctypes.byref(p), _ptr(out), _stream(self.device)))
         return out
 
+    def sdf_build_adjoint(self, q, n, w, grid, params, cot):
+        """Shape gradients: (dL/dq (n, 3), dL/dn (n, 3), dL/dw (n,)) in FP64 for
+        L = Re sum_p cot(p) rho(p), rho = sdf_build(q, n, w, grid, params)."""
+        q = self._dev(q, torch.float64)
+        n = self._dev(n, torch.float64)
+        w = self._dev(w, torch.float64)
+        cot = self._dev(cot, self.cplx)
+        m = int(w.numel())
+        gq = torch.empty((m, 3), dtype=torch.float64, device=self.device)
+        gn = torch.empty((m, 3), dtype=torch.float64, device=self.device)
+        gw = torch.empty(m, dtype=torch.float64, device=self.device)
+        g = _lib.make_grid(grid)
+        p = _lib.make_params(params)
+        self._check(self.lib.sdf_build_adjoint(self.handle, _ptr(q), _ptr(n), _ptr(w), m, ctypes.byref(g),
+                                               ctypes.byref(p), _ptr(cot), _ptr(gq), _ptr(gn), _ptr(gw),
+                                               _stream(self.device)))
+        return gq, gn, gw
+
     def spectrum(self, rho_fixed, grid, out=None):
         rho_fixed = self._dev(rho_fixed, self.cplx)
         if out is None:

@@ -892,6 +892,35 @@ int sdf_build(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_
     return SDF_OK;
 }
 
+int sdf_build_adjoint(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_t n, const sdf_grid* g,
+                      const sdf_params* p, const void* cot, double* grad_q, double* grad_n, double* grad_w,
+                      sdf_stream stream) {
+    if (!q || !nrm || !w || !cot || !grad_q || !grad_n || !grad_w) return fail(ctx, SDF_EINVAL, "NULL array");
+    if (n <= 0 || n > (int64_t(1) << 30)) return fail(ctx, SDF_EINVAL, "sample count must be in [1, 2^30]");
+    int rc = check_grid(ctx, g, "grid");
+    if (rc) return rc;
+    rc = check_params(ctx, p);
+    if (rc) return rc;
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(ctx, SDF_EHIP, "cannot select device");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const sdf::ParamDesc pd{p->lambda1, p->lambda2, p->sigma, p->eps, p->xi_floor};
+    const double* qd = static_cast<const double*>(q);
+    const double* nd = static_cast<const double*>(nrm);
+    const double* wd = static_cast<const double*>(w);
+    ctx->fused_cache_valid = false;  // the Morton-ordered samples share the workspace
+    rc = ensure_ws(ctx, sdf::sdf_build_workspace_bytes(n));
+    if (rc) return rc;
+    hipError_t e = ctx->dtype == SDF_F64
+                       ? sdf::launch_sdf_adjoint<double>(qd, nd, wd, n, desc(g), pd, cot, grad_q, grad_n, grad_w,
+                                                         ctx->ws, s)
+                       : sdf::launch_sdf_adjoint<float>(qd, nd, wd, n, desc(g), pd, cot, grad_q, grad_n, grad_w,
+                                                        ctx->ws, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sdf_build_adjoint");
+    return SDF_OK;
+}
+
 int sdf_fft(sdf_ctx ctx, const void* in, void* out, const sdf_grid* g, int direction, sdf_stream stream) {
     if (!in || !out) return fail(ctx, SDF_EINVAL, "NULL array");
     if (direction != -1 && direction != 1) return fail(ctx, SDF_EINVAL, "direction must be -1 or +1");

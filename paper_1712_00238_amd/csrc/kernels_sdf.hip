@@ -122,40 +122,18 @@ __device__ __forceinline__ double block_reduce(double v, double* red) {
     return v;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __restrict__ q,
-                                                              const double* __restrict__ nrm, SampleTiles st,
-                                                              int64_t ns, GridDesc g, ParamDesc prm,
-                                                              cplx<T>* __restrict__ out) {
-    __shared__ v4<double> sq[2 * kSdfTile];  // pass 1: (qx, qy, qz, -); pass 2: reused as two T tiles
-    __shared__ int sidx[kSdfTile];           // pass 1: original index; pass 2: Morton index
-    __shared__ int tflag[kSdfBlock];         // tiles of the current chunk that the brick visits
-    __shared__ double red[kSdfBlock / 64];
-    v4<T>* sq2 = reinterpret_cast<v4<T>*>(sq);             // (qx, qy, qz, -) relative to the brick
-    v4<T>* sn2 = reinterpret_cast<v4<T>*>(sq) + kSdfTile;  // w (nx, ny, nz), -
-
-    const Brick br = brick_shape(g.nz);
-    const int nbx = (g.nx + br.bx - 1) / br.bx, nby = (g.ny + br.by - 1) / br.by;
-    const int blk = blockIdx.x;
-    const int i0 = (blk % nbx) * br.bx, j0 = ((blk / nbx) % nby) * br.by, k0 = (blk / (nbx * nby)) * br.bz;
-    const int li = threadIdx.x % br.bx, lj = (threadIdx.x / br.bx) % br.by, lk = threadIdx.x / (br.bx * br.by);
-    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
-    const bool valid = i < g.nx && j < g.ny && k < g.nz;
-    // brick corner (FP64) and this node relative to it
-    const double cx = g.ox + g.h * i0, cy = g.oy + g.h * j0, cz = g.oz + g.h * k0;
-    const double rx = g.h * li, ry = g.h * lj, rz = g.h * lk;
-    const double px = cx + rx, py = cy + ry, pz = cz + rz;
-    // box of the brick's nodes inside the grid
-    const double bl[3] = {cx, cy, cz};
-    const double bh[3] = {cx + g.h * (min(br.bx, g.nx - i0) - 1), cy + g.h * (min(br.by, g.ny - j0) - 1),
-                          cz + g.h * (min(br.bz, g.nz - k0) - 1)};
-
-    // ---- pass 1 (FP64): nearest sample, lowest original index on exact ties
+// Pass 1 (FP64) for the node (px, py, pz) of the brick [bl, bh]: squared
+// distance to the nearest sample and its original index (lowest on exact
+// ties), visiting only the tiles within U of the brick.  Block-wide: every
+// thread of the block calls it.
+__device__ __forceinline__ void nearest_pass(const SampleTiles& st, int64_t ns, const double bl[3], const double bh[3],
+                                             double px, double py, double pz, v4<double>* sq, int* sidx, int* tflag,
+                                             double* red, double& best, int& jbest) {
     double u2 = INFINITY;
     for (int64_t t = threadIdx.x; t < st.ntile; t += kSdfBlock) u2 = fmin(u2, box_dmax2(bl, bh, st.box + 6 * t));
     u2 = block_reduce<false>(u2, red) * (1.0 + 1e-9);
-    double best = INFINITY;
-    int jbest = 0;
+    best = INFINITY;
+    jbest = 0;
     for (int64_t c0 = 0; c0 < st.ntile; c0 += kSdfBlock) {
         const int64_t tc = c0 + threadIdx.x;
         __syncthreads();  // the previous chunk is done with tflag, sq and sidx
@@ -186,6 +164,40 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
             }
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __restrict__ q,
+                                                              const double* __restrict__ nrm, SampleTiles st,
+                                                              int64_t ns, GridDesc g, ParamDesc prm,
+                                                              cplx<T>* __restrict__ out) {
+    __shared__ v4<double> sq[2 * kSdfTile];  // pass 1: (qx, qy, qz, -); pass 2: reused as two T tiles
+    __shared__ int sidx[kSdfTile];           // pass 1: original index; pass 2: Morton index
+    __shared__ int tflag[kSdfBlock];         // tiles of the current chunk that the brick visits
+    __shared__ double red[kSdfBlock / 64];
+    v4<T>* sq2 = reinterpret_cast<v4<T>*>(sq);             // (qx, qy, qz, -) relative to the brick
+    v4<T>* sn2 = reinterpret_cast<v4<T>*>(sq) + kSdfTile;  // w (nx, ny, nz), -
+
+    const Brick br = brick_shape(g.nz);
+    const int nbx = (g.nx + br.bx - 1) / br.bx, nby = (g.ny + br.by - 1) / br.by;
+    const int blk = blockIdx.x;
+    const int i0 = (blk % nbx) * br.bx, j0 = ((blk / nbx) % nby) * br.by, k0 = (blk / (nbx * nby)) * br.bz;
+    const int li = threadIdx.x % br.bx, lj = (threadIdx.x / br.bx) % br.by, lk = threadIdx.x / (br.bx * br.by);
+    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+    const bool valid = i < g.nx && j < g.ny && k < g.nz;
+    // brick corner (FP64) and this node relative to it
+    const double cx = g.ox + g.h * i0, cy = g.oy + g.h * j0, cz = g.oz + g.h * k0;
+    const double rx = g.h * li, ry = g.h * lj, rz = g.h * lk;
+    const double px = cx + rx, py = cy + ry, pz = cz + rz;
+    // box of the brick's nodes inside the grid
+    const double bl[3] = {cx, cy, cz};
+    const double bh[3] = {cx + g.h * (min(br.bx, g.nx - i0) - 1), cy + g.h * (min(br.by, g.ny - j0) - 1),
+                          cz + g.h * (min(br.bz, g.nz - k0) - 1)};
+
+    // ---- pass 1 (FP64): nearest sample, lowest original index on exact ties
+    double best;
+    int jbest;
+    nearest_pass(st, ns, bl, bh, px, py, pz, sq, sidx, tflag, red, best, jbest);
     const int64_t jb = jbest;
     const double dot = (px - q[3 * jb]) * nrm[3 * jb] + (py - q[3 * jb + 1]) * nrm[3 * jb + 1] +
                        (pz - q[3 * jb + 2]) * nrm[3 * jb + 2];
@@ -264,6 +276,192 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
             res = mk(acc_re * scale, acc_im * (im_sign * scale));
         }
         out[(int64_t(k) * g.ny + j) * g.nx + i] = res;
+    }
+}
+
+// ---- adjoint with respect to the boundary samples
+// L = Re sum_p g(p) rho(p).  With the nearest sample, membership and contact
+// ball of every node held (FP64 throughout; the cotangent g comes in the
+// context's precision), at a live node with nearest sample q* at xi:
+//   d rho / d w_j = A c_j K(r_j),   d rho / d n_j = A w_j K(r_j) u_j,
+//   d rho / d q_j = A w_j [-K(r_j) (n_j - c_j u_j) / eta_j - c_j K'(r_j) u_j / xi],
+//   d rho / d xi  = -(2 rho + A sum_j w_j c_j K'(r_j) r_j) / xi,   d xi / d q* = -u*,
+// with A = lambda / (2 pi sigma xi^2), K = G P / (1 + r^2)^2 as in the sum and
+//   K' = K (-(r - 1) / sigma^2 - 4 r / (1 + r^2)) + G (-2 r + i s) / (1 + r^2)^2.
+__device__ __forceinline__ void kernel_and_slope(double r, double sig2inv, double s, double& kre, double& kim,
+                                                 double& dre, double& dim) {
+    const double x = r - 1.0;
+    const double G = exp(-0.5 * x * x * sig2inv);
+    const double den = 1.0 + r * r;
+    const double gi = G / (den * den);
+    kre = gi * (1.0 - r * r);
+    kim = gi * (s * r);
+    const double f = -x * sig2inv - 4.0 * r / den;
+    dre = kre * f - 2.0 * r * gi;
+    dim = kim * f + s * gi;
+}
+
+// A block per brick.  Pass 1 as in the build; a node pass over the contact
+// ball gives rho and the xi term, added to the nearest sample's position
+// gradient; a sample pass puts the brick's live nodes in LDS, and each
+// thread owns one sample of a visited tile and sums its gradient over those
+// nodes.  Sums across bricks go through FP64 atomics (their order varies, so
+// the last bits of the gradients may vary between runs).
+template <typename T>
+__global__ __launch_bounds__(kSdfBlock) void sdf_adjoint_kernel(const double* __restrict__ q,
+                                                                const double* __restrict__ nrm,
+                                                                const double* __restrict__ w, SampleTiles st,
+                                                                int64_t ns, GridDesc g, ParamDesc prm,
+                                                                const cplx<T>* __restrict__ cot,
+                                                                double* __restrict__ gq, double* __restrict__ gn,
+                                                                double* __restrict__ gw) {
+    __shared__ v4<double> sq[2 * kSdfTile];
+    __shared__ int sidx[kSdfTile];
+    __shared__ int tflag[kSdfBlock];
+    __shared__ double red[kSdfBlock / 64];
+    __shared__ v4<double> nodep[kSdfBlock];  // (px, py, pz, 1 / xi)
+    __shared__ v4<double> nodeg[kSdfBlock];  // (A g.re, A g.im, ball radius^2 or -1, s)
+    static_assert(kSdfTile == kSdfBlock, "one sample per thread in the sample pass");
+
+    const Brick br = brick_shape(g.nz);
+    const int nbx = (g.nx + br.bx - 1) / br.bx, nby = (g.ny + br.by - 1) / br.by;
+    const int blk = blockIdx.x;
+    const int i0 = (blk % nbx) * br.bx, j0 = ((blk / nbx) % nby) * br.by, k0 = (blk / (nbx * nby)) * br.bz;
+    const int li = threadIdx.x % br.bx, lj = (threadIdx.x / br.bx) % br.by, lk = threadIdx.x / (br.bx * br.by);
+    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+    const bool valid = i < g.nx && j < g.ny && k < g.nz;
+    const double cx = g.ox + g.h * i0, cy = g.oy + g.h * j0, cz = g.oz + g.h * k0;
+    const double px = cx + g.h * li, py = cy + g.h * lj, pz = cz + g.h * lk;
+    const double bl[3] = {cx, cy, cz};
+    const double bh[3] = {cx + g.h * (min(br.bx, g.nx - i0) - 1), cy + g.h * (min(br.by, g.ny - j0) - 1),
+                          cz + g.h * (min(br.bz, g.nz - k0) - 1)};
+
+    double best;
+    int jbest;
+    nearest_pass(st, ns, bl, bh, px, py, pz, sq, sidx, tflag, red, best, jbest);
+    const int64_t jb = jbest;
+    const double ex = px - q[3 * jb], ey = py - q[3 * jb + 1], ez = pz - q[3 * jb + 2];
+    const double dot = ex * nrm[3 * jb] + ey * nrm[3 * jb + 1] + ez * nrm[3 * jb + 2];
+    const int pmc = dot > 0.0 ? 1 : (dot < 0.0 ? -1 : 0);
+    const double xi = sqrt(best);
+    const cplx<T> gt = valid ? cot[(int64_t(k) * g.ny + j) * g.nx + i] : mk(T(0), T(0));
+    const double g_re = double(gt.re), g_im = double(gt.im);
+    const bool act = valid && pmc != 0 && xi >= prm.xi_floor && (g_re != 0.0 || g_im != 0.0);
+    const double r2max = (1.0 + prm.eps) * (1.0 + prm.eps) * best;
+    const double lam = pmc > 0 ? prm.lambda1 : -prm.lambda2;
+    const double sgn = pmc > 0 ? -2.0 : 2.0;
+    const double A = lam / (2.0 * 3.14159265358979323846 * prm.sigma * best);
+    const double inv_xi = 1.0 / xi;
+    const double sig2inv = 1.0 / (prm.sigma * prm.sigma);
+    const double r2brick = block_reduce<true>(act ? r2max : -1.0, red) * (1.0 + 1e-9);
+    if (r2brick < 0.0) return;  // uniform: no node of the brick contributes
+
+    // ---- node pass: rho / A and sum_j w_j c_j K'(r_j) r_j over the ball
+    double rr = 0.0, ri = 0.0, sr = 0.0, si = 0.0;
+    for (int64_t c0 = 0; c0 < st.ntile; c0 += kSdfBlock) {
+        const int64_t tc = c0 + threadIdx.x;
+        __syncthreads();
+        tflag[threadIdx.x] = tc < st.ntile && box_dmin2(bl, bh, st.box + 6 * tc) <= r2brick;
+        __syncthreads();
+        const int nchunk = int(st.ntile - c0 < kSdfBlock ? st.ntile - c0 : kSdfBlock);
+        for (int kk = 0; kk < nchunk; ++kk) {
+            if (!tflag[kk]) continue;  // uniform across the block
+            const int64_t t0 = (c0 + kk) * kSdfTile;
+            const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+            __syncthreads();
+            for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
+                const int64_t s = t0 + a;
+                sq[a] = v4<double>{st.qs[3 * s], st.qs[3 * s + 1], st.qs[3 * s + 2], 0.0};
+                sq[kSdfTile + a] = v4<double>{st.wn[3 * s], st.wn[3 * s + 1], st.wn[3 * s + 2], 0.0};
+            }
+            __syncthreads();
+            if (act) {
+                for (int a = 0; a < cnt; ++a) {
+                    const v4<double> sp = sq[a];
+                    const double dx = px - sp.x, dy = py - sp.y, dz = pz - sp.z;
+                    const double d2 = dx * dx + dy * dy + dz * dz;
+                    if (d2 <= r2max) {
+                        const v4<double> wv = sq[kSdfTile + a];
+                        const double eta = sqrt(d2);
+                        const double wc = (dx * wv.x + dy * wv.y + dz * wv.z) / eta;  // w_j c_j
+                        const double r = eta * inv_xi;
+                        double kre, kim, dre, dim;
+                        kernel_and_slope(r, sig2inv, sgn, kre, kim, dre, dim);
+                        rr += wc * kre;
+                        ri += wc * kim;
+                        sr += wc * dre * r;
+                        si += wc * dim * r;
+                    }
+                }
+            }
+        }
+    }
+    if (act) {
+        // d rho / d xi = -(2 A rr + A sr) / xi (complex), then Re(g ...) along -u*
+        const double dre = -A * (2.0 * rr + sr) * inv_xi, dim = -A * (2.0 * ri + si) * inv_xi;
+        const double coef = (g_re * dre - g_im * dim) * inv_xi;
+        atomicAdd(gq + 3 * jb, -coef * ex);
+        atomicAdd(gq + 3 * jb + 1, -coef * ey);
+        atomicAdd(gq + 3 * jb + 2, -coef * ez);
+    }
+
+    // ---- sample pass: the brick's live nodes in LDS, one sample per thread
+    __syncthreads();
+    nodep[threadIdx.x] = v4<double>{px, py, pz, inv_xi};
+    nodeg[threadIdx.x] = v4<double>{A * g_re, A * g_im, act ? r2max : -1.0, sgn};
+    for (int64_t c0 = 0; c0 < st.ntile; c0 += kSdfBlock) {
+        const int64_t tc = c0 + threadIdx.x;
+        __syncthreads();
+        tflag[threadIdx.x] = tc < st.ntile && box_dmin2(bl, bh, st.box + 6 * tc) <= r2brick;
+        __syncthreads();
+        const int nchunk = int(st.ntile - c0 < kSdfBlock ? st.ntile - c0 : kSdfBlock);
+        for (int kk = 0; kk < nchunk; ++kk) {
+            if (!tflag[kk]) continue;  // uniform across the block
+            const int64_t t0 = (c0 + kk) * kSdfTile;
+            const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+            if (int(threadIdx.x) >= cnt) continue;
+            const int64_t sj = st.js[t0 + threadIdx.x];
+            const double qx = q[3 * sj], qy = q[3 * sj + 1], qz = q[3 * sj + 2];
+            const double nx = nrm[3 * sj], ny = nrm[3 * sj + 1], nz = nrm[3 * sj + 2];
+            const double wj = w[sj];
+            double aq0 = 0.0, aq1 = 0.0, aq2 = 0.0, an0 = 0.0, an1 = 0.0, an2 = 0.0, aw = 0.0;
+            bool any = false;
+            for (int nd = 0; nd < kSdfBlock; ++nd) {
+                const v4<double> ng = nodeg[nd];
+                if (ng.z < 0.0) continue;  // the same node for every thread: uniform
+                const v4<double> np = nodep[nd];
+                const double dx = np.x - qx, dy = np.y - qy, dz = np.z - qz;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                if (d2 > ng.z) continue;
+                any = true;
+                const double ie = 1.0 / sqrt(d2);
+                const double ux = dx * ie, uy = dy * ie, uz = dz * ie;
+                const double c = ux * nx + uy * ny + uz * nz;
+                const double r = d2 * ie * np.w;
+                double kre, kim, dre, dim;
+                kernel_and_slope(r, sig2inv, ng.w, kre, kim, dre, dim);
+                const double gk = ng.x * kre - ng.y * kim;    // Re(A g K)
+                const double gkp = ng.x * dre - ng.y * dim;   // Re(A g K')
+                aw += c * gk;
+                const double wg = wj * gk;
+                an0 += wg * ux;
+                an1 += wg * uy;
+                an2 += wg * uz;
+                const double t1 = -wg * ie, t2 = -wj * c * gkp * np.w;
+                aq0 += t1 * (nx - c * ux) + t2 * ux;
+                aq1 += t1 * (ny - c * uy) + t2 * uy;
+                aq2 += t1 * (nz - c * uz) + t2 * uz;
+            }
+            if (any) {
+                atomicAdd(gq + 3 * sj, aq0);
+                atomicAdd(gq + 3 * sj + 1, aq1);
+                atomicAdd(gq + 3 * sj + 2, aq2);
+                atomicAdd(gn + 3 * sj, an0);
+                atomicAdd(gn + 3 * sj + 1, an1);
+                atomicAdd(gn + 3 * sj + 2, an2);
+                atomicAdd(gw + sj, aw);
+            }
+        }
     }
 }
 
@@ -358,13 +556,9 @@ inline SdfWs sdf_ws_layout(int64_t n) {
     return L;
 }
 
-}  // namespace
-
-size_t sdf_build_workspace_bytes(int64_t ns) { return sdf_ws_layout(ns).total; }
-
-template <typename T>
-hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
-                            const ParamDesc& p, void* rho_out, void* ws, hipStream_t s) {
+// Morton order, sorted copies and tile boxes in the workspace
+hipError_t prepare_tiles(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g, void* ws,
+                         hipStream_t s, SampleTiles* st) {
     const SdfWs L = sdf_ws_layout(ns);
     char* base = static_cast<char*>(ws);
     auto* keys_in = reinterpret_cast<unsigned*>(base + L.keys_in);
@@ -387,17 +581,52 @@ hipError_t launch_sdf_build(const double* q, const double* n, const double* w, i
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(sample_gather_kernel, dim3(gb), dim3(256), 0, s, q, n, w, vals_out, ns, qs, wn);
     hipLaunchKernelGGL(tile_box_kernel, dim3(unsigned((ntile + 63) / 64)), dim3(64), 0, s, qs, ns, ntile, box);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const SampleTiles st{qs, wn, vals_out, box, ntile};
-    const Brick br = brick_shape(g.nz);
-    const int64_t blocks = int64_t((g.nx + br.bx - 1) / br.bx) * ((g.ny + br.by - 1) / br.by) *
-                           ((g.nz + br.bz - 1) / br.bz);
-    hipLaunchKernelGGL(sdf_build_kernel<T>, dim3(unsigned(blocks)), dim3(kSdfBlock), 0, s, q, n, st, ns, g, p,
-                       static_cast<cplx<T>*>(rho_out));
+    *st = SampleTiles{qs, wn, vals_out, box, ntile};
     return hipGetLastError();
 }
 
+int64_t brick_count(const GridDesc& g) {
+    const Brick br = brick_shape(g.nz);
+    return int64_t((g.nx + br.bx - 1) / br.bx) * ((g.ny + br.by - 1) / br.by) * ((g.nz + br.bz - 1) / br.bz);
+}
+
+}  // namespace
+
+size_t sdf_build_workspace_bytes(int64_t ns) { return sdf_ws_layout(ns).total; }
+
+template <typename T>
+hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
+                            const ParamDesc& p, void* rho_out, void* ws, hipStream_t s) {
+    SampleTiles st{};
+    hipError_t e = prepare_tiles(q, n, w, ns, g, ws, s, &st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sdf_build_kernel<T>, dim3(unsigned(brick_count(g))), dim3(kSdfBlock), 0, s, q, n, st, ns, g,
+                       p, static_cast<cplx<T>*>(rho_out));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sdf_adjoint(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
+                              const ParamDesc& p, const void* cot, double* grad_q, double* grad_n, double* grad_w,
+                              void* ws, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(grad_q, 0, sizeof(double) * 3 * size_t(ns), s);
+    if (e == hipSuccess) e = hipMemsetAsync(grad_n, 0, sizeof(double) * 3 * size_t(ns), s);
+    if (e == hipSuccess) e = hipMemsetAsync(grad_w, 0, sizeof(double) * size_t(ns), s);
+    if (e != hipSuccess) return e;
+    SampleTiles st{};
+    e = prepare_tiles(q, n, w, ns, g, ws, s, &st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sdf_adjoint_kernel<T>, dim3(unsigned(brick_count(g))), dim3(kSdfBlock), 0, s, q, n, w, st,
+                       ns, g, p, static_cast<const cplx<T>*>(cot), grad_q, grad_n, grad_w);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sdf_adjoint<float>(const double*, const double*, const double*, int64_t, const GridDesc&,
+                                              const ParamDesc&, const void*, double*, double*, double*, void*,
+                                              hipStream_t);
+template hipError_t launch_sdf_adjoint<double>(const double*, const double*, const double*, int64_t,
+                                               const GridDesc&, const ParamDesc&, const void*, double*, double*,
+                                               double*, void*, hipStream_t);
 template hipError_t launch_sdf_build<float>(const double*, const double*, const double*, int64_t, const GridDesc&,
                                             const ParamDesc&, void*, void*, hipStream_t);
 template hipError_t launch_sdf_build<double>(const double*, const double*, const double*, int64_t, const GridDesc&,

@@ -22,6 +22,12 @@ size_t sdf_build_workspace_bytes(int64_t ns);
 template <typename T>
 hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
                             const ParamDesc& p, void* rho_out, void* ws, hipStream_t s);
+// adjoint of sdf_build: gradients (FP64, zeroed here) of Re sum_p cot(p) rho(p)
+// with respect to the sample positions, normals and weights
+template <typename T>
+hipError_t launch_sdf_adjoint(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
+                              const ParamDesc& p, const void* cot, double* grad_q, double* grad_n, double* grad_w,
+                              void* ws, hipStream_t s);
 
 // ---- rotations: quaternions (FP64, device) -> R (FP64 and cast to T), n x 9 row-major
 template <typename T>

@@ -10,6 +10,7 @@ from oracle import direct as od
 from oracle import grad as og
 from oracle import peak as op
 from oracle import sdf as osdf
+from oracle import sdf_adjoint as oadj
 from oracle import spread as osp
 from workloads import configs as C
 from workloads import shapes
@@ -85,6 +86,39 @@ def test_sdf_build_sample_tile_edges(ctxs, dtype, count):
     rep = sdf_compare(rho, s, grid, params, rel, band)
     flush_print(rep)
     assert rep["ok"], rep
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("case", ["small_3d_ragged", "sphere_257", "peg_2d"])
+def test_sdf_build_adjoint_matches_oracle(ctxs, dtype, case):
+    """Shape gradients of L = Re sum_p cot(p) rho(p) with respect to the
+    samples' positions, normals and weights, against the oracle adjoint (which
+    is pinned by finite differences on the CPU).  FP64 arithmetic in both
+    contexts; the FP32 context rounds the cotangent."""
+    ctx = ctxs[dtype]
+    if case == "small_3d_ragged":
+        pair = C.small_3d(seed=1, n=16, n_m=6)
+        s, grid, params = pair.fixed.samples, C.GridSpec((15, 13, 11), (-7.3, -6.1, -5.2), 1.0), pair.params
+    elif case == "sphere_257":
+        rng = np.random.default_rng(257)
+        v = rng.normal(size=(257, 3))
+        v /= np.linalg.norm(v, axis=1, keepdims=True)
+        s = shapes.PointSamples(4.0 * v + 0.3, v.copy(), rng.uniform(0.5, 1.5, size=257))
+        grid, params = C.GridSpec((14, 13, 12), (-6.5, -6.0, -5.5), 1.0), C.SDFParams(xi_floor=0.25)
+    else:
+        pair = C.peg_in_hole_2d(seed=0)
+        s, grid, params = pair.moving.samples, pair.moving.grid, pair.params
+    nx, ny, nz = grid.n
+    rng = np.random.default_rng(11)
+    cot = rng.normal(size=(nz, ny, nx)) + 1j * rng.normal(size=(nz, ny, nx))
+    if dtype == "f32":
+        cot = cot.astype(np.complex64).astype(np.complex128)  # what the context sees
+    flush_print("sdf_build_adjoint", dtype, case, grid.n, s.count)
+    gq, gn, gw = (to_np(a) for a in ctx.sdf_build_adjoint(s.q, s.n, s.w, grid, params, cot))
+    rq, rn, rw = oadj.sdf_adjoint_grid(s, grid, params, cot)
+    for got, ref in ((gq, rq), (gn, rn), (gw, rw)):
+        scale = np.abs(ref).max()
+        assert np.max(np.abs(got - ref)) <= 1e-9 * scale, (float(np.max(np.abs(got - ref)) / scale))
 
 
 # ----------------------------------------------------------------------------- FFT
