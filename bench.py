@@ -432,6 +432,25 @@ def main():
                 "same_best": bool(int(np.argmax(sw)) == int(np.argmax(sd))),
                 "spearman": round(spearman, 4)}
 
+        # --- shape gradients: the cotangent of 32 refined poses' scores with
+        # respect to the moving coefficients, then the SDF adjoint over the
+        # moving part's boundary samples (both timed with events)
+        sp = torch.tensor(np.concatenate([out["refined"][:32].cpu().numpy(), pair.quats[:32]], axis=1),
+                          dtype=torch.float64, device=dev)
+        ctx.score_grad_coef(rho_f, fx.grid, rho_m, w, mv.grid, sp)
+        ctx.sdf_build_adjoint(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params, rho_m)
+        torch.cuda.synchronize()
+        a0, a1, a2 = ev(), ev(), ev()
+        a0.record(stream)
+        _, _, gco, _ = ctx.score_grad_coef(rho_f, fx.grid, rho_m, w, mv.grid, sp)
+        a1.record(stream)
+        ctx.sdf_build_adjoint(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params, w * gco)
+        a2.record(stream)
+        torch.cuda.synchronize()
+        report["shape_grad"] = {"poses": 32, "moving_samples": mv.samples.count,
+                                "cotangent_ms": round(a0.elapsed_time(a1), 3),
+                                "sdf_adjoint_ms": round(a1.elapsed_time(a2), 3)}
+
         # --- pose-gradient evaluations: forward + backward through the adjoint kernel
         B = args.grad_poses
         top = ctx.topk(out["score"], min(n_rot, B)).long()
@@ -562,6 +581,7 @@ def main():
             "pose_grad_evals_per_s": round(report["pose_grad_evals_per_s"], 1),
             "fp32_vs_fp64": report["fp32_vs_fp64"],
             "window_effect": report.get("window_effect"),
+            "shape_grad": report.get("shape_grad"),
             "stage_GBs": round(report["stage_GBs"], 1),
             "correlation_stage": report["correlation_stage"],
             "slab_reach": report["slab_reach"],

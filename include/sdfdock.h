@@ -318,6 +318,20 @@ int score_grad(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
                void *score, double *grad_pose, void *grad_w, const double *grad_scale,
                sdf_stream stream);
 
+/* As score_grad, with the cotangent of the score with respect to the moving
+ * part's coefficients c_k = w_k rho_M(x_k) (for gradients of rho_M itself,
+ * and through sdf_build_adjoint, of the moving part's boundary samples):
+ *   grad_c[k] = sum_b s_b Phi_b(R_b x_k / h + t_b)   (complex, N_M^3, context
+ *   precision; s_b = grad_scale[b] or 1),
+ * so that d(sum_b s_b f_b) = Re sum_k grad_c[k] dc_k.  The cotangent of
+ * rho_M(x_k) is w_k grad_c[k]; grad_w (may be NULL) receives
+ * Re(rho_M(x_k) grad_c[k]), as score_grad computes it.  grad_pose may be NULL.
+ * Errors: as score_grad, and SDF_EINVAL for a NULL grad_c. */
+int score_grad_coef(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
+                    const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
+                    const double *poses, int64_t B, void *score, double *grad_pose, void *grad_c,
+                    void *grad_w, const double *grad_scale, sdf_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

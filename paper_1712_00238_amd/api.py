@@ -259,6 +259,28 @@ class Context:
         return out
 
     # ------------------------------------------------------------------ refinement
+    def score_grad_coef(self, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, want_pose=False,
+                        want_w=False, grad_scale=None):
+        """score_grad with the cotangent of sum_b s_b f_b with respect to the
+        moving coefficients c_k = w_k rho_M(x_k): grad_c[k] = sum_b s_b
+        Phi_b(y_k), complex, shaped like rho_moving.  Returns (score, grad_pose
+        or None, grad_c, grad_w or None)."""
+        poses = self._dev(poses, torch.float64).reshape(-1, 7)
+        B = poses.shape[0]
+        rf = self._dev(rho_fixed, self.cplx)
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        score = torch.empty(B, dtype=self.real, device=self.device)
+        gp = torch.empty((B, 7), dtype=torch.float64, device=self.device) if want_pose else None
+        gc = torch.empty(rm.shape, dtype=self.cplx, device=self.device)
+        gw = torch.empty(wm.shape, dtype=self.real, device=self.device) if want_w else None
+        gs = None if grad_scale is None else self._dev(grad_scale, torch.float64)
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.score_grad_coef(self.handle, _ptr(rf), ctypes.byref(gf), _ptr(rm), _ptr(wm),
+                                             ctypes.byref(gm), _ptr(poses), B, _ptr(score), _ptr(gp), _ptr(gc),
+                                             _ptr(gw), _ptr(gs), _stream(self.device)))
+        return score, gp, gc, gw
+
     def score_grad(self, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, want_pose=True,
                    want_w=False, grad_scale=None):
         poses = self._dev(poses, torch.float64).reshape(-1, 7)

@@ -1128,9 +1128,10 @@ int sdf_topk(sdf_ctx ctx, const void* scores, int64_t n, int64_t k, int32_t* idx
     return SDF_OK;
 }
 
-int score_grad(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
-               const void* w_moving, const sdf_grid* g_moving, const double* poses, int64_t B, void* score,
-               double* grad_pose, void* grad_w, const double* grad_scale, sdf_stream stream) {
+static int score_grad_impl(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
+                           const void* w_moving, const sdf_grid* g_moving, const double* poses, int64_t B,
+                           void* score, double* grad_pose, void* grad_w, void* grad_c, const double* grad_scale,
+                           sdf_stream stream) {
     if (!rho_fixed || !rho_moving || !w_moving || !poses || !score) return fail(ctx, SDF_EINVAL, "NULL array");
     if (B <= 0) return fail(ctx, SDF_EINVAL, "B must be > 0");
     if (B > (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "B too large");
@@ -1142,22 +1143,39 @@ int score_grad(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, cons
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool planar = g_fixed->n[2] == 1;
     const int N = g_fixed->n[0], nm = g_moving->n[0];
-    const bool want_w = grad_w != nullptr;
-    size_t need = ctx->dtype == SDF_F64 ? sdf::grad_workspace_bytes<double>(B, N, nm, planar, want_w)
-                                        : sdf::grad_workspace_bytes<float>(B, N, nm, planar, want_w);
+    const int wmode = grad_c ? 2 : (grad_w ? 1 : 0);
+    size_t need = ctx->dtype == SDF_F64 ? sdf::grad_workspace_bytes<double>(B, N, nm, planar, wmode)
+                                        : sdf::grad_workspace_bytes<float>(B, N, nm, planar, wmode);
     rc = ensure_ws(ctx, need);
     if (rc) return rc;
     hipError_t e;
     if (ctx->dtype == SDF_F64)
         e = sdf::launch_score_grad<double>(rho_fixed, N, planar, rho_moving, static_cast<const double*>(w_moving), nm,
                                            poses, B, static_cast<double*>(score), grad_pose,
-                                           static_cast<double*>(grad_w), grad_scale, ctx->ws, s);
+                                           static_cast<double*>(grad_w), static_cast<double*>(grad_c), grad_scale,
+                                           ctx->ws, s);
     else
         e = sdf::launch_score_grad<float>(rho_fixed, N, planar, rho_moving, static_cast<const float*>(w_moving), nm,
                                           poses, B, static_cast<float*>(score), grad_pose,
-                                          static_cast<float*>(grad_w), grad_scale, ctx->ws, s);
+                                          static_cast<float*>(grad_w), static_cast<float*>(grad_c), grad_scale,
+                                          ctx->ws, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "score_grad");
     return SDF_OK;
+}
+
+int score_grad(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
+               const void* w_moving, const sdf_grid* g_moving, const double* poses, int64_t B, void* score,
+               double* grad_pose, void* grad_w, const double* grad_scale, sdf_stream stream) {
+    return score_grad_impl(ctx, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, B, score, grad_pose,
+                           grad_w, nullptr, grad_scale, stream);
+}
+
+int score_grad_coef(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
+                    const void* w_moving, const sdf_grid* g_moving, const double* poses, int64_t B, void* score,
+                    double* grad_pose, void* grad_c, void* grad_w, const double* grad_scale, sdf_stream stream) {
+    if (!grad_c) return fail(ctx, SDF_EINVAL, "grad_c is NULL");
+    return score_grad_impl(ctx, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, B, score, grad_pose,
+                           grad_w, grad_c, grad_scale, stream);
 }
 
 }  // extern "C"

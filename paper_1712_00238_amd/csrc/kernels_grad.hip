@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kGBlock) void grad_tile_kernel(const cplx<T>* __res
     int64_t ks[kSPT];
     T xb[kSPT][3];
     cplx<T> ck[kSPT], rm[kSPT];
-    T gw[kSPT];
+    T gw[kSPT], gwi[kSPT];  // wmode 1: Re(rho_M Phi) sums; 2: Phi sums (re, im)
 #pragma unroll
     for (int s = 0; s < kSPT; ++s) {
         const int64_t k = int64_t(sb) * kSamplesPerBlock + s * kGBlock + threadIdx.x;
@@ -82,6 +82,7 @@ __global__ __launch_bounds__(kGBlock) void grad_tile_kernel(const cplx<T>* __res
         rm[s] = k < K ? rho_m[kk] : mk(T(0), T(0));
         ck[s] = rm[s] * (k < K ? w_m[kk] : T(0));
         gw[s] = T(0);
+        gwi[s] = T(0);
     }
 
     __shared__ double red[kGBlock / 64][kNAcc];
@@ -169,7 +170,11 @@ __global__ __launch_bounds__(kGBlock) void grad_tile_kernel(const cplx<T>* __res
                 acc[4] += wv[1] * g2 - wv[2] * g1;
                 acc[5] += wv[2] * g0 - wv[0] * g2;
                 acc[6] += wv[0] * g1 - wv[1] * g0;
-                if (want_w) gw[s] += T(sc) * (rm[s] * phi).re;
+                if (want_w == 1) gw[s] += T(sc) * (rm[s] * phi).re;
+                if (want_w == 2) {
+                    gw[s] += T(sc) * phi.re;
+                    gwi[s] += T(sc) * phi.im;
+                }
             }
         }
         // block reduction of the per-pose sums (FP64)
@@ -189,7 +194,13 @@ __global__ __launch_bounds__(kGBlock) void grad_tile_kernel(const cplx<T>* __res
     if (GRAD && want_w) {
 #pragma unroll
         for (int s = 0; s < kSPT; ++s)
-            if (ks[s] < K) wpart[int64_t(pb) * K + ks[s]] = gw[s];
+            if (ks[s] < K) {
+                if (want_w == 1) wpart[int64_t(pb) * K + ks[s]] = gw[s];
+                else {
+                    wpart[2 * (int64_t(pb) * K + ks[s])] = gw[s];
+                    wpart[2 * (int64_t(pb) * K + ks[s]) + 1] = gwi[s];
+                }
+            }
     }
 }
 
@@ -300,7 +311,7 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
     const float xb0 = float(i) - half, xb1 = float(j) - half, xb2 = float(k) - half;
     const cplx<float> rm = ok ? rho_m[ks] : mk(0.f, 0.f);
     const cplx<float> ck = rm * (ok ? w_m[ks] : 0.f);
-    float gw = 0.f;
+    float gw = 0.f, gwi = 0.f;  // wmode 1: Re(rho_M Phi) sum; 2: Phi sum (re, im)
     // body coordinates of the tile corner (a clipped tile keeps the full
     // tile's bounds, which contain its samples)
     const float xlo0 = float(t0x) - half, xlo1 = float(t0y) - half, xlo2 = float(t0z) - half;
@@ -425,7 +436,11 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
                 acc[4] = w1 * g2 - w2 * g1;
                 acc[5] = w2 * g0 - w0 * g2;
                 acc[6] = w0 * g1 - w1 * g0;
-                if (want_w) gw += float(sc) * (rm * phi).re;
+                if (want_w == 1) gw += float(sc) * (rm * phi).re;
+                if (want_w == 2) {
+                    gw += float(sc) * phi.re;
+                    gwi += float(sc) * phi.im;
+                }
             }
         }
         // block reduction: rows of 16 lanes (DPP), then 32 row sums per value
@@ -443,7 +458,11 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
             part[(b * nsb + sb) * kNAcc + threadIdx.x] = v;
         }
     }
-    if (GRAD && want_w && ok) wpart[int64_t(pb) * K + ks] = gw;
+    if (GRAD && want_w == 1 && ok) wpart[int64_t(pb) * K + ks] = gw;
+    if (GRAD && want_w == 2 && ok) {
+        wpart[2 * (int64_t(pb) * K + ks)] = gw;
+        wpart[2 * (int64_t(pb) * K + ks) + 1] = gwi;
+    }
 }
 
 // Per pose: reduce the sample-tile partials, apply the chain rule through
@@ -489,6 +508,29 @@ __global__ void wsum_kernel(const T* __restrict__ wpart, int npb, int64_t K, T* 
     grad_w[k] = s;
 }
 
+// complex tile partials: grad_c[k] = sum over pose tiles of Phi sums
+template <typename T>
+__global__ void csum_kernel(const T* __restrict__ wpart, int npb, int64_t K, T* __restrict__ grad_c) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    T re = T(0), im = T(0);
+    for (int p = 0; p < npb; ++p) {
+        re += wpart[2 * (int64_t(p) * K + k)];
+        im += wpart[2 * (int64_t(p) * K + k) + 1];
+    }
+    grad_c[2 * k] = re;
+    grad_c[2 * k + 1] = im;
+}
+
+// grad_w[k] = Re(rho_M[k] grad_c[k])
+template <typename T>
+__global__ void w_from_c_kernel(const cplx<T>* __restrict__ rho_m, const T* __restrict__ grad_c, int64_t K,
+                                T* __restrict__ grad_w) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    grad_w[k] = rho_m[k].re * grad_c[2 * k] - rho_m[k].im * grad_c[2 * k + 1];
+}
+
 }  // namespace
 
 // the LDS-staged kernel serves 3D FP32 poses; FP64 and planar use the tile kernel
@@ -511,20 +553,20 @@ void grad_tiles(int64_t B, int N, int n_m, bool planar, int64_t* nsb, int64_t* n
 }
 
 template <typename T>
-size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, bool want_w) {
+size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, int wmode) {
     const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
     int64_t nsb, npb;
     grad_tiles<T>(B, N, n_m, planar, &nsb, &npb);
     size_t bytes = size_t(B * nsb * kNAcc) * sizeof(double);
     bytes = (bytes + 255) / 256 * 256;
-    if (want_w) bytes += (size_t(npb * K) * sizeof(T) + 255) / 256 * 256;
+    if (wmode) bytes += (size_t(npb * K) * sizeof(T) * size_t(wmode) + 255) / 256 * 256;
     if (use_box<T>(planar, N)) bytes += size_t(B) * sizeof(BoxPose);
     return bytes + 256;
 }
 
 template <typename T>
 hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* rho_m, const T* w_m, int n_m,
-                             const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w,
+                             const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w, T* grad_c,
                              const double* grad_scale, void* ws, hipStream_t s) {
     const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
     int64_t nsb64, npb64;
@@ -534,17 +576,19 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
     size_t off = size_t(B * nsb * kNAcc) * sizeof(double);
     off = (off + 255) / 256 * 256;
     T* wpart = reinterpret_cast<T*>(static_cast<char*>(ws) + off);
-    if (grad_w) off += (size_t(npb64 * K) * sizeof(T) + 255) / 256 * 256;
+    // weight mode: 2 sums Phi (complex) per sample, from which grad_w follows;
+    // 1 sums Re(rho_M Phi) directly
+    const int ww = grad_c ? 2 : (grad_w ? 1 : 0);
+    if (ww) off += (size_t(npb64 * K) * sizeof(T) * size_t(ww) + 255) / 256 * 256;
     BoxPose* bpose = reinterpret_cast<BoxPose*>(static_cast<char*>(ws) + off);
     if (use_box<T>(planar, N)) {
         hipLaunchKernelGGL(box_pose_kernel, dim3(unsigned((B + 127) / 128)), dim3(128), 0, s, poses, B, bpose);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    const bool grad = grad_pose != nullptr || grad_w != nullptr;
+    const bool grad = grad_pose != nullptr || ww != 0;
     const auto* rf = static_cast<const cplx<T>*>(rho_f);
     const auto* rm = static_cast<const cplx<T>*>(rho_m);
-    const int ww = grad_w ? 1 : 0;
     // pose tiles run in launches of at most 65535 along grid y
     for (int pb0 = 0; pb0 < npb; pb0 += 65535) {
         const dim3 grid{unsigned(nsb), unsigned(std::min(npb - pb0, 65535)), 1u};
@@ -576,18 +620,23 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
         hipLaunchKernelGGL((grad_finish_kernel<T, false>), g2, dim3(128), 0, s, part, nsb, poses, B, score, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if (grad_w) {
-        hipLaunchKernelGGL(wsum_kernel<T>, dim3(unsigned((K + 255) / 256)), dim3(256), 0, s, wpart, npb, K, grad_w);
-        e = hipGetLastError();
+    const dim3 gk(unsigned((K + 255) / 256));
+    if (ww == 1) {
+        hipLaunchKernelGGL(wsum_kernel<T>, gk, dim3(256), 0, s, wpart, npb, K, grad_w);
+    } else if (ww == 2) {
+        hipLaunchKernelGGL(csum_kernel<T>, gk, dim3(256), 0, s, wpart, npb, K, grad_c);
+        if (grad_w) hipLaunchKernelGGL(w_from_c_kernel<T>, gk, dim3(256), 0, s, rm, grad_c, K, grad_w);
     }
-    return e;
+    return hipGetLastError();
 }
 
-template size_t grad_workspace_bytes<float>(int64_t, int, int, bool, bool);
-template size_t grad_workspace_bytes<double>(int64_t, int, int, bool, bool);
+template size_t grad_workspace_bytes<float>(int64_t, int, int, bool, int);
+template size_t grad_workspace_bytes<double>(int64_t, int, int, bool, int);
 template hipError_t launch_score_grad<float>(const void*, int, bool, const void*, const float*, int, const double*,
-                                             int64_t, float*, double*, float*, const double*, void*, hipStream_t);
+                                             int64_t, float*, double*, float*, float*, const double*, void*,
+                                             hipStream_t);
 template hipError_t launch_score_grad<double>(const void*, int, bool, const void*, const double*, int, const double*,
-                                              int64_t, double*, double*, double*, const double*, void*, hipStream_t);
+                                              int64_t, double*, double*, double*, double*, const double*, void*,
+                                              hipStream_t);
 
 }  // namespace sdf

@@ -292,11 +292,11 @@ __device__ __forceinline__ void kernel_and_slope(double r, double sig2inv, doubl
                                                  double& dre, double& dim) {
     const double x = r - 1.0;
     const double G = exp(-0.5 * x * x * sig2inv);
-    const double den = 1.0 + r * r;
-    const double gi = G / (den * den);
+    const double iden = 1.0 / (1.0 + r * r);
+    const double gi = G * iden * iden;
     kre = gi * (1.0 - r * r);
     kim = gi * (s * r);
-    const double f = -x * sig2inv - 4.0 * r / den;
+    const double f = -x * sig2inv - 4.0 * r * iden;
     dre = kre * f - 2.0 * r * gi;
     dim = kim * f + s * gi;
 }
@@ -382,8 +382,9 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_adjoint_kernel(const double* __
                     const double d2 = dx * dx + dy * dy + dz * dz;
                     if (d2 <= r2max) {
                         const v4<double> wv = sq[kSdfTile + a];
-                        const double eta = sqrt(d2);
-                        const double wc = (dx * wv.x + dy * wv.y + dz * wv.z) / eta;  // w_j c_j
+                        const double ie = rsqrt(d2);
+                        const double eta = d2 * ie;
+                        const double wc = (dx * wv.x + dy * wv.y + dz * wv.z) * ie;  // w_j c_j
                         const double r = eta * inv_xi;
                         double kre, kim, dre, dim;
                         kernel_and_slope(r, sig2inv, sgn, kre, kim, dre, dim);
@@ -405,17 +406,23 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_adjoint_kernel(const double* __
         atomicAdd(gq + 3 * jb + 2, -coef * ez);
     }
 
-    // ---- sample pass: the brick's live nodes in LDS, one sample per thread
+    // ---- sample pass: the brick's live nodes in LDS, one sample per thread.
+    // Every brick is resident at once, so each starts its walk over the tiles
+    // at its own offset: bricks then add to different samples' gradients at a
+    // time instead of contending for the same addresses.
     __syncthreads();
     nodep[threadIdx.x] = v4<double>{px, py, pz, inv_xi};
     nodeg[threadIdx.x] = v4<double>{A * g_re, A * g_im, act ? r2max : -1.0, sgn};
-    for (int64_t c0 = 0; c0 < st.ntile; c0 += kSdfBlock) {
+    const int64_t nchunks = (st.ntile + kSdfBlock - 1) / kSdfBlock;
+    for (int64_t ci = 0; ci < nchunks; ++ci) {
+        const int64_t c0 = ((ci + blk) % nchunks) * kSdfBlock;
         const int64_t tc = c0 + threadIdx.x;
         __syncthreads();
         tflag[threadIdx.x] = tc < st.ntile && box_dmin2(bl, bh, st.box + 6 * tc) <= r2brick;
         __syncthreads();
         const int nchunk = int(st.ntile - c0 < kSdfBlock ? st.ntile - c0 : kSdfBlock);
-        for (int kk = 0; kk < nchunk; ++kk) {
+        for (int k1 = 0; k1 < nchunk; ++k1) {
+            const int kk = (k1 + blk) % nchunk;
             if (!tflag[kk]) continue;  // uniform across the block
             const int64_t t0 = (c0 + kk) * kSdfTile;
             const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
@@ -434,7 +441,7 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_adjoint_kernel(const double* __
                 const double d2 = dx * dx + dy * dy + dz * dz;
                 if (d2 > ng.z) continue;
                 any = true;
-                const double ie = 1.0 / sqrt(d2);
+                const double ie = rsqrt(d2);
                 const double ux = dx * ie, uy = dy * ie, uz = dz * ie;
                 const double c = ux * nx + uy * ny + uz * nz;
                 const double r = d2 * ie * np.w;

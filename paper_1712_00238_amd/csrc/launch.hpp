@@ -147,10 +147,12 @@ size_t topk_workspace_bytes(int64_t n);
 
 // ---- score_grad
 template <typename T>
-size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, bool want_w);
+size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, int wmode);
+// grad_c (may be NULL): complex per-sample sums of grad_scale_b Phi_b(y_k);
+// grad_w then follows as Re(rho_M grad_c)
 template <typename T>
 hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* rho_m, const T* w_m, int n_m,
-                             const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w,
+                             const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w, T* grad_c,
                              const double* grad_scale, void* ws, hipStream_t s);
 
 }  // namespace sdf

@@ -457,6 +457,79 @@ def test_autograd_function_pose_and_weight_paths(ctxs, dtype):
                                         eps=1e-6, atol=1e-6, rtol=1e-5)
 
 
+# ----------------------------------------------------------------------------- shape gradients
+
+def _phi_sum(rho_f, nm, poses, gs):
+    """sum_b s_b Phi_b(R_b x_k + t_b) per body node (oracle)."""
+    xb = osp.body_positions(nm, False)
+    acc = np.zeros(len(xb), dtype=np.complex128)
+    from oracle import rotation as orot
+    for b in range(len(poses)):
+        y = xb @ orot.quat_to_matrix(poses[b, 3:]).T + poses[b, :3]
+        val, _ = og.phi_and_grad(rho_f, y, want_grad=False)
+        acc += gs[b] * val
+    return acc
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,nm", [(16, 6), (24, 8)])
+def test_score_grad_coef_matches_oracle(ctxs, dtype, n, nm):
+    """The cotangent of sum_b s_b f_b with respect to the moving coefficients,
+    sum_b s_b Phi_b(y_k), on the tile kernel (N = 16) and the LDS-box kernel
+    (3D FP32, N = 24), with the derived weight gradient."""
+    ctx = ctxs[dtype]
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, False, 300 + n)
+    rng = np.random.default_rng(n)
+    B = 19
+    poses = np.concatenate([rng.uniform(-n, 2 * n, size=(B, 3)), wr.uniform_quaternions(B, 40 + n)], axis=1)
+    gs = rng.normal(size=B)
+    flush_print("score_grad_coef", dtype, n, nm)
+    _, _, gc, gw = ctx.score_grad_coef(rho_f, gf, rho_m, w, gm, poses, want_w=True, grad_scale=gs)
+    gc, gw = to_np(gc).reshape(-1), to_np(gw).reshape(-1)
+    ref = _phi_sum(rho_f, nm, poses, gs)
+    tol = 1e-10 if dtype == "f64" else 2e-5
+    assert np.max(np.abs(gc - ref)) <= tol * np.abs(ref).max()
+    gw_ref = np.real(rho_m.reshape(-1) * ref)
+    assert np.max(np.abs(gw - gw_ref)) <= tol * np.abs(gw_ref).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_shape_gradient_through_autograd(ctxs, dtype):
+    """d(sum_b g_b f_b) with respect to the moving part's boundary samples,
+    through sdf_field (sdf_build and its adjoint) and sdf_score (the moving
+    field's cotangent w_k sum_b g_b Phi_b): against the oracle adjoint applied
+    to the oracle cotangent."""
+    import torch
+    from paper_1712_00238_amd.autograd import sdf_field, sdf_score
+    ctx = ctxs[dtype]
+    pair = C.small_3d(seed=2, n=24, n_m=8)
+    fx, mv = pair.fixed, pair.moving
+    rho_f = osdf.sdf_grid(fx.samples, fx.grid, pair.params)
+    dev = torch.device("cuda")
+    real = torch.float64 if dtype == "f64" else torch.float32
+    cplx = torch.complex128 if dtype == "f64" else torch.complex64
+    rng = np.random.default_rng(8)
+    B = 6
+    poses = np.concatenate([rng.uniform(-3, 3, size=(B, 3)), wr.uniform_quaternions(B, 17)], axis=1)
+    g = rng.normal(size=B)
+    q = torch.tensor(mv.samples.q, dtype=torch.float64, device=dev, requires_grad=True)
+    nn = torch.tensor(mv.samples.n, dtype=torch.float64, device=dev, requires_grad=True)
+    ww = torch.tensor(mv.samples.w, dtype=torch.float64, device=dev, requires_grad=True)
+    rho_m = sdf_field(q, nn, ww, ctx, mv.grid, pair.params)
+    w_node = torch.ones(rho_m.shape, dtype=real, device=dev)
+    rf = torch.as_tensor(rho_f, dtype=cplx, device=dev)
+    p = torch.tensor(poses, dtype=torch.float64, device=dev)
+    flush_print("shape gradient", dtype)
+    score = sdf_score(p, w_node, ctx, rf, fx.grid, rho_m, mv.grid)
+    (score.double() * torch.as_tensor(g, device=dev)).sum().backward()
+    cot = _phi_sum(rho_f, mv.grid.n[0], poses, g).reshape(rho_m.shape)
+    rq, rn, rw = oadj.sdf_adjoint_grid(mv.samples, mv.grid, pair.params, cot)
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    for got, ref in ((q.grad, rq), (nn.grad, rn), (ww.grad, rw)):
+        got = got.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), float(np.max(np.abs(got - ref)) / np.abs(ref).max())
+
+
 # ----------------------------------------------------------------------------- end to end, planar
 
 def test_peg_in_hole_end_to_end_f64(ctxs):
