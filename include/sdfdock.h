@@ -332,6 +332,19 @@ int score_grad_coef(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
                     const double *poses, int64_t B, void *score, double *grad_pose, void *grad_c,
                     void *grad_w, const double *grad_scale, sdf_stream stream);
 
+/* Cotangent of sum_b s_b f_b with respect to the fixed part's field (the
+ * adjoint of the gather in score_grad): every f_b is linear in rho_F, so
+ *   grad_f(p) = sum_b s_b sum_k c_k B3(p - R_b x_k / h - t_b),   periodic,
+ * with c_k = w_k rho_M(x_k) and s_b = grad_scale[b] (or 1): complex, the fixed
+ * grid's size and layout, context precision, overwritten.  With
+ * sdf_build_adjoint it gives the fixed part's shape gradients.  Sums use
+ * atomic adds (the last bits may vary between runs).  Same constraints as
+ * score_grad; rho_fixed is not needed.
+ * Errors: SDF_EINVAL, SDF_ENOMEM, SDF_EHIP. */
+int score_grad_fixed(sdf_ctx ctx, const sdf_grid *g_fixed, const void *rho_moving, const void *w_moving,
+                     const sdf_grid *g_moving, const double *poses, int64_t B, const double *grad_scale,
+                     void *grad_f, sdf_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,3 +86,16 @@ def fd_gradient(fun, x, h: float = 1e-3) -> np.ndarray:
         e[i] = h
         g[i] = (fun(x + e) - fun(x - e)) / (2.0 * h)
     return g
+
+
+def fixed_cotangent(c, xb, poses, grad_scale, shape) -> np.ndarray:
+    """Cotangent of sum_b s_b f_b with respect to rho_F: f_b is linear in
+    rho_F, f_b = Re sum_p rho_F(p) sum_k c_k B3(p - y_kb), so the cotangent is
+    the periodic spread sum_b s_b sum_k c_k B3(p - y_kb), y_kb = R_b x_k + t_b."""
+    out = np.zeros(shape, dtype=np.complex128)
+    c = np.asarray(c, dtype=np.complex128).ravel()
+    for b, pose in enumerate(np.asarray(poses, dtype=np.float64).reshape(-1, 7)):
+        r = rotation.quat_to_matrix(pose[3:])
+        y = xb @ r.T + pose[:3]
+        out += grad_scale[b] * spread.spread(c, y, shape)
+    return out

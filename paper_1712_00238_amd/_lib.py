@@ -18,7 +18,7 @@ EXPORTS = ["sdf_ctx_create", "sdf_ctx_destroy", "sdf_last_error", "sdf_ctx_set_o
            "sdf_ctx_stats", "sdf_ctx_stats_reset",
            "sdf_build", "sdf_spectrum", "score_rotations", "score_pairs", "sdf_autotune", "score_volume",
            "sdf_spread", "sdf_fft", "sdf_topk", "score_grad", "score_rotations_direct", "sdf_build_adjoint",
-           "score_grad_coef"]
+           "score_grad_coef", "score_grad_fixed"]
 
 
 class SdfGrid(ctypes.Structure):
@@ -77,6 +77,7 @@ def load() -> ctypes.CDLL:
         "sdf_topk": ([vp, vp, i64, i64, vp, vp], ctypes.c_int),
         "score_grad": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "score_grad_coef": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "score_grad_fixed": ([vp, gp, vp, vp, gp, vp, i64, vp, vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

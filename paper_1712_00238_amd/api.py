@@ -281,6 +281,22 @@ class Context:
                                              _ptr(gw), _ptr(gs), _stream(self.device)))
         return score, gp, gc, gw
 
+    def score_grad_fixed(self, g_fixed, rho_moving, w_moving, g_moving, poses, grad_scale=None):
+        """Cotangent of sum_b s_b f_b with respect to rho_F: the periodic
+        spread sum_b s_b sum_k c_k B3(p - y_kb), complex, shaped like the fixed
+        grid (nz, ny, nx)."""
+        poses = self._dev(poses, torch.float64).reshape(-1, 7)
+        B = poses.shape[0]
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        nx, ny, nz = g_fixed.n
+        out = torch.empty((nz, ny, nx), dtype=self.cplx, device=self.device)
+        gs = None if grad_scale is None else self._dev(grad_scale, torch.float64)
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.score_grad_fixed(self.handle, ctypes.byref(gf), _ptr(rm), _ptr(wm), ctypes.byref(gm),
+                                              _ptr(poses), B, _ptr(gs), _ptr(out), _stream(self.device)))
+        return out
+
     def score_grad(self, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, want_pose=True,
                    want_w=False, grad_scale=None):
         poses = self._dev(poses, torch.float64).reshape(-1, 7)

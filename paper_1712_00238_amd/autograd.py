@@ -8,7 +8,8 @@ weights or the moving field need a gradient, backward re-runs the kernel with
 the incoming gradient as per-pose scale and takes the cotangent of the moving
 coefficients c_k = w_k rho_M(x_k), G_k = sum_b g_b Phi_b(y_k): then
 d(loss)/d(w_k) = Re(rho_M(x_k) G_k) and the moving field's cotangent is
-w_k G_k.  The B-spline stencils are recomputed in every call; no spread grid
+w_k G_k.  The fixed field's cotangent is the spread sum_b g_b sum_k c_k
+B3(p - y_kb) (score_grad_fixed).  The B-spline stencils are recomputed in every call; no spread grid
 is stored.
 
 SDFBuild: forward(q, n, w) -> rho (sdf_build); backward through
@@ -30,7 +31,7 @@ class SDFScore(torch.autograd.Function):
     def forward(ctx, poses, w, sctx, rho_fixed, g_fixed, rho_moving, g_moving):
         pose_only = bool(ctx.needs_input_grad[0]) and not (bool(ctx.needs_input_grad[1]) or
                                                              bool(ctx.needs_input_grad[5]))
-        score, gp, _ = sctx.score_grad(rho_fixed, g_fixed, rho_moving.detach(), w.detach(), g_moving,
+        score, gp, _ = sctx.score_grad(rho_fixed.detach(), g_fixed, rho_moving.detach(), w.detach(), g_moving,
                                        poses.detach(), want_pose=pose_only, want_w=False)
         ctx.save_for_backward(poses, w, rho_moving)
         ctx.aux = (sctx, rho_fixed, g_fixed, g_moving)
@@ -42,15 +43,22 @@ class SDFScore(torch.autograd.Function):
         poses, w, rho_moving = ctx.saved_tensors
         gs = grad_score.detach().to(torch.float64).contiguous()
         want_w, want_rho = bool(ctx.needs_input_grad[1]), bool(ctx.needs_input_grad[5])
-        if ctx.gp is not None and not (want_w or want_rho):
-            return ctx.gp * gs[:, None], None, None, None, None, None, None
+        want_fixed = bool(ctx.needs_input_grad[3])
         sctx, rho_fixed, g_fixed, g_moving = ctx.aux
+        grad_fixed = None
+        if want_fixed:
+            grad_fixed = torch.conj(sctx.score_grad_fixed(g_fixed, rho_moving.detach(), w.detach(), g_moving,
+                                                          poses.detach(), grad_scale=gs))
+        if ctx.gp is not None and not (want_w or want_rho):
+            return ctx.gp * gs[:, None], None, None, grad_fixed, None, None, None
         want_pose = bool(ctx.needs_input_grad[0])
+        if not (want_pose or want_w or want_rho):
+            return None, None, None, grad_fixed, None, None, None
         _, gp, gc, gw = sctx.score_grad_coef(rho_fixed, g_fixed, rho_moving.detach(), w.detach(), g_moving,
                                              poses.detach(), want_pose=want_pose, want_w=want_w, grad_scale=gs)
         grad_poses = gp * gs[:, None] if want_pose else None
         grad_rho = torch.conj(w.detach().to(gc.real.dtype) * gc) if want_rho else None
-        return grad_poses, (gw if want_w else None), None, None, None, grad_rho, None
+        return grad_poses, (gw if want_w else None), None, grad_fixed, None, grad_rho, None
 
 
 def sdf_score(poses, w, sctx, rho_fixed, g_fixed, rho_moving, g_moving):

@@ -1178,4 +1178,29 @@ int score_grad_coef(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed,
                            grad_w, grad_c, grad_scale, stream);
 }
 
+int score_grad_fixed(sdf_ctx ctx, const sdf_grid* g_fixed, const void* rho_moving, const void* w_moving,
+                     const sdf_grid* g_moving, const double* poses, int64_t B, const double* grad_scale, void* grad_f,
+                     sdf_stream stream) {
+    if (!rho_moving || !w_moving || !poses || !grad_f) return fail(ctx, SDF_EINVAL, "NULL array");
+    if (B <= 0) return fail(ctx, SDF_EINVAL, "B must be > 0");
+    if (B > (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "B too large");
+    int rc = check_pair(ctx, g_fixed, g_moving, false);
+    if (rc) return rc;
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    ctx->fused_cache_valid = false;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool planar = g_fixed->n[2] == 1;
+    const int N = g_fixed->n[0], nm = g_moving->n[0];
+    rc = ensure_ws(ctx, sizeof(double) * 12 * size_t(B) + 256);
+    if (rc) return rc;
+    hipError_t e = ctx->dtype == SDF_F64
+                       ? sdf::launch_fixed_cotangent<double>(rho_moving, static_cast<const double*>(w_moving), nm,
+                                                             planar, N, poses, B, grad_scale, grad_f, ctx->ws, s)
+                       : sdf::launch_fixed_cotangent<float>(rho_moving, static_cast<const float*>(w_moving), nm,
+                                                            planar, N, poses, B, grad_scale, grad_f, ctx->ws, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "score_grad_fixed");
+    return SDF_OK;
+}
+
 }  // extern "C"

@@ -470,13 +470,22 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
 template <typename T, bool GRAD>
 __global__ void grad_finish_kernel(const double* __restrict__ part, int nsb, const double* __restrict__ poses,
                                    int64_t B, T* __restrict__ score, double* __restrict__ grad_pose) {
-    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    // one wave per pose: lanes stride over the sample tiles (a pose's partials
+    // are contiguous, so a wave's loads are too), then a wave reduction
+    const int lane = threadIdx.x & 63;
+    const int64_t b = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+    if (b >= B) return;  // uniform across the wave
     double acc[kNAcc];
+#pragma unroll
     for (int a = 0; a < kNAcc; ++a) acc[a] = 0.0;
-    const int nacc = GRAD ? kNAcc : 1;
-    for (int sb = 0; sb < nsb; ++sb)
-        for (int a = 0; a < nacc; ++a) acc[a] += part[(b * nsb + sb) * kNAcc + a];
+    constexpr int nacc = GRAD ? kNAcc : 1;
+    const double* pb = part + b * nsb * kNAcc;
+    for (int sb = lane; sb < nsb; sb += 64)
+#pragma unroll
+        for (int a = 0; a < nacc; ++a) acc[a] += pb[sb * kNAcc + a];
+#pragma unroll
+    for (int a = 0; a < nacc; ++a) acc[a] = warp_sum(acc[a]);
+    if (lane != 0) return;
     score[b] = T(acc[0]);
     if (!GRAD || !grad_pose) return;
     const double* q = poses + 7 * b + 3;
@@ -529,6 +538,67 @@ __global__ void w_from_c_kernel(const cplx<T>* __restrict__ rho_m, const T* __re
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= K) return;
     grad_w[k] = rho_m[k].re * grad_c[2 * k] - rho_m[k].im * grad_c[2 * k + 1];
+}
+
+// ---- cotangent of the scores with respect to rho_F (the adjoint of the
+// gather): G(p) = sum_b s_b sum_k c_k B3(p - y_kb), periodic, y_kb = R_b x_k + t_b.
+// Per pose: R (FP64) and t split into floor and fraction, so that positions
+// are formed near the origin in T.
+__global__ void fixed_pose_kernel(const double* __restrict__ poses, int64_t B, double* __restrict__ out) {
+    const int64_t b = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double* pose = poses + 7 * b;
+    double r[9];
+    quat_rot(pose + 3, r);
+#pragma unroll
+    for (int a = 0; a < 9; ++a) out[12 * b + a] = r[a];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) out[12 * b + 9 + a] = pose[a];
+}
+
+// One thread per (body node, pose): the node's coefficient times s_b, spread
+// with its 4^3 (planar 4^2) B-spline stencil by atomic adds.
+template <typename T>
+__global__ void fixed_cot_kernel(const cplx<T>* __restrict__ rho_m, const T* __restrict__ w_m, int n_m, int planar,
+                                 const double* __restrict__ pr, const double* __restrict__ gscale, int64_t B,
+                                 int b0, int N, T* __restrict__ out) {
+    const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t b = b0 + int64_t(blockIdx.y);
+    if (k >= K || b >= B) return;
+    const T sb = T(gscale ? gscale[b] : 1.0);
+    const cplx<T> ck = rho_m[k] * (w_m[k] * sb);
+    if (ck.re == T(0) && ck.im == T(0)) return;
+    const double* P = pr + 12 * b;
+    const T half = T(0.5) * T(n_m);
+    const T xb[3] = {T(int(k % n_m)) - half, T(int((k / n_m) % n_m)) - half,
+                     planar ? T(0) : T(int(k / (int64_t(n_m) * n_m))) - half};
+    int base[3];
+    T wgt[3][4];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const double ti = floor(P[9 + a]);
+        const T y = T(P[9 + a] - ti) + T(P[3 * a]) * xb[0] + T(P[3 * a + 1]) * xb[1] + T(P[3 * a + 2]) * xb[2];
+        const T fl = dev_floor(y);
+        base[a] = int(fl) + int(ti) - 1;
+        bspline3_weights(y - fl, wgt[a]);
+    }
+    const int zc = planar ? 1 : 4;
+    for (int cz = 0; cz < zc; ++cz) {
+        const int iz = planar ? 0 : wrap(base[2] + cz, N);
+        const T wz = planar ? T(1) : wgt[2][cz];
+        for (int cy = 0; cy < 4; ++cy) {
+            const int iy = wrap(base[1] + cy, N);
+            const T wyz = wgt[1][cy] * wz;
+            for (int cx = 0; cx < 4; ++cx) {
+                const int ix = wrap(base[0] + cx, N);
+                const T wt = wgt[0][cx] * wyz;
+                const int64_t idx = (int64_t(iz) * N + iy) * N + ix;
+                atomicAdd(out + 2 * idx, ck.re * wt);
+                atomicAdd(out + 2 * idx + 1, ck.im * wt);
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -613,11 +683,11 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 g2(unsigned((B + 127) / 128));
+    dim3 g2(unsigned((B + 3) / 4));  // 4 waves of 64 lanes per block, one pose per wave
     if (grad)
-        hipLaunchKernelGGL((grad_finish_kernel<T, true>), g2, dim3(128), 0, s, part, nsb, poses, B, score, grad_pose);
+        hipLaunchKernelGGL((grad_finish_kernel<T, true>), g2, dim3(256), 0, s, part, nsb, poses, B, score, grad_pose);
     else
-        hipLaunchKernelGGL((grad_finish_kernel<T, false>), g2, dim3(128), 0, s, part, nsb, poses, B, score, nullptr);
+        hipLaunchKernelGGL((grad_finish_kernel<T, false>), g2, dim3(256), 0, s, part, nsb, poses, B, score, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const dim3 gk(unsigned((K + 255) / 256));
@@ -630,6 +700,27 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_fixed_cotangent(const void* rho_m, const T* w_m, int n_m, bool planar, int N, const double* poses,
+                                  int64_t B, const double* grad_scale, void* grad_f, void* ws, hipStream_t s) {
+    const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
+    const int64_t G = planar ? int64_t(N) * N : int64_t(N) * N * N;
+    hipError_t e = hipMemsetAsync(grad_f, 0, 2 * sizeof(T) * size_t(G), s);
+    if (e != hipSuccess) return e;
+    double* pr = static_cast<double*>(ws);
+    hipLaunchKernelGGL(fixed_pose_kernel, dim3(unsigned((B + 127) / 128)), dim3(128), 0, s, poses, B, pr);
+    for (int64_t b0 = 0; b0 < B; b0 += 65535) {
+        const dim3 grid{unsigned((K + 255) / 256), unsigned(std::min<int64_t>(B - b0, 65535)), 1u};
+        hipLaunchKernelGGL(fixed_cot_kernel<T>, grid, dim3(256), 0, s, static_cast<const cplx<T>*>(rho_m), w_m, n_m,
+                           planar ? 1 : 0, pr, grad_scale, B, int(b0), N, static_cast<T*>(grad_f));
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_fixed_cotangent<float>(const void*, const float*, int, bool, int, const double*, int64_t,
+                                                  const double*, void*, void*, hipStream_t);
+template hipError_t launch_fixed_cotangent<double>(const void*, const double*, int, bool, int, const double*, int64_t,
+                                                   const double*, void*, void*, hipStream_t);
 template size_t grad_workspace_bytes<float>(int64_t, int, int, bool, int);
 template size_t grad_workspace_bytes<double>(int64_t, int, int, bool, int);
 template hipError_t launch_score_grad<float>(const void*, int, bool, const void*, const float*, int, const double*,

@@ -150,6 +150,11 @@ template <typename T>
 size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, int wmode);
 // grad_c (may be NULL): complex per-sample sums of grad_scale_b Phi_b(y_k);
 // grad_w then follows as Re(rho_M grad_c)
+// cotangent of sum_b s_b f_b with respect to rho_F (complex, zeroed here);
+// ws: 12 B doubles
+template <typename T>
+hipError_t launch_fixed_cotangent(const void* rho_m, const T* w_m, int n_m, bool planar, int N, const double* poses,
+                                  int64_t B, const double* grad_scale, void* grad_f, void* ws, hipStream_t s);
 template <typename T>
 hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* rho_m, const T* w_m, int n_m,
                              const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w, T* grad_c,

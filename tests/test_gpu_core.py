@@ -530,6 +530,68 @@ def test_shape_gradient_through_autograd(ctxs, dtype):
         assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), float(np.max(np.abs(got - ref)) / np.abs(ref).max())
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("planar", [False, True])
+def test_score_grad_fixed_matches_oracle(ctxs, dtype, planar):
+    """The fixed field's cotangent, the periodic spread of the moving
+    coefficients at every pose scaled by s_b, against the oracle."""
+    ctx = ctxs[dtype]
+    n, nm = (16, 6) if not planar else (32, 12)
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, planar, 500 + n)
+    rng = np.random.default_rng(n + 1)
+    B = 9
+    t = rng.uniform(-n, 2 * n, size=(B, 3))
+    q = wr.uniform_quaternions(B, 60)
+    if planar:
+        t[:, 2] = 0.0
+        q = wr.planar_rotations(41.0, B)
+    poses = np.concatenate([t, q], axis=1)
+    gs = rng.normal(size=B)
+    flush_print("score_grad_fixed", dtype, planar)
+    got = to_np(ctx.score_grad_fixed(gf, rho_m, w, gm, poses, grad_scale=gs))
+    c = oc.moving_coefficients(rho_m, w)
+    ref = og.fixed_cotangent(c, osp.body_positions(nm, planar), poses, gs, rho_f.shape)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fixed_part_shape_gradient_through_autograd(ctxs, dtype):
+    """d(sum_b g_b f_b) with respect to the fixed part's boundary samples,
+    through sdf_field for rho_F and sdf_score (whose backward returns the
+    fixed field's cotangent): against the oracle adjoint applied to the
+    oracle's spread cotangent."""
+    import torch
+    from paper_1712_00238_amd.autograd import sdf_field, sdf_score
+    ctx = ctxs[dtype]
+    pair = C.small_3d(seed=3, n=16, n_m=6)
+    fx, mv = pair.fixed, pair.moving
+    rho_m = osdf.sdf_grid(mv.samples, mv.grid, pair.params)
+    dev = torch.device("cuda")
+    real = torch.float64 if dtype == "f64" else torch.float32
+    cplx = torch.complex128 if dtype == "f64" else torch.complex64
+    rng = np.random.default_rng(9)
+    B = 5
+    poses = np.concatenate([rng.uniform(-4, 4, size=(B, 3)), wr.uniform_quaternions(B, 19)], axis=1)
+    g = rng.normal(size=B)
+    q = torch.tensor(fx.samples.q, dtype=torch.float64, device=dev, requires_grad=True)
+    nn = torch.tensor(fx.samples.n, dtype=torch.float64, device=dev, requires_grad=True)
+    ww = torch.tensor(fx.samples.w, dtype=torch.float64, device=dev, requires_grad=True)
+    rho_f = sdf_field(q, nn, ww, ctx, fx.grid, pair.params)
+    rm = torch.as_tensor(rho_m, dtype=cplx, device=dev)
+    w_node = torch.ones(rm.shape, dtype=real, device=dev)
+    flush_print("fixed shape gradient", dtype)
+    score = sdf_score(torch.tensor(poses, dtype=torch.float64, device=dev), w_node, ctx, rho_f, fx.grid, rm, mv.grid)
+    (score.double() * torch.as_tensor(g, device=dev)).sum().backward()
+    c = oc.moving_coefficients(rho_m, np.ones(rho_m.shape))
+    cot = og.fixed_cotangent(c, osp.body_positions(mv.grid.n[0]), poses, g, rho_f.shape)
+    rq, rn, rw = oadj.sdf_adjoint_grid(fx.samples, fx.grid, pair.params, cot)
+    tol = 1e-9 if dtype == "f64" else 1e-4
+    for got, ref in ((q.grad, rq), (nn.grad, rn), (ww.grad, rw)):
+        got = got.cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max(), float(np.max(np.abs(got - ref)) / np.abs(ref).max())
+
+
 # ----------------------------------------------------------------------------- end to end, planar
 
 def test_peg_in_hole_end_to_end_f64(ctxs):

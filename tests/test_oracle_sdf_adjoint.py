@@ -85,3 +85,23 @@ def test_weight_gradient_is_exact_by_linearity():
         # rho is linear in w with the discrete choices fixed (they do not depend on w)
         lj = _L(shapes.PointSamples(s.q, s.n, e), pts, params, cot)
         assert abs(gw[j] * s.w[j] - lj) <= 1e-12 * max(1.0, abs(lj))
+
+
+def test_fixed_cotangent_is_the_adjoint_of_the_gather():
+    """sum_b s_b f_b evaluated by gathering Phi at the moved samples equals
+    Re sum_p rho_F(p) G(p) with G the spread cotangent (the gather and the
+    spread are transposes)."""
+    from oracle import grad as og
+    from oracle import spread as osp
+    from workloads import rotations as wr
+    rng = np.random.default_rng(5)
+    n, nm = 12, 5
+    rho_f = rng.normal(size=(n, n, n)) + 1j * rng.normal(size=(n, n, n))
+    c = rng.normal(size=nm ** 3) + 1j * rng.normal(size=nm ** 3)
+    xb = osp.body_positions(nm)
+    B = 4
+    poses = np.concatenate([rng.uniform(-n, 2 * n, size=(B, 3)), wr.uniform_quaternions(B, 3)], axis=1)
+    s = rng.normal(size=B)
+    gather = sum(s[b] * og.pose_value(rho_f, c, xb, poses[b, :3], poses[b, 3:]) for b in range(B))
+    g = og.fixed_cotangent(c, xb, poses, s, rho_f.shape)
+    assert abs(gather - np.real(np.sum(rho_f * g))) <= 1e-10 * max(1.0, abs(gather))
