@@ -304,8 +304,12 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
     const int t0x = (sb % nt) * kBoxTile, t0y = ((sb / nt) % nt) * kBoxTile, t0z = (sb / (nt * nt)) * kBoxTile;
     const int64_t K = int64_t(n_m) * n_m * n_m;
     const float half = 0.5f * float(n_m);
-    // this thread's sample
-    const int i = t0x + (threadIdx.x & 7), j = t0y + ((threadIdx.x >> 3) & 7), k = t0z + (threadIdx.x >> 6);
+    // this thread's sample: a wave covers a 4 x 4 x 4 sub-block of the tile
+    // (compact in 3D, which spreads its stencil gathers over more LDS banks
+    // than an 8 x 8 x 1 slice)
+    const int wq = int(threadIdx.x >> 6), ln = int(threadIdx.x & 63);
+    const int i = t0x + 4 * (wq & 1) + (ln & 3), j = t0y + 4 * ((wq >> 1) & 1) + ((ln >> 2) & 3),
+              k = t0z + 4 * (wq >> 2) + (ln >> 4);
     const bool ok = i < n_m && j < n_m && k < n_m;
     const int64_t ks = ok ? (int64_t(k) * n_m + j) * n_m + i : 0;
     const float xb0 = float(i) - half, xb1 = float(j) - half, xb2 = float(k) - half;
@@ -335,7 +339,10 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
             const float y0 = tfr[a] + r[3 * a] * xlo0 + r[3 * a + 1] * xlo1 + r[3 * a + 2] * xlo2;
             const int fmin = int(floorf(y0 + P.dmin[a] - kBoxMargin));
             lo[a] = __builtin_amdgcn_readfirstlane(fmin - 1 + tint[a]);
-            ext[a] = __builtin_amdgcn_readfirstlane(int(floorf(y0 + P.dmax[a] + kBoxMargin)) - fmin + 4);
+            // at most kBoxMax for any rotation (see above); the clamp only guards
+            // non-finite poses, whose conversions give in-range but meaningless boxes
+            ext[a] = __builtin_amdgcn_readfirstlane(
+                min(int(floorf(y0 + P.dmax[a] + kBoxMargin)) - fmin + 4, kBoxMax));
         }
         // stage the box: slot s holds rows 3 q .. 3 q + 2 of plane cz, with
         // s = cz nts + q; lane = 17 j + cx covers row 3 q + j, cell cx
