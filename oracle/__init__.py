@@ -14,6 +14,9 @@ Modules:
   correlate score volumes f(R, t) = Re sum_p rho_F(p) M_R(p - t) (eq. 8)
   peak      per-rotation peak, 27-neighbourhood, sub-voxel refinement, top-K
   grad      pose value and gradients of the score, finite differences
+  octree    octree-adaptive aggregation of the moving samples
+  nfft      nonequispaced route: type-1 transform (definition and spread/FFT/
+            deconvolution algorithm), trigonometric-interpolation scores
 
 Functions whose result the tests cannot pin to anything but themselves say
 "parity unpinned" in their docstring.
