@@ -52,6 +52,10 @@ def parse():
     ap.add_argument("--fp64-rotations", type=int, default=64, help="rotations timed on the plain FP64 path")
     ap.add_argument("--direct-rotations", type=int, default=32,
                     help="top rotations rescored by the windowless reference search")
+    ap.add_argument("--nfft-rotations", type=int, default=32,
+                    help="of the directly rescored rotations, how many the nonequispaced route scores (0: skip)")
+    ap.add_argument("--nfft-width", type=int, default=6, help="ES kernel width of the nonequispaced route")
+    ap.add_argument("--nfft-tols", default="0,0.003,0.01,0.03", help="octree tolerances (0: every node)")
     ap.add_argument("--grad-poses", type=int, default=1024)
     ap.add_argument("--refine-poses", type=int, default=1024,
                     help="protein-like refinement: poses perturbed from the top peaks (0 skips)")
@@ -432,6 +436,46 @@ def main():
                 "same_best": bool(int(np.argmax(sw)) == int(np.argmax(sd))),
                 "spearman": round(spearman, 4)}
 
+        # --- the nonequispaced route: octree-adaptive samples of the moving part
+        # and the type-1 transform (ES spreading on the 2x grid, FFT,
+        # deconvolution) for the same rotations as the direct reference
+        if args.direct_rotations and args.nfft_rotations:
+            qn = qd[:args.nfft_rotations]
+            sdn, tdn = sd[:len(qn)], td[:len(qn)]
+            rows, s_full = [], None
+            for tol in [float(v) for v in args.nfft_tols.split(",")]:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                pos, cc, lev = ctx.octree_samples(rho_m, w, mv.grid, tol, 3)  # reading the count synchronises
+                t_oct = time.perf_counter() - t0
+                ctx.score_rotations_nfft(spec, fx.grid, pos, cc, qn[:1], width=args.nfft_width)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                on = ctx.score_rotations_nfft(spec, fx.grid, pos, cc, qn, width=args.nfft_width)
+                torch.cuda.synchronize()
+                dt_n = time.perf_counter() - t0
+                sn = on["score"].cpu().numpy().astype(np.float64)
+                tn = on["t"].cpu().numpy()
+                if s_full is None:
+                    s_full = sn
+                shift = np.abs(tn.astype(np.int64) - tdn.astype(np.int64))
+                shift = np.minimum(shift, 128 - shift)
+                rk_n = np.argsort(np.argsort(-sn)); rk_d = np.argsort(np.argsort(-sdn))
+                nq = len(qn)
+                rows.append({
+                    "tol": tol, "samples": int(len(cc)), "sample_frac": round(len(cc) / float(rho_m.numel()), 4),
+                    "levels": np.bincount(lev.cpu().numpy(), minlength=4).tolist(),
+                    "octree_ms": round(1e3 * t_oct, 3), "rotations_per_s": round(nq / dt_n, 1),
+                    "vs_direct_median_rel": float(np.median(np.abs(sn - sdn) / np.abs(sdn))),
+                    "vs_direct_max_rel": float(np.max(np.abs(sn - sdn) / np.abs(sdn))),
+                    "vs_direct_same_t_frac": float(np.mean(np.all(shift == 0, axis=1))),
+                    "vs_direct_same_best": bool(int(np.argmax(sn)) == int(np.argmax(sdn))),
+                    "vs_direct_spearman": round(1.0 - 6.0 * float(np.sum((rk_n - rk_d) ** 2)) / (nq * (nq * nq - 1)),
+                                                4) if nq > 1 else None,
+                    "vs_all_nodes_max_rel": float(np.max(np.abs(sn - s_full) / np.abs(s_full)))})
+            report["nonequispaced"] = {"width": args.nfft_width, "oversampling": 2, "rotations": int(len(qn)),
+                                       "octree_levels": 3, "per_tolerance": rows}
+
         # --- shape gradients: the cotangent of 32 refined poses' scores with
         # respect to the moving coefficients, then the SDF adjoint over the
         # moving part's boundary samples (both timed with events)
@@ -581,6 +625,7 @@ def main():
             "pose_grad_evals_per_s": round(report["pose_grad_evals_per_s"], 1),
             "fp32_vs_fp64": report["fp32_vs_fp64"],
             "window_effect": report.get("window_effect"),
+            "nonequispaced": report.get("nonequispaced"),
             "shape_grad": report.get("shape_grad"),
             "stage_GBs": round(report["stage_GBs"], 1),
             "correlation_stage": report["correlation_stage"],

@@ -345,6 +345,67 @@ int score_grad_fixed(sdf_ctx ctx, const sdf_grid *g_fixed, const void *rho_movin
                      const sdf_grid *g_moving, const double *poses, int64_t B, const double *grad_scale,
                      void *grad_f, sdf_stream stream);
 
+/* ------------------------------------------------ nonequispaced route */
+
+/* Octree-adaptive samples of the moving part (Implementation section: the
+ * affinity varies most near the skeleton, so it is sampled on an octree,
+ * deeper where it varies more, and the m' << m nonequispaced samples meet the
+ * fixed part through a nonequispaced FFT).  The paper gives no subdivision
+ * rule; this library's reading, on c_k = w_k rho_M(x_k) over the body box:
+ *   - a cell is a cube of 2^l nodes per side (1 <= l <= max_level), aligned to
+ *     multiples of 2^l; it is flat when over its nodes
+ *       max Re c - min Re c < tau  and  max Im c - min Im c < tau,
+ *       tau = tol * max_k max(|Re c_k|, |Im c_k|)
+ *     (all in the context's precision; tol = 0 merges nothing);
+ *   - each node goes to the highest flat cell above it, else stays a leaf of
+ *     its own; a leaf is one sample at the cell centre, in grid units from
+ *     the body origin (node k at k - N_M/2), carrying the sum of its nodes'
+ *     coefficients (summed in FP64); leaves whose nodes are all zero are
+ *     dropped;
+ *   - order: 8^3 (planar 8^2) node blocks in flat x-fastest order, leaves in
+ *     Morton order (x bit lowest) inside a block.
+ * Arguments: rho_moving complex, w_moving real, N_M^3 or N_M^2 x 1 with N_M a
+ * multiple of 8; max_level in [0, 3]; tol finite, >= 0.  Outputs (device,
+ * capacity N_M^3 or N_M^2 leaves): pos_out real x 3 per leaf (z = 0 in 2D),
+ * c_out complex, level_out int32 cell level l (may be NULL), count_out one
+ * int64 = number of leaves.  Coefficients must be finite.
+ * Errors: SDF_EINVAL, SDF_ENOMEM, SDF_EHIP. */
+int octree_samples(sdf_ctx ctx, const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
+                   double tol, int max_level, void *pos_out, void *c_out, int32_t *level_out,
+                   int64_t *count_out, sdf_stream stream);
+
+/* The search through the nonequispaced transform (Implementation section)
+ * instead of the B-spline window: m samples at positions pos_k (real x 3,
+ * grid units from the body origin, any values) with complex coefficients c_k
+ * (from octree_samples, or every node of the body box) meet the fixed part
+ * through its trigonometric interpolant,
+ *   f(R, t) = sum_k c_k rho_F^trig(t + R pos_k),
+ *   rho_F^trig(z) = N^-d sum_{kappa in [-N/2, N/2)^d} rho_F^(kappa) e^{2 pi i kappa.z / N},
+ * evaluated per rotation by the type-1 transform of the reflected samples
+ * -R pos_k: spreading with the "exponential of semicircle" kernel
+ * exp(2.30 w (sqrt(1 - z^2) - 1)) over `width` nodes per axis of the 2x
+ * oversampled grid, FFT, the N^d central modes divided by the kernel's
+ * transform (Barnett, Magland and af Klinteberg, 2019; relative error about
+ * 10^(1 - width)), product with spec_fixed, inverse FFT.  Peaks, 27-
+ * neighbourhoods and sub-voxel offsets as in score_rotations.
+ *   spec_fixed: output of sdf_spectrum; g_fixed N^3 or N^2 x 1 with N in
+ *   {8, 16, 32, 64, 128}; width in [2, 8]; m >= 0 (m = 0 scores 0).
+ *   quats (host): n_rot x 4 FP64.
+ * Device workspace: up to 512 MiB of oversampled grids per batch of
+ * rotations plus one N^d grid per rotation of the batch.
+ * Errors: SDF_EINVAL, SDF_EUNSUPPORTED (N), SDF_ENOMEM, SDF_EHIP. */
+int score_rotations_nfft(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
+                         const void *pos, const void *c, int64_t m, int width,
+                         const double *quats, int64_t n_rot,
+                         void *peak_score, int32_t *peak_t, void *peak_nbhd, double *refined_t,
+                         sdf_stream stream);
+
+/* Full volumes Re f(R, t) of the nonequispaced route (real, n_rot x grid
+ * size); same inputs and constraints as score_rotations_nfft. */
+int score_volume_nfft(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
+                      const void *pos, const void *c, int64_t m, int width,
+                      const double *quats, int64_t n_rot, void *vol_out, sdf_stream stream);
+
 #ifdef __cplusplus
 }
 #endif

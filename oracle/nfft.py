@@ -79,7 +79,7 @@ def es_transform(kappa, w: int, n_fine: int) -> np.ndarray:
     out = []
     for k in np.atleast_1d(kappa):
         f = lambda x, k=k: float(es_kernel(2.0 * x / w, w)) * np.cos(2.0 * np.pi * k * x / n_fine)
-        v, _ = integrate.quad(f, -w / 2.0, w / 2.0, limit=200, epsabs=1e-14, epsrel=1e-13)
+        v, _ = integrate.quad(f, -w / 2.0, w / 2.0, limit=200, epsabs=1e-13, epsrel=1e-12)
         out.append(v)
     return np.array(out)
 

@@ -232,6 +232,57 @@ class Context:
                                           _stream(self.device)))
         return out
 
+    def octree_samples(self, rho_moving, w_moving, g_moving, tol, max_level=3):
+        """Octree-adaptive samples of the moving part: (pos (m', 3) real, c
+        (m',) complex, level (m',) int32), device tensors trimmed to the leaf
+        count (reading the count synchronises the stream)."""
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        cap = int(rm.numel())
+        pos = torch.empty((cap, 3), dtype=self.real, device=self.device)
+        c = torch.empty(cap, dtype=self.cplx, device=self.device)
+        lev = torch.empty(cap, dtype=torch.int32, device=self.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=self.device)
+        gm = _lib.make_grid(g_moving)
+        self._check(self.lib.octree_samples(self.handle, _ptr(rm), _ptr(wm), ctypes.byref(gm), float(tol),
+                                            int(max_level), _ptr(pos), _ptr(c), _ptr(lev), _ptr(cnt),
+                                            _stream(self.device)))
+        m = int(cnt.item())
+        return pos[:m], c[:m], lev[:m]
+
+    def score_rotations_nfft(self, spec, g_fixed, pos, c, quats, width=6, nbhd=True, refined=True):
+        """Search through the nonequispaced transform of samples (pos, c);
+        returns dict(score, t, nbhd, refined) as score_rotations."""
+        q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+        n_rot = len(q)
+        spec = self._dev(spec, self.cplx)
+        ps = self._dev(pos, self.real).reshape(-1, 3)
+        cs = self._dev(c, self.cplx).reshape(-1)
+        out = {"score": torch.empty(n_rot, dtype=self.real, device=self.device),
+               "t": torch.empty((n_rot, 3), dtype=torch.int32, device=self.device),
+               "nbhd": torch.empty((n_rot, 27), dtype=self.real, device=self.device) if nbhd else None,
+               "refined": torch.empty((n_rot, 3), dtype=torch.float64, device=self.device) if refined else None}
+        gf = _lib.make_grid(g_fixed)
+        self._check(self.lib.score_rotations_nfft(self.handle, _ptr(spec), ctypes.byref(gf), _ptr(ps), _ptr(cs),
+                                                  int(cs.numel()), int(width), q.ctypes.data_as(ctypes.c_void_p),
+                                                  n_rot, _ptr(out["score"]), _ptr(out["t"]), _ptr(out["nbhd"]),
+                                                  _ptr(out["refined"]), _stream(self.device)))
+        return out
+
+    def score_volume_nfft(self, spec, g_fixed, pos, c, quats, width=6):
+        """Volumes Re f(R, t) of the nonequispaced route, (n_rot, nz, ny, nx)."""
+        q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
+        spec = self._dev(spec, self.cplx)
+        ps = self._dev(pos, self.real).reshape(-1, 3)
+        cs = self._dev(c, self.cplx).reshape(-1)
+        nx, ny, nz = g_fixed.n
+        out = torch.empty((len(q), nz, ny, nx), dtype=self.real, device=self.device)
+        gf = _lib.make_grid(g_fixed)
+        self._check(self.lib.score_volume_nfft(self.handle, _ptr(spec), ctypes.byref(gf), _ptr(ps), _ptr(cs),
+                                               int(cs.numel()), int(width), q.ctypes.data_as(ctypes.c_void_p), len(q),
+                                               _ptr(out), _stream(self.device)))
+        return out
+
     def spread(self, g_fixed, rho_moving, w_moving, g_moving, quats):
         q = np.ascontiguousarray(np.asarray(quats, dtype=np.float64).reshape(-1, 4))
         rm = self._dev(rho_moving, self.cplx)

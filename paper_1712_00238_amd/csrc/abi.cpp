@@ -763,6 +763,88 @@ int direct_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const double*
     return SDF_OK;
 }
 
+// Nonequispaced route: batches of rotations through the type-1 transform of
+// the given samples, then the plain path's inverse FFT and peak (or real part).
+constexpr size_t kNfftFineBudget = size_t(512) << 20;  // oversampled grids per batch
+
+template <typename T>
+int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos, const void* c, int64_t m, int w,
+              const double* quats, int64_t n_rot, Mode mode, void* score, int32_t* t, void* nbhd, double* refined,
+              void* vol_out, hipStream_t s) {
+    ctx->fused_cache_valid = false;
+    const int N = gf->n[0];
+    const bool planar = gf->n[2] == 1;
+    const int nf = 2 * N;
+    const int64_t G = gsize(gf);
+    const int64_t Gf = planar ? int64_t(nf) * nf : int64_t(nf) * nf * nf;
+    const size_t fine_bytes = 2 * sizeof(T) * size_t(Gf);
+    const int64_t B = std::max<int64_t>(1, std::min<int64_t>(n_rot, int64_t(kNfftFineBudget / fine_bytes)));
+    const int nparts = sdf::peak_parts<T>(N, planar);
+    Carve cv{nullptr};
+    cv.take(sizeof(double) * 4 * n_rot);
+    cv.take(sizeof(double) * 9 * n_rot);
+    cv.take(sizeof(T) * 9 * n_rot);
+    cv.take(sizeof(T) * N);
+    cv.take(fine_bytes * B);
+    cv.take(2 * sizeof(T) * G * B);
+    cv.take(sizeof(T) * nparts * B);
+    cv.take(sizeof(int) * nparts * B);
+    int rc = ensure_ws(ctx, cv.off);
+    if (rc) return rc;
+    Carve c2{static_cast<char*>(ctx->ws)};
+    double* qd = static_cast<double*>(c2.take(sizeof(double) * 4 * n_rot));
+    double* r64 = static_cast<double*>(c2.take(sizeof(double) * 9 * n_rot));
+    T* RT = static_cast<T*>(c2.take(sizeof(T) * 9 * n_rot));
+    T* inv = static_cast<T*>(c2.take(sizeof(T) * N));
+    void* fine = c2.take(fine_bytes * B);
+    void* grid = c2.take(2 * sizeof(T) * G * B);
+    T* pval = static_cast<T*>(c2.take(sizeof(T) * nparts * B));
+    int* pidx = static_cast<int*>(c2.take(sizeof(int) * nparts * B));
+    SDF_TRY_HIP(ctx, hipMemcpyAsync(qd, quats, sizeof(double) * 4 * n_rot, hipMemcpyHostToDevice, s),
+                "quaternion upload");
+    SDF_TRY_HIP(ctx, sdf::launch_quat_to_rot<T>(qd, n_rot, r64, RT, s), "rotations");
+    SDF_TRY_HIP(ctx, sdf::launch_es_deconv<T>(N, w, inv, s), "deconvolution table");
+    for (int64_t r0 = 0; r0 < n_rot; r0 += B) {
+        const int nb = int(std::min<int64_t>(B, n_rot - r0));
+        SDF_TRY_HIP(ctx,
+                    sdf::launch_nfft_modes<T>(static_cast<const T*>(pos), c, m, RT + 9 * r0, nb, N, planar, w, inv,
+                                              spec, fine, grid, s),
+                    "nonequispaced transform");
+        SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, nb, +1, 1.0, s), "inverse fft");
+        if (mode == Mode::Volume) {
+            SDF_TRY_HIP(ctx, sdf::launch_real_part<T>(grid, static_cast<T*>(vol_out) + r0 * G, G * nb, s),
+                        "real part");
+        } else {
+            SDF_TRY_HIP(ctx,
+                        sdf::launch_peak<T>(grid, true, N, planar, nb, pval, pidx, nparts,
+                                            static_cast<T*>(score) + r0, t + 3 * r0,
+                                            nbhd ? static_cast<T*>(nbhd) + 27 * r0 : nullptr,
+                                            refined ? refined + 3 * r0 : nullptr, s),
+                        "peak");
+        }
+    }
+    return SDF_OK;
+}
+
+int check_nfft_args(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos, const void* c, int64_t m,
+                    int w, const double* quats, int64_t n_rot) {
+    if (!spec || (m > 0 && (!pos || !c))) return fail(ctx, SDF_EINVAL, "NULL array");
+    int rc = check_grid(ctx, gf, "g_fixed");
+    if (rc) return rc;
+    const int N = gf->n[0];
+    if (gf->n[1] != N || (gf->n[2] != N && gf->n[2] != 1))
+        return fail(ctx, SDF_EINVAL, "g_fixed: must be N x N x N or N x N x 1");
+    if (N != 8 && N != 16 && N != 32 && N != 64 && N != 128)
+        return fail(ctx, SDF_EUNSUPPORTED, "g_fixed: the nonequispaced route needs N in {8, 16, 32, 64, 128}");
+    if (m < 0 || m > (int64_t(1) << 31)) return fail(ctx, SDF_EINVAL, "sample count must be in [0, 2^31]");
+    if (w < 2 || w > 8) return fail(ctx, SDF_EINVAL, "kernel width must be in [2, 8]");
+    rc = check_quats(ctx, quats, n_rot);
+    if (rc) return rc;
+    if (n_rot > (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "n_rot too large");
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    return SDF_OK;
+}
+
 extern "C" {
 
 int sdf_ctx_create(sdf_ctx* out, int device, sdf_dtype dtype, size_t workspace_cap_bytes) {
@@ -1201,6 +1283,65 @@ int score_grad_fixed(sdf_ctx ctx, const sdf_grid* g_fixed, const void* rho_movin
                                                             planar, N, poses, B, grad_scale, grad_f, ctx->ws, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "score_grad_fixed");
     return SDF_OK;
+}
+
+int octree_samples(sdf_ctx ctx, const void* rho_moving, const void* w_moving, const sdf_grid* g_moving, double tol,
+                   int max_level, void* pos_out, void* c_out, int32_t* level_out, int64_t* count_out,
+                   sdf_stream stream) {
+    if (!rho_moving || !w_moving || !pos_out || !c_out || !count_out) return fail(ctx, SDF_EINVAL, "NULL array");
+    int rc = check_grid(ctx, g_moving, "g_moving");
+    if (rc) return rc;
+    const int nm = g_moving->n[0];
+    const bool planar = g_moving->n[2] == 1;
+    if (g_moving->n[1] != nm || (!planar && g_moving->n[2] != nm))
+        return fail(ctx, SDF_EINVAL, "g_moving: must be N_M^3 or N_M^2 x 1");
+    if (nm < 8 || nm % 8) return fail(ctx, SDF_EINVAL, "g_moving: N_M must be a positive multiple of 8");
+    if (max_level < 0 || max_level > 3) return fail(ctx, SDF_EINVAL, "max_level must be in [0, 3]");
+    if (!std::isfinite(tol) || tol < 0) return fail(ctx, SDF_EINVAL, "tol must be finite and >= 0");
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ctx->fused_cache_valid = false;
+    rc = ensure_ws(ctx, sdf::octree_workspace_bytes(nm, planar, esize(ctx)));
+    if (rc) return rc;
+    int* lv = reinterpret_cast<int*>(level_out);
+    hipError_t e =
+        ctx->dtype == SDF_F64
+            ? sdf::launch_octree<double>(rho_moving, static_cast<const double*>(w_moving), nm, planar, tol, max_level,
+                                         static_cast<double*>(pos_out), c_out, lv, count_out, ctx->ws, s)
+            : sdf::launch_octree<float>(rho_moving, static_cast<const float*>(w_moving), nm, planar, tol, max_level,
+                                        static_cast<float*>(pos_out), c_out, lv, count_out, ctx->ws, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "octree_samples");
+    return SDF_OK;
+}
+
+int score_rotations_nfft(sdf_ctx ctx, const void* spec_fixed, const sdf_grid* g_fixed, const void* pos,
+                         const void* c, int64_t m, int width, const double* quats, int64_t n_rot, void* peak_score,
+                         int32_t* peak_t, void* peak_nbhd, double* refined_t, sdf_stream stream) {
+    if (!peak_score || !peak_t) return fail(ctx, SDF_EINVAL, "NULL array");
+    int rc = check_nfft_args(ctx, spec_fixed, g_fixed, pos, c, m, width, quats, n_rot);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->dtype == SDF_F64)
+        return nfft_impl<double>(ctx, spec_fixed, g_fixed, pos, c, m, width, quats, n_rot, Mode::Peaks, peak_score,
+                                 peak_t, peak_nbhd, refined_t, nullptr, s);
+    return nfft_impl<float>(ctx, spec_fixed, g_fixed, pos, c, m, width, quats, n_rot, Mode::Peaks, peak_score, peak_t,
+                            peak_nbhd, refined_t, nullptr, s);
+}
+
+int score_volume_nfft(sdf_ctx ctx, const void* spec_fixed, const sdf_grid* g_fixed, const void* pos, const void* c,
+                      int64_t m, int width, const double* quats, int64_t n_rot, void* vol_out, sdf_stream stream) {
+    if (!vol_out) return fail(ctx, SDF_EINVAL, "NULL array");
+    int rc = check_nfft_args(ctx, spec_fixed, g_fixed, pos, c, m, width, quats, n_rot);
+    if (rc) return rc;
+    DeviceGuard dg(ctx->device);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->dtype == SDF_F64)
+        return nfft_impl<double>(ctx, spec_fixed, g_fixed, pos, c, m, width, quats, n_rot, Mode::Volume, nullptr,
+                                 nullptr, nullptr, nullptr, vol_out, s);
+    return nfft_impl<float>(ctx, spec_fixed, g_fixed, pos, c, m, width, quats, n_rot, Mode::Volume, nullptr, nullptr,
+                            nullptr, nullptr, vol_out, s);
 }
 
 }  // extern "C"

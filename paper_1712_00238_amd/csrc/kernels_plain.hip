@@ -10,6 +10,12 @@
 
 namespace sdf {
 
+// 256-point lines (the 2x oversampled grid of the nonequispaced route)
+template <>
+struct DefaultPlan<256> {
+    using type = Radices<8, 8, 4>;
+};
+
 namespace {
 
 // ------------------------------------------------------------------ rotations
@@ -141,6 +147,7 @@ __global__ void place_direct_kernel(const cplx<T>* __restrict__ rho, int n_m, in
 }
 
 // ------------------------------------------------------------------ FFT passes
+
 constexpr int kFftBlock = 256;
 
 // Rows (x axis, contiguous): a block transforms conc = 256 / (N/8) rows.
@@ -415,6 +422,7 @@ hipError_t launch_fft3(void* data, int N, bool planar, int batch, int dir, doubl
         case 64: return fft3_impl<T, 64>(data, planar, batch, dir, scale, s);
         case 96: return fft3_impl<T, 96>(data, planar, batch, dir, scale, s);
         case 128: return fft3_impl<T, 128>(data, planar, batch, dir, scale, s);
+        case 256: return fft3_impl<T, 256>(data, planar, batch, dir, scale, s);
         default: return hipErrorInvalidValue;
     }
 }

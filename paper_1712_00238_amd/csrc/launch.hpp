@@ -140,6 +140,25 @@ hipError_t launch_fused_batch(const FusedPlan& fp, const FusedRot* rots, int n_r
 // deterministic pseudo-random complex64 fill (autotune inputs)
 hipError_t launch_fill_random(void* data, int64_t count, uint32_t seed, float amp, hipStream_t s);
 
+// ---- nonequispaced route: octree-adaptive samples and the type-1 transform
+// workspace of launch_octree for an N_M box of `elem`-byte reals
+size_t octree_workspace_bytes(int nm, bool planar, size_t elem);
+// leaves of the adaptive tree over c = w rho_M (N_M % 8 == 0, max_level <= 3):
+// pos (3 per leaf, grid units from the body origin), c_out, level (may be
+// NULL) in block / Morton order; *count_out (device) = number of leaves
+template <typename T>
+hipError_t launch_octree(const void* rho_m, const T* w_m, int nm, bool planar, double tol, int max_level, T* pos,
+                         void* c_out, int* level, int64_t* count_out, void* ws, hipStream_t s);
+// 1 / phihat of the width-w kernel for the N FFT-order modes of the 2N grid
+template <typename T>
+hipError_t launch_es_deconv(int N, int w, T* inv, hipStream_t s);
+// `batch` rotations R[b] (9 T each) of the m samples: zero the (2N)^d grids
+// `fine`, spread, transform, and write out[b] = deconvolved N^d modes times
+// spec (ready for the inverse FFT of the correlation)
+template <typename T>
+hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
+                             int w, const T* inv, const void* spec, void* fine, void* out, hipStream_t s);
+
 // ---- top-k
 template <typename T>
 hipError_t launch_topk(const T* scores, int64_t n, int64_t k, void* ws, int32_t* idx_out, hipStream_t s);
