@@ -778,7 +778,8 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
     const int64_t G = gsize(gf);
     const int64_t Gf = planar ? int64_t(nf) * nf : int64_t(nf) * nf * nf;
     const size_t fine_bytes = 2 * sizeof(T) * size_t(Gf);
-    const int64_t B = std::max<int64_t>(1, std::min<int64_t>(n_rot, int64_t(kNfftFineBudget / fine_bytes)));
+    int64_t B = std::max<int64_t>(1, std::min<int64_t>(n_rot, int64_t(kNfftFineBudget / fine_bytes)));
+    if (m > 0) B = std::max<int64_t>(1, std::min<int64_t>(B, (int64_t(1) << 30) / m));  // binned samples < 2^31
     const int nparts = sdf::peak_parts<T>(N, planar);
     Carve cv{nullptr};
     cv.take(sizeof(double) * 4 * n_rot);
@@ -789,6 +790,8 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
     cv.take(2 * sizeof(T) * G * B);
     cv.take(sizeof(T) * nparts * B);
     cv.take(sizeof(int) * nparts * B);
+    const size_t bin_bytes = sdf::nfft_workspace_bytes(m, int(B), N, planar, sizeof(T));
+    cv.take(bin_bytes);
     int rc = ensure_ws(ctx, cv.off);
     if (rc) return rc;
     Carve c2{static_cast<char*>(ctx->ws)};
@@ -800,6 +803,7 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
     void* grid = c2.take(2 * sizeof(T) * G * B);
     T* pval = static_cast<T*>(c2.take(sizeof(T) * nparts * B));
     int* pidx = static_cast<int*>(c2.take(sizeof(int) * nparts * B));
+    void* bins = c2.take(bin_bytes);
     SDF_TRY_HIP(ctx, hipMemcpyAsync(qd, quats, sizeof(double) * 4 * n_rot, hipMemcpyHostToDevice, s),
                 "quaternion upload");
     SDF_TRY_HIP(ctx, sdf::launch_quat_to_rot<T>(qd, n_rot, r64, RT, s), "rotations");
@@ -808,7 +812,7 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
         const int nb = int(std::min<int64_t>(B, n_rot - r0));
         SDF_TRY_HIP(ctx,
                     sdf::launch_nfft_modes<T>(static_cast<const T*>(pos), c, m, RT + 9 * r0, nb, N, planar, w, inv,
-                                              spec, fine, grid, s),
+                                              spec, fine, grid, bins, s),
                     "nonequispaced transform");
         SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, nb, +1, 1.0, s), "inverse fft");
         if (mode == Mode::Volume) {
@@ -836,7 +840,7 @@ int check_nfft_args(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const voi
         return fail(ctx, SDF_EINVAL, "g_fixed: must be N x N x N or N x N x 1");
     if (N != 8 && N != 16 && N != 32 && N != 64 && N != 128)
         return fail(ctx, SDF_EUNSUPPORTED, "g_fixed: the nonequispaced route needs N in {8, 16, 32, 64, 128}");
-    if (m < 0 || m > (int64_t(1) << 31)) return fail(ctx, SDF_EINVAL, "sample count must be in [0, 2^31]");
+    if (m < 0 || m > (int64_t(1) << 30)) return fail(ctx, SDF_EINVAL, "sample count must be in [0, 2^30]");
     if (w < 2 || w > 8) return fail(ctx, SDF_EINVAL, "kernel width must be in [2, 8]");
     rc = check_quats(ctx, quats, n_rot);
     if (rc) return rc;

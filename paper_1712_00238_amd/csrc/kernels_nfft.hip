@@ -17,6 +17,8 @@
 #include <hipcub/hipcub.hpp>
 
 #include "common.hpp"
+#include "fft.hpp"
+#include "fft256.hpp"
 #include "launch.hpp"
 
 namespace sdf {
@@ -208,114 +210,420 @@ constexpr int kEsQuad = 4096;
 // in FP64 converges fast even for narrow kernels, whose edge value e^-beta
 // is not small.
 template <typename T>
-__global__ void es_deconv_kernel(int N, int w, T* __restrict__ inv) {
-    const int jj = int(blockIdx.x * blockDim.x + threadIdx.x);
-    if (jj >= N) return;
+__global__ __launch_bounds__(256) void es_deconv_kernel(int N, int w, T* __restrict__ inv) {
+    __shared__ double red[4];
+    const int jj = int(blockIdx.x);
     const double kap = jj < N / 2 ? double(jj) : double(jj - N);
     const double beta = kEsBetaPerWidth * w, half = 0.5 * w, h = M_PI / kEsQuad;
     double acc = 0.0;
-    for (int q = 1; q < kEsQuad; ++q) {  // the end points contribute cos(+-pi/2) = 0
+    // interior Simpson nodes q = 1 .. kEsQuad - 1; the end points contribute cos(+-pi/2) = 0
+    for (int q = 1 + int(threadIdx.x); q < kEsQuad; q += 256) {
         const double th = -0.5 * M_PI + q * h;
         double st, ct;
         sincos(th, &st, &ct);
         const double g = exp(beta * (ct - 1.0)) * cospi(kap * half * st / double(N)) * half * ct;
         acc += (q & 1 ? 4.0 : 2.0) * g;
     }
-    inv[jj] = T(1.0 / (acc * h / 3.0));
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) inv[jj] = T(1.0 / ((red[0] + red[1] + red[2] + red[3]) * h / 3.0));
 }
 
-// One thread per sample and rotation: the reflected rotated position
-// -R x_k, doubled onto the fine grid of nf = 2N nodes (periodic), spread
-// over W^DIM nodes with global atomics.  `fine` must be zero.
-template <typename T, int DIM, int W>
-__global__ __launch_bounds__(256) void nfft_spread_kernel(const T* __restrict__ pos, const cplx<T>* __restrict__ c,
-                                                          int64_t m, const T* __restrict__ R, int nf,
-                                                          cplx<T>* __restrict__ fine) {
-    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (k >= m) return;
-    const cplx<T> ck = c[k];
-    if (ck.re == T(0) && ck.im == T(0)) return;
-    const T* r = R + 9 * blockIdx.y;
-    const T px = pos[3 * k], py = pos[3 * k + 1], pz = DIM == 3 ? pos[3 * k + 2] : T(0);
-    const int64_t gsz = DIM == 3 ? int64_t(nf) * nf * nf : int64_t(nf) * nf;
-    cplx<T>* g = fine + int64_t(blockIdx.y) * gsz;
-    const T beta = T(kEsBetaPerWidth * W), half = T(0.5 * W), zs = T(2.0 / W), fn = T(nf);
-    int l0[3] = {0, 0, 0};
-    T wt[3][W];
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        T y = -T(2) * (r[3 * a] * px + r[3 * a + 1] * py + r[3 * a + 2] * pz);
-        y = y - dev_floor(y / fn) * fn;
-        l0[a] = int(dceil(y - half));
-#pragma unroll
-        for (int q = 0; q < W; ++q) {
-            const T z = (T(l0[a] + q) - y) * zs;
-            const T s = T(1) - z * z;
-            wt[a][q] = s >= T(0) ? dexp(beta * (dsqrt(s) - T(1))) : T(0);
-        }
+// ------------------------------------------------------------------ tiled spreading
+// The oversampled grid is cut into tiles of at most 4096 nodes (3D 32 x 16 x 8,
+// planar 64 x 64, clipped to the grid).  Per rotation each sample is binned by
+// the tile that holds its first kernel node l0 = ceil(v - w/2), v being the
+// reflected rotated position on the 2x grid wrapped to [0, 2N).  As w is at
+// most every tile side, the sample's w nodes per axis lie in that tile or the
+// next one, so a tile gathers the samples of its own bin and of the bins just
+// below it along each axis, accumulates its nodes in LDS and stores each node
+// once (no zero pass, no global atomics).
+struct TileShape {
+    int tx, ty, tz;     // tile sides in nodes
+    int ntx, nty, ntz;  // tiles per axis
+    int py, pz;         // LDS pitches of a row and a plane (padded against bank conflicts)
+};
+constexpr int kTileLds = 4352;  // >= (tz - 1) pz + (ty - 1) py + tx for every shape below
+
+TileShape tile_shape(int nf, bool planar) {
+    TileShape t{};
+    if (planar) {
+        t.tx = nf < 64 ? nf : 64;
+        t.ty = t.tx;
+        t.tz = 1;
+    } else {
+        t.tx = nf < 32 ? nf : 32;
+        t.ty = nf < 16 ? nf : 16;
+        t.tz = nf < 8 ? nf : 8;
     }
-    if (DIM == 2) {
+    t.ntx = nf / t.tx;
+    t.nty = nf / t.ty;
+    t.ntz = planar ? 1 : nf / t.tz;
+    // rows one node longer and planes three more: a rotated cluster of
+    // samples then spreads over about twice as many banks
+    t.py = t.tx + 1;
+    t.pz = t.ty * t.py + 3;
+    return t;
+}
+
+// first kernel node along an axis (not wrapped); the bin and tile kernels
+// both take it from the same stored v
+template <typename T>
+__device__ __forceinline__ int first_node(T v, T half) {
+    return int(dceil(v - half));
+}
+
+__global__ void clear_ints_kernel(int* __restrict__ p, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = 0;
+}
+
+// SCATTER = false counts the samples of each (rotation, tile) bin; true
+// writes each sample's fine position (4 reals) and coefficient at
+// offsets[bin] + its rank in the bin (arrival order).  Zero samples are skipped.
+template <typename T, int DIM, bool SCATTER>
+__global__ __launch_bounds__(256) void nfft_bin_kernel(const T* __restrict__ pos, const cplx<T>* __restrict__ c,
+                                                       int64_t m, const T* __restrict__ R, int nf, int w, TileShape ts,
+                                                       int* __restrict__ counts, const int* __restrict__ offsets,
+                                                       int* __restrict__ cursor, T* __restrict__ vbuf,
+                                                       cplx<T>* __restrict__ cbuf) {
+    const int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int lane = int(threadIdx.x & 63);
+    const int rot = int(blockIdx.y);
+    cplx<T> ck = mk(T(0), T(0));
+    if (k < m) ck = c[k];
+    const bool active = k < m && (ck.re != T(0) || ck.im != T(0));
+    T v[3] = {T(0), T(0), T(0)};
+    int64_t bin = -1;
+    if (active) {
+        const T* r = R + 9 * rot;
+        const T px = pos[3 * k], py = pos[3 * k + 1], pz = DIM == 3 ? pos[3 * k + 2] : T(0);
+        const T fn = T(nf), half = T(0.5 * w);
+        int b[3] = {0, 0, 0};
 #pragma unroll
-        for (int b = 0; b < W; ++b) {
-            const int yy = wrap(l0[1] + b, nf);
+        for (int a = 0; a < DIM; ++a) {
+            const T y = -T(2) * (r[3 * a] * px + r[3 * a + 1] * py + r[3 * a + 2] * pz);
+            v[a] = y - dev_floor(y / fn) * fn;
+            b[a] = first_node(v[a], half) & (nf - 1);
+        }
+        const int nbins = ts.ntx * ts.nty * ts.ntz;
+        bin = int64_t(rot) * nbins + (b[2] / ts.tz * ts.nty + b[1] / ts.ty) * ts.ntx + b[0] / ts.tx;
+    }
+    // Samples are in Morton order, so a wave's lanes share few bins: each
+    // group of lanes with one bin makes one atomic, issued by its lowest lane.
+    unsigned long long pending = __ballot(active);
+    int64_t slot = 0;
+    while (pending) {
+        const int leader = __ffsll((long long)pending) - 1;
+        const int64_t lbin = __shfl(bin, leader);
+        const unsigned long long grp = __ballot(active && bin == lbin);
+        const int cnt = __popcll(grp);
+        if (!SCATTER) {
+            if (lane == leader) atomicAdd(&counts[lbin], cnt);
+        } else {
+            int base = 0;
+            if (lane == leader) base = offsets[lbin] + atomicAdd(&cursor[lbin], cnt);
+            base = __shfl(base, leader);
+            if ((grp >> lane) & 1ull) slot = int64_t(base) + __popcll(grp & ((1ull << lane) - 1ull));
+        }
+        pending &= ~grp;
+    }
+    if (SCATTER && active) {
+        vbuf[4 * slot] = v[0];
+        vbuf[4 * slot + 1] = v[1];
+        vbuf[4 * slot + 2] = v[2];
+        cbuf[slot] = ck;
+    }
+}
+
+// Fixed-point accumulation of a tile: LDS integer atomics run many times
+// faster than LDS float atomics.  Each tile takes its own scale from
+// S = sum over the samples that touch it of max(|Re c|, |Im c|): every term
+// c w (|w| <= 1) then maps to at most 2^30 (FP32, int32) or 2^62 (FP64,
+// int64) in magnitude, and so does every partial sum, in any order.
+template <typename T>
+struct TileAcc;
+template <>
+struct TileAcc<float> {
+    using A = int;
+    static constexpr double kOne = 1073741824.0;  // 2^30
+    __device__ static A to(float v) { return __float2int_rn(v); }
+    __device__ static float back(int a) { return float(a); }
+};
+template <>
+struct TileAcc<double> {
+    using A = unsigned long long;  // two's complement sums, read back as signed
+    static constexpr double kOne = 4611686018427387904.0;  // 2^62
+    __device__ static A to(double v) { return (unsigned long long)__double2ll_rn(v); }
+    __device__ static double back(unsigned long long a) { return double((long long)a); }
+};
+
+// per axis: do any of the W nodes o + q (mod nf) fall in [0, side)?
+template <int W>
+__device__ __forceinline__ bool reaches(int o, int side, int msk) {
+    bool hit = false;
 #pragma unroll
-            for (int a = 0; a < W; ++a) {
-                const T wgt = wt[0][a] * wt[1][b];
-                cplx<T>* p = g + int64_t(yy) * nf + wrap(l0[0] + a, nf);
-                atomicAdd(&p->re, ck.re * wgt);
-                atomicAdd(&p->im, ck.im * wgt);
+    for (int q = 0; q < W; ++q) hit |= ((o + q) & msk) < side;
+    return hit;
+}
+
+// One block per (tile, rotation): pass 1 sums S over the touching samples,
+// pass 2 spreads them in fixed point, then every node of the tile is stored.
+template <typename T, int DIM, int W>
+__global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vbuf, const cplx<T>* __restrict__ cbuf,
+                                                        const int* __restrict__ counts, const int* __restrict__ offsets,
+                                                        int nf, TileShape ts, cplx<T>* __restrict__ fine) {
+    using Acc = TileAcc<T>;
+    using A = typename Acc::A;
+    __shared__ A lre[kTileLds], lim[kTileLds];
+    __shared__ T red[4];
+    const int nbins = ts.ntx * ts.nty * ts.ntz;
+    const int tile = int(blockIdx.x), rot = int(blockIdx.y);
+    const int tbx = tile % ts.ntx, tby = (tile / ts.ntx) % ts.nty, tbz = tile / (ts.ntx * ts.nty);
+    const int org[3] = {tbx * ts.tx, tby * ts.ty, tbz * ts.tz};
+    const int side[3] = {ts.tx, ts.ty, ts.tz};
+    const int nodes = ts.tx * ts.ty * ts.tz;
+    const int msk = nf - 1;
+    const T half = T(0.5 * W), beta = T(kEsBetaPerWidth * W), zs = T(2.0 / W);
+    for (int e = int(threadIdx.x); e < kTileLds; e += 256) {
+        lre[e] = A(0);
+        lim[e] = A(0);
+    }
+    // the bins whose samples can reach this tile: its own and the ones just
+    // below it along each axis that has more than one tile
+    int bstart[8], bcount[8], nbs = 0;
+    for (int nb = 0; nb < (1 << DIM); ++nb) {
+        const int dx = nb & 1, dy = (nb >> 1) & 1, dz = (nb >> 2) & 1;
+        if ((dx && ts.ntx == 1) || (dy && ts.nty == 1) || (dz && ts.ntz == 1)) continue;
+        const int bx = (tbx - dx + ts.ntx) % ts.ntx, by = (tby - dy + ts.nty) % ts.nty;
+        const int bz = (tbz - dz + ts.ntz) % ts.ntz;
+        const int64_t bin = int64_t(rot) * nbins + (bz * ts.nty + by) * ts.ntx + bx;
+        bstart[nbs] = offsets[bin];
+        bcount[nbs] = counts[bin];
+        ++nbs;
+    }
+    // pass 1: S
+    T part = T(0);
+    for (int bi = 0; bi < nbs; ++bi) {
+        for (int p = int(threadIdx.x); p < bcount[bi]; p += 256) {
+            const int64_t at = int64_t(bstart[bi]) + p;
+            const T* vp = vbuf + 4 * at;
+            bool hit = true;
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) hit = hit && reaches<W>(first_node(vp[a], half) - org[a], side[a], msk);
+            if (hit) {
+                const cplx<T> ck = cbuf[at];
+                part += dmax(dabs(ck.re), dabs(ck.im));
             }
         }
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    const T S = red[0] + red[1] + red[2] + red[3];
+    const T sc = S > T(0) ? T(Acc::kOne) / S : T(0);
+    // pass 2: spread in fixed point
+    if (S > T(0)) {
+        for (int bi = 0; bi < nbs; ++bi) {
+            for (int p = int(threadIdx.x); p < bcount[bi]; p += 256) {
+                const int64_t at = int64_t(bstart[bi]) + p;
+                const T* vp = vbuf + 4 * at;
+                int o[3] = {0, 0, 0}, l0[3] = {0, 0, 0};
+                T va[3] = {T(0), T(0), T(0)};
+                bool hit = true;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    va[a] = vp[a];
+                    l0[a] = first_node(va[a], half);
+                    o[a] = l0[a] - org[a];
+                    hit = hit && reaches<W>(o[a], side[a], msk);
+                }
+                if (!hit) continue;
+                const cplx<T> ck = cbuf[at];
+                const T cre = ck.re * sc, cim = ck.im * sc;
+                T wt[3][W];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+#pragma unroll
+                    for (int q = 0; q < W; ++q) {
+                        const T z = (T(l0[a] + q) - va[a]) * zs;
+                        const T sq = T(1) - z * z;
+                        wt[a][q] = sq >= T(0) ? dexp(beta * (dsqrt(sq) - T(1))) : T(0);
+                    }
+                }
+                if (DIM == 2) {
+#pragma unroll
+                    for (int bq = 0; bq < W; ++bq) {
+                        const int iy = (o[1] + bq) & msk;
+                        if (iy >= ts.ty) continue;
+#pragma unroll
+                        for (int aq = 0; aq < W; ++aq) {
+                            const int ix = (o[0] + aq) & msk;
+                            if (ix >= ts.tx) continue;
+                            const T wgt = wt[0][aq] * wt[1][bq];
+                            atomicAdd(&lre[iy * ts.py + ix], Acc::to(cre * wgt));
+                            atomicAdd(&lim[iy * ts.py + ix], Acc::to(cim * wgt));
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int cq = 0; cq < W; ++cq) {
+                        const int iz = (o[2] + cq) & msk;
+                        if (iz >= ts.tz) continue;
+#pragma unroll
+                        for (int bq = 0; bq < W; ++bq) {
+                            const int iy = (o[1] + bq) & msk;
+                            if (iy >= ts.ty) continue;
+                            const T wyz = wt[1][bq] * wt[2][cq];
+                            const int rowo = iz * ts.pz + iy * ts.py;
+#pragma unroll
+                            for (int aq = 0; aq < W; ++aq) {
+                                const int ix = (o[0] + aq) & msk;
+                                if (ix >= ts.tx) continue;
+                                const T wgt = wt[0][aq] * wyz;
+                                atomicAdd(&lre[rowo + ix], Acc::to(cre * wgt));
+                                atomicAdd(&lim[rowo + ix], Acc::to(cim * wgt));
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const T inv = S > T(0) ? S / T(Acc::kOne) : T(0);
+    const int64_t gsz = DIM == 3 ? int64_t(nf) * nf * nf : int64_t(nf) * nf;
+    cplx<T>* g = fine + int64_t(rot) * gsz;
+    for (int e = int(threadIdx.x); e < nodes; e += 256) {
+        const int ix = e % ts.tx, iy = (e / ts.tx) % ts.ty, iz = e / (ts.tx * ts.ty);
+        const int l = iz * ts.pz + iy * ts.py + ix;
+        g[(int64_t(org[2] + iz) * nf + (org[1] + iy)) * nf + (org[0] + ix)] = mk(Acc::back(lre[l]) * inv, Acc::back(lim[l]) * inv);
+    }
+}
+
+// ------------------------------------------------------------------ pruned transform
+// Forward FFT of the 2N grid that keeps only the N central modes per axis:
+// each pass transforms full 2N-point lines in LDS and stores the N kept
+// outputs, so the next pass reads half as much (x: 2N^3 -> N (2N)^2 values,
+// y: -> N^2 2N, z: -> N^3).  The last pass divides by the kernel's transform
+// and multiplies by the fixed spectrum.
+
+// j-th of the N kept modes (FFT order) on the 2N grid
+__device__ __forceinline__ int fine_mode(int j, int N) { return j < N / 2 ? j : j + N; }
+
+template <typename T, int NF>
+__global__ __launch_bounds__(256) void nfft_rows_pruned_kernel(const cplx<T>* __restrict__ in,
+                                                               cplx<T>* __restrict__ out, int64_t nrows) {
+    constexpr int TPL = FFTShape<NF>::TPL, CONC = 256 / TPL, N = NF / 2;
+    __shared__ cplx<T> buf[CONC * NF];
+    __shared__ cplx<T> tw[NF];
+    fill_twiddles<T, NF>(tw);
+    const int64_t row0 = int64_t(blockIdx.x) * CONC;
+    const int nr = int(nrows - row0 < CONC ? nrows - row0 : CONC);
+    const cplx<T>* src = in + row0 * NF;
+    for (int i = int(threadIdx.x); i < nr * NF; i += 256) buf[i] = src[i];
+    __syncthreads();
+    lds_fft_lines<T, NF, -1, false>(buf, 1, NF, nr, tw);
+    cplx<T>* dst = out + row0 * N;
+    for (int i = int(threadIdx.x); i < nr * N; i += 256) {
+        const int r = i / N, j = i - r * N;
+        dst[i] = buf[r * NF + fine_mode(j, N)];
+    }
+}
+
+// columns per block: a power of two that the block's threads cover and that
+// divides N
+template <int NF>
+constexpr int pruned_width() {
+    int w = 1;
+    while (w * 2 <= 256 / FFTShape<NF>::TPL && w * 2 <= NF / 2) w *= 2;
+    return w;
+}
+
+// A block transforms W consecutive x columns along a strided axis (element
+// stride es_in) and stores the N kept outputs (stride es_out).  FINAL: the
+// axis is the last one (y of a planar grid, z in 3D); outputs are the modes
+// (jx, jy[, jz]) times inv[jx] inv[jy] [inv[jz]] spec.
+template <typename T, int NF, bool FINAL, bool PLANAR>
+__global__ __launch_bounds__(256) void nfft_cols_pruned_kernel(const cplx<T>* __restrict__ in,
+                                                               cplx<T>* __restrict__ out, int64_t es_in,
+                                                               int64_t os_in, int64_t bs_in, int64_t es_out,
+                                                               int64_t os_out, int64_t bs_out,
+                                                               const T* __restrict__ inv,
+                                                               const cplx<T>* __restrict__ spec) {
+    constexpr int W = pruned_width<NF>(), N = NF / 2;
+    __shared__ cplx<T> buf[NF * W];
+    __shared__ cplx<T> tw[NF];
+    fill_twiddles<T, NF>(tw);
+    const int x0 = int(blockIdx.x) * W, o = int(blockIdx.y), b = int(blockIdx.z);
+    const cplx<T>* src = in + int64_t(b) * bs_in + int64_t(o) * os_in + x0;
+    for (int i = int(threadIdx.x); i < NF * W; i += 256) {
+        const int e = i / W, xl = i - e * W;
+        buf[i] = src[int64_t(e) * es_in + xl];
+    }
+    __syncthreads();
+    lds_fft_lines<T, NF, -1, true>(buf, W, 1, W, tw);
+    cplx<T>* dst = out + int64_t(b) * bs_out + int64_t(o) * os_out + x0;
+    for (int i = int(threadIdx.x); i < N * W; i += 256) {
+        const int j = i / W, xl = i - j * W;
+        cplx<T> v = buf[fine_mode(j, N) * W + xl];
+        if (FINAL) {
+            const int jx = x0 + xl, jy = PLANAR ? j : o, jz = PLANAR ? 0 : j;
+            const T sc = inv[jx] * inv[jy] * (PLANAR ? T(1) : inv[jz]);
+            v = v * sc * spec[(int64_t(jz) * N + jy) * N + jx];
+        }
+        dst[int64_t(j) * es_out + xl] = v;
+    }
+}
+
+template <typename T, int NF>
+void pruned_transform(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_buf, int batch, bool planar,
+                      const T* inv, const cplx<T>* spec, cplx<T>* out, hipStream_t s) {
+    constexpr int N = NF / 2, TPL = FFTShape<NF>::TPL, CONC = 256 / TPL, W = pruned_width<NF>();
+    const int64_t nrows = int64_t(batch) * NF * (planar ? 1 : NF);
+    hipLaunchKernelGGL((nfft_rows_pruned_kernel<T, NF>), dim3(unsigned((nrows + CONC - 1) / CONC)), dim3(256), 0,
+                       s, fine, half_buf, nrows);
+    if (planar) {
+        // y, last: half_buf [b][y < NF][x < N] -> out [b][jy][jx]
+        hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, true>), dim3(N / W, 1, unsigned(batch)), dim3(256),
+                           0, s, half_buf, out, int64_t(N), int64_t(0), int64_t(NF) * N, int64_t(N), int64_t(0),
+                           int64_t(N) * N, inv, spec);
         return;
     }
-#pragma unroll
-    for (int cz = 0; cz < W; ++cz) {
-        const int zz = wrap(l0[2] + cz, nf);
-#pragma unroll
-        for (int b = 0; b < W; ++b) {
-            const int yy = wrap(l0[1] + b, nf);
-            const T wyz = wt[1][b] * wt[2][cz];
-            cplx<T>* row = g + (int64_t(zz) * nf + yy) * nf;
-#pragma unroll
-            for (int a = 0; a < W; ++a) {
-                const T wgt = wt[0][a] * wyz;
-                cplx<T>* p = row + wrap(l0[0] + a, nf);
-                atomicAdd(&p->re, ck.re * wgt);
-                atomicAdd(&p->im, ck.im * wgt);
-            }
-        }
-    }
+    // y: half_buf [b][z < NF][y < NF][x < N] -> quarter_buf [b][z < NF][jy][x < N]
+    hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, false, false>), dim3(N / W, NF, unsigned(batch)), dim3(256),
+                       0, s, half_buf, quarter_buf, int64_t(N), int64_t(NF) * N, int64_t(NF) * NF * N, int64_t(N),
+                       int64_t(N) * N, int64_t(NF) * N * N, inv, spec);
+    // z, last: quarter_buf [b][z < NF][jy][jx] -> out [b][jz][jy][jx]
+    hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, false>), dim3(N / W, N, unsigned(batch)), dim3(256), 0,
+                       s, quarter_buf, out, int64_t(N) * N, int64_t(N), int64_t(NF) * N * N, int64_t(N) * N,
+                       int64_t(N), int64_t(N) * N * N, inv, spec);
 }
 
-// The N^d central modes of the fine transform, deconvolved and multiplied by
-// the fixed part's spectrum: out[b][j] = G[b][j mod-shifted] inv inv inv spec[j].
 template <typename T>
-__global__ void nfft_crop_kernel(const cplx<T>* __restrict__ fine, int N, int planar, int batch,
-                                 const T* __restrict__ inv, const cplx<T>* __restrict__ spec,
-                                 cplx<T>* __restrict__ out) {
-    const int nf = 2 * N;
-    const int64_t G = planar ? int64_t(N) * N : int64_t(N) * N * N;
-    const int64_t Gf = planar ? int64_t(nf) * nf : int64_t(nf) * nf * nf;
-    const int64_t total = G * batch;
-    for (int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; e < total;
-         e += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t b = e / G, idx = e - b * G;
-        const int jx = int(idx % N), jy = int((idx / N) % N), jz = planar ? 0 : int(idx / (int64_t(N) * N));
-        const int fx = jx < N / 2 ? jx : jx + N, fy = jy < N / 2 ? jy : jy + N;
-        const int fz = planar ? 0 : (jz < N / 2 ? jz : jz + N);
-        const T sc = inv[jx] * inv[jy] * (planar ? T(1) : inv[jz]);
-        out[e] = fine[b * Gf + (int64_t(fz) * nf + fy) * nf + fx] * sc * spec[idx];
+hipError_t launch_pruned(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_buf, int batch, int N, bool planar,
+                         const T* inv, const cplx<T>* spec, cplx<T>* out, hipStream_t s) {
+    switch (2 * N) {
+        case 16: pruned_transform<T, 16>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
+        case 32: pruned_transform<T, 32>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
+        case 64: pruned_transform<T, 64>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
+        case 128: pruned_transform<T, 128>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
+        case 256: pruned_transform<T, 256>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
+        default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
 }
 
 template <typename T, int DIM>
-hipError_t spread_width(const T* pos, const cplx<T>* c, int64_t m, const T* R, int batch, int nf, int w,
-                        cplx<T>* fine, hipStream_t s) {
-    const dim3 grid(unsigned((m + 255) / 256), unsigned(batch));
+hipError_t tile_width(const T* vbuf, const cplx<T>* cbuf, const int* counts, const int* offsets, int batch, int nf,
+                      int w, TileShape ts, cplx<T>* fine, hipStream_t s) {
+    const dim3 grid(unsigned(ts.ntx * ts.nty * ts.ntz), unsigned(batch));
     switch (w) {
-#define SDF_NFFT_W(WW)                                                                                          \
-    case WW:                                                                                                    \
-        hipLaunchKernelGGL((nfft_spread_kernel<T, DIM, WW>), grid, dim3(256), 0, s, pos, c, m, R, nf, fine); \
+#define SDF_NFFT_W(WW)                                                                                         \
+    case WW:                                                                                                   \
+        hipLaunchKernelGGL((nfft_tile_kernel<T, DIM, WW>), grid, dim3(256), 0, s, vbuf, cbuf, counts, offsets, \
+                           nf, ts, fine);                                                                      \
         break;
         SDF_NFFT_W(2)
         SDF_NFFT_W(3)
@@ -329,6 +637,42 @@ hipError_t spread_width(const T* pos, const cplx<T>* c, int64_t m, const T* R, i
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// workspace of launch_nfft_modes: bin counts, cursors and offsets per
+// (rotation, tile), the binned samples (4 + 2 reals each), scan temporaries
+struct NfftWs {
+    size_t counts, cursor, offsets, vbuf, cbuf, half, temp, temp_bytes, total;
+};
+
+NfftWs nfft_ws_layout(int64_t m, int batch, int N, bool planar, size_t elem) {
+    const TileShape ts = tile_shape(2 * N, planar);
+    const int64_t nb = int64_t(ts.ntx) * ts.nty * ts.ntz * batch;
+    size_t temp_bytes = 0;
+    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, static_cast<const int*>(nullptr),
+                                           static_cast<int*>(nullptr), int(nb));
+    const size_t nbi = size_t(nb) * sizeof(int), ns = size_t(m) * size_t(batch);
+    NfftWs L{};
+    size_t off = 0;
+    L.counts = off;
+    off += (nbi + 255) / 256 * 256;
+    L.cursor = off;
+    off += (nbi + 255) / 256 * 256;
+    L.offsets = off;
+    off += (nbi + 255) / 256 * 256;
+    L.vbuf = off;
+    off += (4 * elem * ns + 255) / 256 * 256;
+    L.cbuf = off;
+    off += (2 * elem * ns + 255) / 256 * 256;
+    // x-pruned transform: N (2N)^2 (planar N 2N) values per rotation
+    const size_t hv = size_t(N) * 2 * N * (planar ? 1 : 2 * N) * size_t(batch);
+    L.half = off;
+    off += (2 * elem * hv + 255) / 256 * 256;
+    L.temp = off;
+    L.temp_bytes = temp_bytes;
+    off += (temp_bytes + 255) / 256 * 256;
+    L.total = off;
+    return L;
 }
 
 // workspace of launch_octree: coefficients, A, per-block counts and
@@ -410,31 +754,61 @@ hipError_t launch_octree(const void* rho_m, const T* w_m, int nm, bool planar, d
 
 template <typename T>
 hipError_t launch_es_deconv(int N, int w, T* inv, hipStream_t s) {
-    hipLaunchKernelGGL((es_deconv_kernel<T>), dim3(unsigned((N + 63) / 64)), dim3(64), 0, s, N, w, inv);
+    hipLaunchKernelGGL((es_deconv_kernel<T>), dim3(unsigned(N)), dim3(256), 0, s, N, w, inv);
     return hipGetLastError();
+}
+
+size_t nfft_workspace_bytes(int64_t m, int batch, int N, bool planar, size_t elem) {
+    return nfft_ws_layout(m, batch, N, planar, elem).total;
 }
 
 template <typename T>
 hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
-                             int w, const T* inv, const void* spec, void* fine, void* out, hipStream_t s) {
+                             int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s) {
     const int nf = 2 * N;
-    const int64_t Gf = planar ? int64_t(nf) * nf : int64_t(nf) * nf * nf;
-    const int64_t G = planar ? int64_t(N) * N : int64_t(N) * N * N;
-    hipError_t e = launch_zero<T>(fine, Gf * batch, s);
-    if (e != hipSuccess) return e;
+    const TileShape ts = tile_shape(nf, planar);
+    const NfftWs L = nfft_ws_layout(m, batch, N, planar, sizeof(T));
+    char* base = static_cast<char*>(ws);
+    int* counts = reinterpret_cast<int*>(base + L.counts);
+    int* cursor = reinterpret_cast<int*>(base + L.cursor);
+    int* offsets = reinterpret_cast<int*>(base + L.offsets);
+    T* vbuf = reinterpret_cast<T*>(base + L.vbuf);
+    cplx<T>* cbuf = reinterpret_cast<cplx<T>*>(base + L.cbuf);
+    const int64_t nb = int64_t(ts.ntx) * ts.nty * ts.ntz * batch;
     const cplx<T>* cc = static_cast<const cplx<T>*>(c);
     cplx<T>* fg = static_cast<cplx<T>*>(fine);
+    const int64_t zb = (2 * nb + 255) / 256;
+        hipLaunchKernelGGL(clear_ints_kernel, dim3(unsigned(zb < 4096 ? zb : 4096)), dim3(256), 0, s, counts, nb);
+    hipLaunchKernelGGL(clear_ints_kernel, dim3(unsigned(zb < 4096 ? zb : 4096)), dim3(256), 0, s, cursor, nb);
     if (m > 0) {
-        e = planar ? spread_width<T, 2>(pos, cc, m, R, batch, nf, w, fg, s)
-                   : spread_width<T, 3>(pos, cc, m, R, batch, nf, w, fg, s);
-        if (e != hipSuccess) return e;
+        const dim3 g(unsigned((m + 255) / 256), unsigned(batch));
+        if (planar)
+            hipLaunchKernelGGL((nfft_bin_kernel<T, 2, false>), g, dim3(256), 0, s, pos, cc, m, R, nf, w, ts, counts,
+                               offsets, cursor, vbuf, cbuf);
+        else
+            hipLaunchKernelGGL((nfft_bin_kernel<T, 3, false>), g, dim3(256), 0, s, pos, cc, m, R, nf, w, ts, counts,
+                               offsets, cursor, vbuf, cbuf);
     }
-    e = launch_fft3<T>(fine, nf, planar, batch, -1, 1.0, s);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int64_t cb = (G * batch + 255) / 256;
-    hipLaunchKernelGGL((nfft_crop_kernel<T>), dim3(unsigned(cb < 16384 ? cb : 16384)), dim3(256), 0, s, fg, N,
-                       planar ? 1 : 0, batch, inv, static_cast<const cplx<T>*>(spec), static_cast<cplx<T>*>(out));
-    return hipGetLastError();
+    size_t tb = L.temp_bytes;
+    e = hipcub::DeviceScan::ExclusiveSum(base + L.temp, tb, counts, offsets, int(nb), s);
+    if (e != hipSuccess) return e;
+    if (m > 0) {
+        const dim3 g(unsigned((m + 255) / 256), unsigned(batch));
+        if (planar)
+            hipLaunchKernelGGL((nfft_bin_kernel<T, 2, true>), g, dim3(256), 0, s, pos, cc, m, R, nf, w, ts, counts,
+                               offsets, cursor, vbuf, cbuf);
+        else
+            hipLaunchKernelGGL((nfft_bin_kernel<T, 3, true>), g, dim3(256), 0, s, pos, cc, m, R, nf, w, ts, counts,
+                               offsets, cursor, vbuf, cbuf);
+    }
+    e = planar ? tile_width<T, 2>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s)
+               : tile_width<T, 3>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s);
+    if (e != hipSuccess) return e;
+    // the y pass's output reuses the oversampled grids, free after the x pass
+    return launch_pruned<T>(fg, reinterpret_cast<cplx<T>*>(base + L.half), fg, batch, N, planar, inv,
+                            static_cast<const cplx<T>*>(spec), static_cast<cplx<T>*>(out), s);
 }
 
 template hipError_t launch_octree<float>(const void*, const float*, int, bool, double, int, float*, void*, int*,
@@ -444,8 +818,8 @@ template hipError_t launch_octree<double>(const void*, const double*, int, bool,
 template hipError_t launch_es_deconv<float>(int, int, float*, hipStream_t);
 template hipError_t launch_es_deconv<double>(int, int, double*, hipStream_t);
 template hipError_t launch_nfft_modes<float>(const float*, const void*, int64_t, const float*, int, int, bool, int,
-                                             const float*, const void*, void*, void*, hipStream_t);
+                                             const float*, const void*, void*, void*, void*, hipStream_t);
 template hipError_t launch_nfft_modes<double>(const double*, const void*, int64_t, const double*, int, int, bool,
-                                              int, const double*, const void*, void*, void*, hipStream_t);
+                                              int, const double*, const void*, void*, void*, void*, hipStream_t);
 
 }  // namespace sdf

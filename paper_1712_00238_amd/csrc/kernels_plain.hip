@@ -6,15 +6,10 @@
 // straightforward baseline the fused FP32 kernels are measured against.
 #include "common.hpp"
 #include "fft.hpp"
+#include "fft256.hpp"
 #include "launch.hpp"
 
 namespace sdf {
-
-// 256-point lines (the 2x oversampled grid of the nonequispaced route)
-template <>
-struct DefaultPlan<256> {
-    using type = Radices<8, 8, 4>;
-};
 
 namespace {
 

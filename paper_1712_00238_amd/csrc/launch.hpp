@@ -152,12 +152,14 @@ hipError_t launch_octree(const void* rho_m, const T* w_m, int nm, bool planar, d
 // 1 / phihat of the width-w kernel for the N FFT-order modes of the 2N grid
 template <typename T>
 hipError_t launch_es_deconv(int N, int w, T* inv, hipStream_t s);
-// `batch` rotations R[b] (9 T each) of the m samples: zero the (2N)^d grids
-// `fine`, spread, transform, and write out[b] = deconvolved N^d modes times
-// spec (ready for the inverse FFT of the correlation)
+// `batch` rotations R[b] (9 T each) of the m samples: bin them per tile of
+// the (2N)^d grids `fine`, spread tile by tile (every node written),
+// transform, and write out[b] = deconvolved N^d modes times spec (ready for
+// the inverse FFT of the correlation); ws holds nfft_workspace_bytes
+size_t nfft_workspace_bytes(int64_t m, int batch, int N, bool planar, size_t elem);
 template <typename T>
 hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
-                             int w, const T* inv, const void* spec, void* fine, void* out, hipStream_t s);
+                             int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s);
 
 // ---- top-k
 template <typename T>
