@@ -71,8 +71,14 @@ __global__ __launch_bounds__(256) void absmax_kernel(const cplx<T>* __restrict__
         const cplx<T> v = c[i];
         m = dmax(m, dmax(dabs(v.re), dabs(v.im)));
     }
+    __shared__ T wmax[4];
     for (int off = 32; off > 0; off >>= 1) m = dmax(m, __shfl_xor(m, off));
-    if ((threadIdx.x & 63) == 0 && m > T(0)) atomicMax(out, to_bits(m));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = dmax(dmax(wmax[0], wmax[1]), dmax(wmax[2], wmax[3]));
+        if (m > T(0)) atomicMax(out, to_bits(m));  // one atomic per block
+    }
 }
 
 constexpr int kOctBlock = 512;
@@ -726,7 +732,7 @@ hipError_t launch_octree(const void* rho_m, const T* w_m, int nm, bool planar, d
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((clear_bits_kernel<U>), dim3(1), dim3(64), 0, s, amax);
     const int64_t ab = (K + 255) / 256;
-    hipLaunchKernelGGL((absmax_kernel<T>), dim3(unsigned(ab < 2048 ? ab : 2048)), dim3(256), 0, s, coef, K, amax);
+    hipLaunchKernelGGL((absmax_kernel<T>), dim3(unsigned(ab < 512 ? ab : 512)), dim3(256), 0, s, coef, K, amax);
     const T tl = T(tol);
     cplx<T>* oc = static_cast<cplx<T>*>(c_out);
     if (planar) {
