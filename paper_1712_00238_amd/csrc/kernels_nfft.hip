@@ -16,6 +16,8 @@
 
 #include <hipcub/hipcub.hpp>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "fft.hpp"
 #include "fft256.hpp"
@@ -252,8 +254,27 @@ struct TileShape {
 };
 constexpr int kTileLds = 4352;  // >= (tz - 1) pz + (ty - 1) py + tx for every shape below
 
-TileShape tile_shape(int nf, bool planar) {
+// Line tiles (FP32 3D): whole periodic x lines of 8 x 8 (y, z) rows, so no x
+// tap needs a test; one block of 1024 threads per CU holds the 128 KiB of
+// integer rows.
+constexpr int kLineRows = 8;
+constexpr int kLineBlock = 1024;
+
+inline int line_pitch(int nf) { return nf + 11; }  // nf + 8 wrap slots, odd against bank aliasing of rows
+
+TileShape tile_shape(int nf, bool planar, bool line) {
     TileShape t{};
+    if (line) {
+        t.tx = nf;
+        t.ty = kLineRows;
+        t.tz = kLineRows;
+        t.ntx = 1;
+        t.nty = nf / kLineRows;
+        t.ntz = nf / kLineRows;
+        t.py = line_pitch(nf);
+        t.pz = kLineRows * t.py;
+        return t;
+    }
     if (planar) {
         t.tx = nf < 64 ? nf : 64;
         t.ty = t.tx;
@@ -621,6 +642,141 @@ hipError_t launch_pruned(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarte
     return hipGetLastError();
 }
 
+// Line tile (FP32, 3D): one block per (8 x 8 rows of whole x lines, rotation).
+// Samples of the tile's bin and of the bins below it in y and z; per
+// sample, each of its W^2 (y, z) rows that lies in the tile is one branch
+// with W unconditional integer adds at constant offsets from the row base
+// (x positions past the line's end land in 8 spare slots, folded back when
+// the row is stored).  Fixed-point scale per tile as in nfft_tile_kernel.
+constexpr int kLineLds = kLineRows * kLineRows * (256 + 11);  // ints per plane at nf = 256
+
+template <int W>
+__global__ __launch_bounds__(kLineBlock) void nfft_line_tile_kernel(const float* __restrict__ vbuf,
+                                                                    const cplx<float>* __restrict__ cbuf,
+                                                                    const int* __restrict__ counts,
+                                                                    const int* __restrict__ offsets, int nf,
+                                                                    TileShape ts, cplx<float>* __restrict__ fine) {
+    __shared__ int lre[kLineLds], lim[kLineLds];
+    __shared__ float red[kLineBlock / 64];
+    const int nbins = ts.nty * ts.ntz;
+    const int tile = int(blockIdx.x), rot = int(blockIdx.y);
+    const int tby = tile % ts.nty, tbz = tile / ts.nty;
+    const int y0 = tby * kLineRows, z0 = tbz * kLineRows;
+    const int px = ts.py;
+    const int used = kLineRows * kLineRows * px;
+    const int msk = nf - 1;
+    const float half = float(0.5 * W), beta = float(kEsBetaPerWidth * W), zs = float(2.0 / W);
+    int bstart[4], bcount[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int by = (tby - (nb & 1) + ts.nty) % ts.nty, bz = (tbz - (nb >> 1) + ts.ntz) % ts.ntz;
+        const int64_t bin = int64_t(rot) * nbins + bz * ts.nty + by;
+        bstart[nb] = offsets[bin];
+        bcount[nb] = counts[bin];
+    }
+    // y / z offset of a sample's first window row from the tile, in (-nf/2, nf/2]
+    auto rel = [&](float v, int org) { return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2; };
+    float part = 0.f;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
+            const int64_t at = int64_t(bstart[nb]) + p;
+            const float* vp = vbuf + 4 * at;
+            const int oy = rel(vp[1], y0), oz = rel(vp[2], z0);
+            if (oy > -W && oy < kLineRows && oz > -W && oz < kLineRows) {
+                const cplx<float> ck = cbuf[at];
+                part += fmaxf(fabsf(ck.re), fabsf(ck.im));
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    float S = 0.f;
+#pragma unroll
+    for (int i = 0; i < kLineBlock / 64; ++i) S += red[i];
+    cplx<float>* g = fine + int64_t(rot) * nf * nf * nf;
+    const int sh = __ffs(nf) - 1;  // nf is a power of two
+    if (!(S > 0.f)) {  // no sample reaches the tile: store zeros, skip the LDS work
+        for (int e = int(threadIdx.x); e < kLineRows * kLineRows * nf; e += kLineBlock) {
+            const int x = e & msk, row = e >> sh;
+            g[(int64_t(z0 + row / kLineRows) * nf + (y0 + row % kLineRows)) * nf + x] = mk(0.f, 0.f);
+        }
+        return;
+    }
+    for (int e = int(threadIdx.x); e < used; e += kLineBlock) {
+        lre[e] = 0;
+        lim[e] = 0;
+    }
+    __syncthreads();
+    const float sc = float(TileAcc<float>::kOne) / S;
+    {
+#pragma unroll 1
+        for (int nb = 0; nb < 4; ++nb) {
+            for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
+                const int64_t at = int64_t(bstart[nb]) + p;
+                const float* vp = vbuf + 4 * at;
+                const float vx = vp[0], vy = vp[1], vz = vp[2];
+                const int oy = rel(vy, y0), oz = rel(vz, z0);
+                if (!(oy > -W && oy < kLineRows && oz > -W && oz < kLineRows)) continue;
+                const int lx = first_node(vx, half);
+                const int ly = first_node(vy, half), lz = first_node(vz, half);
+                const cplx<float> ck = cbuf[at];
+                float xr[W], xi[W], wy[W], wz[W];
+#pragma unroll
+                for (int q = 0; q < W; ++q) {
+                    const float zx = (float(lx + q) - vx) * zs, zy = (float(ly + q) - vy) * zs,
+                                zz = (float(lz + q) - vz) * zs;
+                    const float sx = 1.f - zx * zx, sy = 1.f - zy * zy, sz = 1.f - zz * zz;
+                    const float wx = sx >= 0.f ? expf(beta * (sqrtf(sx) - 1.f)) : 0.f;
+                    wy[q] = sy >= 0.f ? expf(beta * (sqrtf(sy) - 1.f)) : 0.f;
+                    wz[q] = sz >= 0.f ? expf(beta * (sqrtf(sz) - 1.f)) : 0.f;
+                    xr[q] = ck.re * sc * wx;
+                    xi[q] = ck.im * sc * wx;
+                }
+                const int xb = lx & msk;  // taps xb .. xb + W - 1 < nf + 8
+#pragma unroll
+                for (int cq = 0; cq < W; ++cq) {
+                    const int iz = oz + cq;
+#pragma unroll
+                    for (int bq = 0; bq < W; ++bq) {
+                        const int iy = oy + bq;
+                        if (unsigned(iz) < unsigned(kLineRows) && unsigned(iy) < unsigned(kLineRows)) {
+                            const float wyz = wy[bq] * wz[cq];
+                            int* rr = lre + (iz * kLineRows + iy) * px + xb;
+                            int* ri = lim + (iz * kLineRows + iy) * px + xb;
+#pragma unroll
+                            for (int aq = 0; aq < W; ++aq) {
+                                atomicAdd(rr + aq, __float2int_rn(xr[aq] * wyz));
+                                atomicAdd(ri + aq, __float2int_rn(xi[aq] * wyz));
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const float inv = S / float(TileAcc<float>::kOne);
+    for (int e = int(threadIdx.x); e < kLineRows * kLineRows * nf; e += kLineBlock) {
+        const int x = e & msk, row = e >> sh;  // row = iz * 8 + iy
+        const int iy = row % kLineRows, iz = row / kLineRows;
+        int ar = lre[row * px + x], ai = lim[row * px + x];
+        if (x < 8) {  // fold the wrap slots
+            ar += lre[row * px + nf + x];
+            ai += lim[row * px + nf + x];
+        }
+        g[(int64_t(z0 + iz) * nf + (y0 + iy)) * nf + x] = mk(float(ar) * inv, float(ai) * inv);
+    }
+}
+
+template <int W>
+void launch_line_tile(const float* vbuf, const cplx<float>* cbuf, const int* counts, const int* offsets, int batch,
+                      int nf, TileShape ts, cplx<float>* fine, hipStream_t s) {
+    hipLaunchKernelGGL((nfft_line_tile_kernel<W>), dim3(unsigned(ts.nty * ts.ntz), unsigned(batch)),
+                       dim3(kLineBlock), 0, s, vbuf, cbuf, counts, offsets, nf, ts, fine);
+}
+
 template <typename T, int DIM>
 hipError_t tile_width(const T* vbuf, const cplx<T>* cbuf, const int* counts, const int* offsets, int batch, int nf,
                       int w, TileShape ts, cplx<T>* fine, hipStream_t s) {
@@ -651,8 +807,12 @@ struct NfftWs {
     size_t counts, cursor, offsets, vbuf, cbuf, half, temp, temp_bytes, total;
 };
 
+// FP32 3D grids use line tiles; FP64 (whose 64-bit rows would not fit) and
+// planar grids the general tiles
+bool use_lines(bool planar, size_t elem) { return !planar && elem == sizeof(float); }
+
 NfftWs nfft_ws_layout(int64_t m, int batch, int N, bool planar, size_t elem) {
-    const TileShape ts = tile_shape(2 * N, planar);
+    const TileShape ts = tile_shape(2 * N, planar, use_lines(planar, elem));
     const int64_t nb = int64_t(ts.ntx) * ts.nty * ts.ntz * batch;
     size_t temp_bytes = 0;
     (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, static_cast<const int*>(nullptr),
@@ -772,7 +932,8 @@ template <typename T>
 hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
                              int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s) {
     const int nf = 2 * N;
-    const TileShape ts = tile_shape(nf, planar);
+    const bool lines = use_lines(planar, sizeof(T));
+    const TileShape ts = tile_shape(nf, planar, lines);
     const NfftWs L = nfft_ws_layout(m, batch, N, planar, sizeof(T));
     char* base = static_cast<char*>(ws);
     int* counts = reinterpret_cast<int*>(base + L.counts);
@@ -809,8 +970,27 @@ hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R,
             hipLaunchKernelGGL((nfft_bin_kernel<T, 3, true>), g, dim3(256), 0, s, pos, cc, m, R, nf, w, ts, counts,
                                offsets, cursor, vbuf, cbuf);
     }
-    e = planar ? tile_width<T, 2>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s)
-               : tile_width<T, 3>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s);
+    if constexpr (std::is_same<T, float>::value) {
+        if (lines) {
+            switch (w) {
+                case 2: launch_line_tile<2>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
+                case 3: launch_line_tile<3>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
+                case 4: launch_line_tile<4>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
+                case 5: launch_line_tile<5>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
+                case 6: launch_line_tile<6>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
+                case 7: launch_line_tile<7>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
+                case 8: launch_line_tile<8>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
+                default: return hipErrorInvalidValue;
+            }
+            e = hipGetLastError();
+        } else {
+            e = planar ? tile_width<T, 2>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s)
+                       : tile_width<T, 3>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s);
+        }
+    } else {
+        e = planar ? tile_width<T, 2>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s)
+                   : tile_width<T, 3>(vbuf, cbuf, counts, offsets, batch, nf, w, ts, fg, s);
+    }
     if (e != hipSuccess) return e;
     // the y pass's output reuses the oversampled grids, free after the x pass
     return launch_pruned<T>(fg, reinterpret_cast<cplx<T>*>(base + L.half), fg, batch, N, planar, inv,
