@@ -108,6 +108,27 @@ def test_argument_validation_without_a_device():
     assert lib.sdf_topk(null, dummy, 10, 11, dummy, null) == _lib.SDF_EINVAL
     assert lib.score_grad(null, dummy, ctypes.byref(g), dummy, dummy, ctypes.byref(gm6), dummy, 0, dummy, null, null,
                           null, null) == _lib.SDF_EINVAL
+    # octree samples: N_M a multiple of 8, max_level <= 3, finite tol >= 0
+    cnt = ctypes.c_void_p(8192)
+    for n_m, lev, tol in ((12, 3, 0.1), (16, 4, 0.1), (16, -1, 0.1), (16, 3, -0.5), (16, 3, math.nan)):
+        gmo = grid((n_m, n_m, n_m))
+        assert lib.octree_samples(null, dummy, dummy, ctypes.byref(gmo), tol, lev, dummy, dummy, null, cnt,
+                                  null) == _lib.SDF_EINVAL, (n_m, lev, tol)
+    g16m = grid((16, 16, 16))
+    assert lib.octree_samples(null, dummy, dummy, ctypes.byref(g16m), 0.1, 3, dummy, dummy, null, cnt,
+                              null) == _lib.SDF_EINVAL and "ctx is NULL" in err_of(lib)
+    # nonequispaced route: power-of-two N, width in [2, 8], sample count >= 0
+    assert lib.score_volume_nfft(null, dummy, ctypes.byref(g), dummy, dummy, 10, 9, qp, 1, dummy,
+                                 null) == _lib.SDF_EINVAL and "width" in err_of(lib)
+    assert lib.score_volume_nfft(null, dummy, ctypes.byref(g), dummy, dummy, -1, 6, qp, 1, dummy,
+                                 null) == _lib.SDF_EINVAL
+    g96 = grid((96, 96, 96))
+    assert lib.score_volume_nfft(null, dummy, ctypes.byref(g96), dummy, dummy, 10, 6, qp, 1, dummy,
+                                 null) == _lib.SDF_EUNSUPPORTED
+    assert lib.score_rotations_nfft(null, dummy, ctypes.byref(g), dummy, dummy, 10, 6, qz.ctypes.data_as(
+        ctypes.c_void_p), 1, dummy, dummy, null, null, null) == _lib.SDF_EINVAL and "zero quaternion" in err_of(lib)
+    assert lib.score_rotations_nfft(null, dummy, ctypes.byref(g), null, null, 0, 6, qp, 1, dummy, dummy, null, null,
+                                    null) == _lib.SDF_EINVAL and "ctx is NULL" in err_of(lib)
     # options need a context
     assert lib.sdf_ctx_set_option(null, b"batch", 8) == _lib.SDF_EINVAL
     # context creation rejects bad dtypes and out pointers
