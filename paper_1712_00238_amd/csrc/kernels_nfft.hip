@@ -604,13 +604,15 @@ __global__ __launch_bounds__(256) void nfft_cols_pruned_kernel(const cplx<T>* __
     }
 }
 
+// rows_done: the x pass already wrote half_buf (fused into the line tiles)
 template <typename T, int NF>
 void pruned_transform(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_buf, int batch, bool planar,
-                      const T* inv, const cplx<T>* spec, cplx<T>* out, hipStream_t s) {
+                      const T* inv, const cplx<T>* spec, cplx<T>* out, bool rows_done, hipStream_t s) {
     constexpr int N = NF / 2, TPL = FFTShape<NF>::TPL, CONC = 256 / TPL, W = pruned_width<NF>();
     const int64_t nrows = int64_t(batch) * NF * (planar ? 1 : NF);
-    hipLaunchKernelGGL((nfft_rows_pruned_kernel<T, NF>), dim3(unsigned((nrows + CONC - 1) / CONC)), dim3(256), 0,
-                       s, fine, half_buf, nrows);
+    if (!rows_done)
+        hipLaunchKernelGGL((nfft_rows_pruned_kernel<T, NF>), dim3(unsigned((nrows + CONC - 1) / CONC)), dim3(256),
+                           0, s, fine, half_buf, nrows);
     if (planar) {
         // y, last: half_buf [b][y < NF][x < N] -> out [b][jy][jx]
         hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, true>), dim3(N / W, 1, unsigned(batch)), dim3(256),
@@ -630,13 +632,18 @@ void pruned_transform(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_b
 
 template <typename T>
 hipError_t launch_pruned(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_buf, int batch, int N, bool planar,
-                         const T* inv, const cplx<T>* spec, cplx<T>* out, hipStream_t s) {
+                         const T* inv, const cplx<T>* spec, cplx<T>* out, bool rows_done, hipStream_t s) {
     switch (2 * N) {
-        case 16: pruned_transform<T, 16>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
-        case 32: pruned_transform<T, 32>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
-        case 64: pruned_transform<T, 64>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
-        case 128: pruned_transform<T, 128>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
-        case 256: pruned_transform<T, 256>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, s); break;
+#define SDF_PRUNED(NF)                                                                                             \
+    case NF:                                                                                                       \
+        pruned_transform<T, NF>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, rows_done, s);          \
+        break;
+        SDF_PRUNED(16)
+        SDF_PRUNED(32)
+        SDF_PRUNED(64)
+        SDF_PRUNED(128)
+        SDF_PRUNED(256)
+#undef SDF_PRUNED
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -775,6 +782,185 @@ void launch_line_tile(const float* vbuf, const cplx<float>* cbuf, const int* cou
                       int nf, TileShape ts, cplx<float>* fine, hipStream_t s) {
     hipLaunchKernelGGL((nfft_line_tile_kernel<W>), dim3(unsigned(ts.nty * ts.ntz), unsigned(batch)),
                        dim3(kLineBlock), 0, s, vbuf, cbuf, counts, offsets, nf, ts, fine);
+}
+
+// Line tile with the x pass of the pruned transform fused in (FP32, 3D,
+// 2N >= 32): after the fixed-point accumulation the tile's 64 x lines are
+// converted to complex in the same LDS, transformed there (2N points), and
+// only the N kept modes of each line are stored, into the x-pruned buffer
+// [b][z][y][N] that the y pass reads.  The oversampled grid itself is never
+// written to memory.
+template <int W, int NF>
+__global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* __restrict__ vbuf,
+                                                                   const cplx<float>* __restrict__ cbuf,
+                                                                   const int* __restrict__ counts,
+                                                                   const int* __restrict__ offsets, TileShape ts,
+                                                                   cplx<float>* __restrict__ half_buf) {
+    constexpr int nf = NF, N = NF / 2, msk = NF - 1, ROWS = kLineRows * kLineRows;
+    constexpr int PER = ROWS * NF / kLineBlock;  // converted values per thread
+    static_assert(ROWS * NF * sizeof(cplx<float>) <= 2 * kLineLds * sizeof(int), "complex rows exceed the LDS");
+    __shared__ __align__(16) int acc[2 * kLineLds];
+    __shared__ cplx<float> tw[NF];
+    __shared__ float red[kLineBlock / 64];
+    int* lre = acc;
+    int* lim = acc + kLineLds;
+    cplx<float>* cb = reinterpret_cast<cplx<float>*>(acc);
+    fill_twiddles<float, NF>(tw);
+    const int nbins = ts.nty * ts.ntz;
+    const int tile = int(blockIdx.x), rot = int(blockIdx.y);
+    const int tby = tile % ts.nty, tbz = tile / ts.nty;
+    const int y0 = tby * kLineRows, z0 = tbz * kLineRows;
+    const int px = ts.py;
+    const float half = float(0.5 * W), beta = float(kEsBetaPerWidth * W), zs = float(2.0 / W);
+    int bstart[4], bcount[4];
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        const int by = (tby - (nb & 1) + ts.nty) % ts.nty, bz = (tbz - (nb >> 1) + ts.ntz) % ts.ntz;
+        const int64_t bin = int64_t(rot) * nbins + bz * ts.nty + by;
+        bstart[nb] = offsets[bin];
+        bcount[nb] = counts[bin];
+    }
+    auto rel = [&](float v, int org) { return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2; };
+    float part = 0.f;
+#pragma unroll
+    for (int nb = 0; nb < 4; ++nb) {
+        for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
+            const int64_t at = int64_t(bstart[nb]) + p;
+            const float* vp = vbuf + 4 * at;
+            const int oy = rel(vp[1], y0), oz = rel(vp[2], z0);
+            if (oy > -W && oy < kLineRows && oz > -W && oz < kLineRows) {
+                const cplx<float> ck = cbuf[at];
+                part += fmaxf(fabsf(ck.re), fabsf(ck.im));
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+    __syncthreads();
+    float S = 0.f;
+#pragma unroll
+    for (int i = 0; i < kLineBlock / 64; ++i) S += red[i];
+    // x-pruned rows of this tile: row r = iz * 8 + iy at [b][z0 + iz][y0 + iy][0 .. N)
+    cplx<float>* hb = half_buf + int64_t(rot) * NF * NF * N;
+    auto hrow = [&](int r) { return hb + (int64_t(z0 + r / kLineRows) * NF + (y0 + r % kLineRows)) * N; };
+    if (!(S > 0.f)) {  // no sample reaches the tile: its modes are zero
+        for (int e = int(threadIdx.x); e < ROWS * N; e += kLineBlock) hrow(e / N)[e % N] = mk(0.f, 0.f);
+        return;
+    }
+    const int used = ROWS * px;
+    for (int e = int(threadIdx.x); e < used; e += kLineBlock) {
+        lre[e] = 0;
+        lim[e] = 0;
+    }
+    __syncthreads();
+    const float sc = float(TileAcc<float>::kOne) / S;
+#pragma unroll 1
+    for (int nb = 0; nb < 4; ++nb) {
+        for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
+            const int64_t at = int64_t(bstart[nb]) + p;
+            const float* vp = vbuf + 4 * at;
+            const float vx = vp[0], vy = vp[1], vz = vp[2];
+            const int oy = rel(vy, y0), oz = rel(vz, z0);
+            if (!(oy > -W && oy < kLineRows && oz > -W && oz < kLineRows)) continue;
+            const int lx = first_node(vx, half);
+            const int ly = first_node(vy, half), lz = first_node(vz, half);
+            const cplx<float> ck = cbuf[at];
+            float xr[W], xi[W], wy[W], wz[W];
+#pragma unroll
+            for (int q = 0; q < W; ++q) {
+                const float zx = (float(lx + q) - vx) * zs, zy = (float(ly + q) - vy) * zs,
+                            zz = (float(lz + q) - vz) * zs;
+                const float sx = 1.f - zx * zx, sy = 1.f - zy * zy, sz = 1.f - zz * zz;
+                const float wx = sx >= 0.f ? expf(beta * (sqrtf(sx) - 1.f)) : 0.f;
+                wy[q] = sy >= 0.f ? expf(beta * (sqrtf(sy) - 1.f)) : 0.f;
+                wz[q] = sz >= 0.f ? expf(beta * (sqrtf(sz) - 1.f)) : 0.f;
+                xr[q] = ck.re * sc * wx;
+                xi[q] = ck.im * sc * wx;
+            }
+            const int xb = lx & msk;  // taps xb .. xb + W - 1 < nf + 8
+#pragma unroll
+            for (int cq = 0; cq < W; ++cq) {
+                const int iz = oz + cq;
+#pragma unroll
+                for (int bq = 0; bq < W; ++bq) {
+                    const int iy = oy + bq;
+                    if (unsigned(iz) < unsigned(kLineRows) && unsigned(iy) < unsigned(kLineRows)) {
+                        const float wyz = wy[bq] * wz[cq];
+                        int* rr = lre + (iz * kLineRows + iy) * px + xb;
+                        int* ri = lim + (iz * kLineRows + iy) * px + xb;
+#pragma unroll
+                        for (int aq = 0; aq < W; ++aq) {
+                            atomicAdd(rr + aq, __float2int_rn(xr[aq] * wyz));
+                            atomicAdd(ri + aq, __float2int_rn(xi[aq] * wyz));
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // integer rows (with their wrap slots folded) -> complex lines in the same LDS
+    const float inv = S / float(TileAcc<float>::kOne);
+    cplx<float> val[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = int(threadIdx.x) + k * kLineBlock;
+        const int x = e & msk, row = e / NF;
+        int ar = lre[row * px + x], ai = lim[row * px + x];
+        if (x < 8) {
+            ar += lre[row * px + nf + x];
+            ai += lim[row * px + nf + x];
+        }
+        val[k] = mk(float(ar) * inv, float(ai) * inv);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) cb[int(threadIdx.x) + k * kLineBlock] = val[k];
+    __syncthreads();
+    lds_fft_lines<float, NF, -1, false>(cb, 1, NF, ROWS, tw);
+    __syncthreads();
+    for (int e = int(threadIdx.x); e < ROWS * N; e += kLineBlock) {
+        const int r = e / N, j = e % N;
+        hrow(r)[j] = cb[r * NF + fine_mode(j, N)];
+    }
+}
+
+// 2N in {32, 64, 128, 256}: line tiles with the fused x pass
+inline bool fused_x_pass(int nf) { return nf >= 32 && nf <= 256; }
+
+template <int NF>
+void launch_line_fft_nf(const float* vbuf, const cplx<float>* cbuf, const int* counts, const int* offsets, int batch,
+                        int w, TileShape ts, cplx<float>* half_buf, hipStream_t s) {
+    const dim3 grid(unsigned(ts.nty * ts.ntz), unsigned(batch));
+    switch (w) {
+#define SDF_LINE_W(WW)                                                                                          \
+    case WW:                                                                                                    \
+        hipLaunchKernelGGL((nfft_line_fft_kernel<WW, NF>), grid, dim3(kLineBlock), 0, s, vbuf, cbuf, counts,   \
+                           offsets, ts, half_buf);                                                              \
+        break;
+        SDF_LINE_W(2)
+        SDF_LINE_W(3)
+        SDF_LINE_W(4)
+        SDF_LINE_W(5)
+        SDF_LINE_W(6)
+        SDF_LINE_W(7)
+        SDF_LINE_W(8)
+#undef SDF_LINE_W
+        default: break;
+    }
+}
+
+hipError_t launch_line_fft(const float* vbuf, const cplx<float>* cbuf, const int* counts, const int* offsets,
+                           int batch, int nf, int w, TileShape ts, cplx<float>* half_buf, hipStream_t s) {
+    if (w < 2 || w > 8) return hipErrorInvalidValue;
+    switch (nf) {
+        case 32: launch_line_fft_nf<32>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
+        case 64: launch_line_fft_nf<64>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
+        case 128: launch_line_fft_nf<128>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
+        case 256: launch_line_fft_nf<256>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int DIM>
@@ -970,8 +1156,13 @@ hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R,
             hipLaunchKernelGGL((nfft_bin_kernel<T, 3, true>), g, dim3(256), 0, s, pos, cc, m, R, nf, w, ts, counts,
                                offsets, cursor, vbuf, cbuf);
     }
+    bool rows_done = false;
     if constexpr (std::is_same<T, float>::value) {
-        if (lines) {
+        if (lines && fused_x_pass(nf)) {
+            e = launch_line_fft(vbuf, cbuf, counts, offsets, batch, nf, w, ts,
+                                reinterpret_cast<cplx<float>*>(base + L.half), s);
+            rows_done = true;
+        } else if (lines) {
             switch (w) {
                 case 2: launch_line_tile<2>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
                 case 3: launch_line_tile<3>(vbuf, cbuf, counts, offsets, batch, nf, ts, fg, s); break;
@@ -994,7 +1185,7 @@ hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R,
     if (e != hipSuccess) return e;
     // the y pass's output reuses the oversampled grids, free after the x pass
     return launch_pruned<T>(fg, reinterpret_cast<cplx<T>*>(base + L.half), fg, batch, N, planar, inv,
-                            static_cast<const cplx<T>*>(spec), static_cast<cplx<T>*>(out), s);
+                            static_cast<const cplx<T>*>(spec), static_cast<cplx<T>*>(out), rows_done, s);
 }
 
 template hipError_t launch_octree<float>(const void*, const float*, int, bool, double, int, float*, void*, int*,

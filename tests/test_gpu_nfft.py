@@ -178,6 +178,27 @@ def test_nfft_every_kernel_width(ctxs, w):
     assert err <= 1e-9
 
 
+@pytest.mark.parametrize("w", [2, 3, 4, 5, 6, 7, 8])
+def test_nfft_every_kernel_width_fp32_line_tiles(ctxs, w):
+    # FP32 3D grids spread in line tiles with the first FFT pass fused in
+    ctx = ctxs["f32"]
+    rng = np.random.default_rng(200 + w)
+    n = 32
+    rho_f = smooth_field(rng, n, False, damping=60.0).astype(np.complex64)
+    pos = rng.uniform(-9, 9, (1500, 3)).astype(np.float32)
+    coef = (rng.normal(size=1500) + 1j * rng.normal(size=1500)).astype(np.complex64)
+    gf = grid_spec(n, False)
+    spec = ctx.spectrum(rho_f, gf)
+    q = wr.uniform_quaternions(2, 31 + w)
+    vol = to_np(ctx.score_volume_nfft(spec, gf, pos, coef, q, width=w)).astype(np.float64)
+    for r in range(2):
+        alg = onf.score_volume_trig(rho_f.astype(np.complex128), pos.astype(np.float64), coef.astype(np.complex128),
+                                    q[r], False, w=w)
+        err = np.abs(vol[r] - alg).max() / np.abs(alg).max()
+        flush_print("fp32 width", w, "rotation", r, "err vs algorithm", err)
+        assert err <= 2e-5
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_nfft_peaks_match_oracle_volumes(ctxs, dtype):
     ctx = ctxs[dtype]
