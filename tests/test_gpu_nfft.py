@@ -199,6 +199,29 @@ def test_nfft_every_kernel_width_fp32_line_tiles(ctxs, w):
         assert err <= 2e-5
 
 
+@pytest.mark.parametrize("dtype,planar,n", [("f32", False, 8), ("f64", False, 8), ("f64", False, 32),
+                                             ("f32", True, 64), ("f64", True, 64), ("f32", True, 16)])
+def test_nfft_grid_sizes_and_tilings(ctxs, dtype, planar, n):
+    # every spreading path: FP32 line tiles without the fused x pass (N = 8),
+    # general tiles split along every axis (FP64 3D N = 32, planar N = 64)
+    ctx = ctxs[dtype]
+    rng = np.random.default_rng(300 + n + planar)
+    rho_f = smooth_field(rng, n, planar, damping=0.3 * n * n / 16)
+    m = 700
+    pos = rng.uniform(-0.6 * n, 0.6 * n, (m, 3))
+    if planar:
+        pos[:, 2] = 0
+    coef = rng.normal(size=m) + 1j * rng.normal(size=m)
+    pos = pos.astype(REAL[dtype]).astype(np.float64)
+    coef = coef.astype(CPLX[dtype]).astype(np.complex128)
+    gf = grid_spec(n, planar)
+    spec = ctx.spectrum(rho_f.astype(CPLX[dtype]), gf)
+    quats = planar_quats(2, n) if planar else wr.uniform_quaternions(2, n)
+    flush_print("sizes", dtype, planar, n)
+    vol = to_np(ctx.score_volume_nfft(spec, gf, pos.astype(REAL[dtype]), coef.astype(CPLX[dtype]), quats, width=6))
+    check_volumes(vol.astype(np.float64), rho_f, pos, coef, quats, planar, dtype, 6)
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_nfft_peaks_match_oracle_volumes(ctxs, dtype):
     ctx = ctxs[dtype]
