@@ -812,26 +812,58 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     const int y0 = tby * kLineRows, z0 = tbz * kLineRows;
     const int px = ts.py;
     const float half = float(0.5 * W), beta = float(kEsBetaPerWidth * W), zs = float(2.0 / W);
-    int bstart[4], bcount[4];
+    // candidates: the samples of the tile's bin and of the bins below it in y
+    // and z, as one flat list; each thread keeps its first KC in registers
+    // from the S pass to the spreading pass (their loads issue together)
+    int bstart[4], bpre[5];
+    bpre[0] = 0;
 #pragma unroll
     for (int nb = 0; nb < 4; ++nb) {
         const int by = (tby - (nb & 1) + ts.nty) % ts.nty, bz = (tbz - (nb >> 1) + ts.ntz) % ts.ntz;
         const int64_t bin = int64_t(rot) * nbins + bz * ts.nty + by;
         bstart[nb] = offsets[bin];
-        bcount[nb] = counts[bin];
+        bpre[nb + 1] = bpre[nb] + counts[bin];
     }
-    auto rel = [&](float v, int org) { return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2; };
+    const int total = bpre[4];
+    // base of candidate i's bin minus the candidates before it
+    const int base0 = bstart[0], base1 = bstart[1] - bpre[1], base2 = bstart[2] - bpre[2],
+              base3 = bstart[3] - bpre[3];
+    const int pre1 = bpre[1], pre2 = bpre[2], pre3 = bpre[3];
+    const int d1 = base1 - base0, d2 = base2 - base1, d3 = base3 - base2;
+    auto slot = [=](int i) __attribute__((always_inline)) {
+        // the bin boundaries are ordered, so the deltas of the passed ones add up
+        const int base = base0 + int(i >= pre1) * d1 + int(i >= pre2) * d2 + int(i >= pre3) * d3;
+        return int64_t(base) + i;
+    };
+    auto rel = [=](float v, int org) __attribute__((always_inline)) { return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2; };
+    auto touches = [=](int oy, int oz) __attribute__((always_inline)) { return oy > -W && oy < kLineRows && oz > -W && oz < kLineRows; };
+    constexpr int KC = 4;
+    float cvx[KC], cvy[KC], cvz[KC];
+    cplx<float> cck[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int i = int(threadIdx.x) + k * kLineBlock;
+        cvx[k] = cvy[k] = cvz[k] = 0.f;
+        cck[k] = mk(0.f, 0.f);
+        if (i < total) {
+            const int64_t at = slot(i);
+            cvx[k] = vbuf[4 * at];
+            cvy[k] = vbuf[4 * at + 1];
+            cvz[k] = vbuf[4 * at + 2];
+            cck[k] = cbuf[at];
+        }
+    }
     float part = 0.f;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
-            const int64_t at = int64_t(bstart[nb]) + p;
-            const float* vp = vbuf + 4 * at;
-            const int oy = rel(vp[1], y0), oz = rel(vp[2], z0);
-            if (oy > -W && oy < kLineRows && oz > -W && oz < kLineRows) {
-                const cplx<float> ck = cbuf[at];
-                part += fmaxf(fabsf(ck.re), fabsf(ck.im));
-            }
+    for (int k = 0; k < KC; ++k) {
+        const int i = int(threadIdx.x) + k * kLineBlock;
+        if (i < total && touches(rel(cvy[k], y0), rel(cvz[k], z0))) part += fmaxf(fabsf(cck[k].re), fabsf(cck[k].im));
+    }
+    for (int i = int(threadIdx.x) + KC * kLineBlock; i < total; i += kLineBlock) {
+        const int64_t at = slot(i);
+        if (touches(rel(vbuf[4 * at + 1], y0), rel(vbuf[4 * at + 2], z0))) {
+            const cplx<float> ck = cbuf[at];
+            part += fmaxf(fabsf(ck.re), fabsf(ck.im));
         }
     }
     for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
@@ -842,7 +874,7 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     for (int i = 0; i < kLineBlock / 64; ++i) S += red[i];
     // x-pruned rows of this tile: row r = iz * 8 + iy at [b][z0 + iz][y0 + iy][0 .. N)
     cplx<float>* hb = half_buf + int64_t(rot) * NF * NF * N;
-    auto hrow = [&](int r) { return hb + (int64_t(z0 + r / kLineRows) * NF + (y0 + r % kLineRows)) * N; };
+    auto hrow = [=](int r) __attribute__((always_inline)) { return hb + (int64_t(z0 + r / kLineRows) * NF + (y0 + r % kLineRows)) * N; };
     if (!(S > 0.f)) {  // no sample reaches the tile: its modes are zero
         for (int e = int(threadIdx.x); e < ROWS * N; e += kLineBlock) hrow(e / N)[e % N] = mk(0.f, 0.f);
         return;
@@ -854,49 +886,58 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     }
     __syncthreads();
     const float sc = float(TileAcc<float>::kOne) / S;
-#pragma unroll 1
-    for (int nb = 0; nb < 4; ++nb) {
-        for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
-            const int64_t at = int64_t(bstart[nb]) + p;
-            const float* vp = vbuf + 4 * at;
-            const float vx = vp[0], vy = vp[1], vz = vp[2];
-            const int oy = rel(vy, y0), oz = rel(vz, z0);
-            if (!(oy > -W && oy < kLineRows && oz > -W && oz < kLineRows)) continue;
-            const int lx = first_node(vx, half);
-            const int ly = first_node(vy, half), lz = first_node(vz, half);
-            const cplx<float> ck = cbuf[at];
-            float xr[W], xi[W], wy[W], wz[W];
+    auto spread = [=](float vx, float vy, float vz, cplx<float> ck) __attribute__((always_inline)) {
+        const int oy = rel(vy, y0), oz = rel(vz, z0);
+        if (!touches(oy, oz)) return;
+        const int lx = first_node(vx, half);
+        const int ly = first_node(vy, half), lz = first_node(vz, half);
+        float xr[W], xi[W], wy[W], wz[W];
 #pragma unroll
-            for (int q = 0; q < W; ++q) {
-                const float zx = (float(lx + q) - vx) * zs, zy = (float(ly + q) - vy) * zs,
-                            zz = (float(lz + q) - vz) * zs;
-                const float sx = 1.f - zx * zx, sy = 1.f - zy * zy, sz = 1.f - zz * zz;
-                const float wx = sx >= 0.f ? expf(beta * (sqrtf(sx) - 1.f)) : 0.f;
-                wy[q] = sy >= 0.f ? expf(beta * (sqrtf(sy) - 1.f)) : 0.f;
-                wz[q] = sz >= 0.f ? expf(beta * (sqrtf(sz) - 1.f)) : 0.f;
-                xr[q] = ck.re * sc * wx;
-                xi[q] = ck.im * sc * wx;
-            }
-            const int xb = lx & msk;  // taps xb .. xb + W - 1 < nf + 8
+        for (int q = 0; q < W; ++q) {
+            const float zx = (float(lx + q) - vx) * zs, zy = (float(ly + q) - vy) * zs, zz = (float(lz + q) - vz) * zs;
+            const float sx = 1.f - zx * zx, sy = 1.f - zy * zy, sz = 1.f - zz * zz;
+            const float wx = sx >= 0.f ? expf(beta * (sqrtf(sx) - 1.f)) : 0.f;
+            wy[q] = sy >= 0.f ? expf(beta * (sqrtf(sy) - 1.f)) : 0.f;
+            wz[q] = sz >= 0.f ? expf(beta * (sqrtf(sz) - 1.f)) : 0.f;
+            xr[q] = ck.re * sc * wx;
+            xi[q] = ck.im * sc * wx;
+        }
+        const int xb = lx & msk;  // taps xb .. xb + W - 1 < nf + 8
 #pragma unroll
-            for (int cq = 0; cq < W; ++cq) {
-                const int iz = oz + cq;
+        for (int cq = 0; cq < W; ++cq) {
+            const int iz = oz + cq;
 #pragma unroll
-                for (int bq = 0; bq < W; ++bq) {
-                    const int iy = oy + bq;
-                    if (unsigned(iz) < unsigned(kLineRows) && unsigned(iy) < unsigned(kLineRows)) {
-                        const float wyz = wy[bq] * wz[cq];
-                        int* rr = lre + (iz * kLineRows + iy) * px + xb;
-                        int* ri = lim + (iz * kLineRows + iy) * px + xb;
+            for (int bq = 0; bq < W; ++bq) {
+                const int iy = oy + bq;
+                if (unsigned(iz) < unsigned(kLineRows) && unsigned(iy) < unsigned(kLineRows)) {
+                    const float wyz = wy[bq] * wz[cq];
+                    int* rr = lre + (iz * kLineRows + iy) * px + xb;
+                    int* ri = lim + (iz * kLineRows + iy) * px + xb;
 #pragma unroll
-                        for (int aq = 0; aq < W; ++aq) {
-                            atomicAdd(rr + aq, __float2int_rn(xr[aq] * wyz));
-                            atomicAdd(ri + aq, __float2int_rn(xi[aq] * wyz));
-                        }
+                    for (int aq = 0; aq < W; ++aq) {
+                        atomicAdd(rr + aq, __float2int_rn(xr[aq] * wyz));
+                        atomicAdd(ri + aq, __float2int_rn(xi[aq] * wyz));
                     }
                 }
             }
         }
+    };
+    // one copy of the spreading code: take element 0, then shift the register
+    // copies down (constant indices keep them out of scratch)
+#pragma unroll 1
+    for (int k = 0; k < KC; ++k) {
+        if (int(threadIdx.x) + k * kLineBlock < total) spread(cvx[0], cvy[0], cvz[0], cck[0]);
+#pragma unroll
+        for (int j = 0; j + 1 < KC; ++j) {
+            cvx[j] = cvx[j + 1];
+            cvy[j] = cvy[j + 1];
+            cvz[j] = cvz[j + 1];
+            cck[j] = cck[j + 1];
+        }
+    }
+    for (int i = int(threadIdx.x) + KC * kLineBlock; i < total; i += kLineBlock) {
+        const int64_t at = slot(i);
+        spread(vbuf[4 * at], vbuf[4 * at + 1], vbuf[4 * at + 2], cbuf[at]);
     }
     __syncthreads();
     // integer rows (with their wrap slots folded) -> complex lines in the same LDS
