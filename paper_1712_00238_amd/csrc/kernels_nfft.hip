@@ -561,38 +561,45 @@ __global__ __launch_bounds__(256) void nfft_rows_pruned_kernel(const cplx<T>* __
 
 // columns per block: a power of two that the block's threads cover and that
 // divides N
-template <int NF>
+template <int NF, int BS = 256>
 constexpr int pruned_width() {
     int w = 1;
-    while (w * 2 <= 256 / FFTShape<NF>::TPL && w * 2 <= NF / 2) w *= 2;
+    while (w * 2 <= BS / FFTShape<NF>::TPL && w * 2 <= NF / 2) w *= 2;
     return w;
+}
+
+// threads per column block: 512 for 2N = 256, so a block reads 16 columns
+// (128-byte row segments) instead of 8
+template <int NF>
+constexpr int cols_block() {
+    return NF >= 256 ? 512 : 256;
 }
 
 // A block transforms W consecutive x columns along a strided axis (element
 // stride es_in) and stores the N kept outputs (stride es_out).  FINAL: the
 // axis is the last one (y of a planar grid, z in 3D); outputs are the modes
 // (jx, jy[, jz]) times inv[jx] inv[jy] [inv[jz]] spec.
-template <typename T, int NF, bool FINAL, bool PLANAR>
-__global__ __launch_bounds__(256) void nfft_cols_pruned_kernel(const cplx<T>* __restrict__ in,
+template <typename T, int NF, bool FINAL, bool PLANAR, int BS = cols_block<NF>()>
+__global__ __launch_bounds__(BS) void nfft_cols_pruned_kernel(const cplx<T>* __restrict__ in,
                                                                cplx<T>* __restrict__ out, int64_t es_in,
                                                                int64_t os_in, int64_t bs_in, int64_t es_out,
                                                                int64_t os_out, int64_t bs_out,
                                                                const T* __restrict__ inv,
                                                                const cplx<T>* __restrict__ spec) {
-    constexpr int W = pruned_width<NF>(), N = NF / 2;
+    constexpr int W = pruned_width<NF, BS>(), N = NF / 2;
     __shared__ cplx<T> buf[NF * W];
     __shared__ cplx<T> tw[NF];
     fill_twiddles<T, NF>(tw);
     const int x0 = int(blockIdx.x) * W, o = int(blockIdx.y), b = int(blockIdx.z);
     const cplx<T>* src = in + int64_t(b) * bs_in + int64_t(o) * os_in + x0;
-    for (int i = int(threadIdx.x); i < NF * W; i += 256) {
+    for (int i = int(threadIdx.x); i < NF * W; i += BS) {
         const int e = i / W, xl = i - e * W;
         buf[i] = src[int64_t(e) * es_in + xl];
     }
     __syncthreads();
     lds_fft_lines<T, NF, -1, true>(buf, W, 1, W, tw);
     cplx<T>* dst = out + int64_t(b) * bs_out + int64_t(o) * os_out + x0;
-    for (int i = int(threadIdx.x); i < N * W; i += 256) {
+    for (int i = int(threadIdx.x); i < N * W; i += BS) {
         const int j = i / W, xl = i - j * W;
         cplx<T> v = buf[fine_mode(j, N) * W + xl];
         if (FINAL) {
@@ -608,24 +615,25 @@ __global__ __launch_bounds__(256) void nfft_cols_pruned_kernel(const cplx<T>* __
 template <typename T, int NF>
 void pruned_transform(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_buf, int batch, bool planar,
                       const T* inv, const cplx<T>* spec, cplx<T>* out, bool rows_done, hipStream_t s) {
-    constexpr int N = NF / 2, TPL = FFTShape<NF>::TPL, CONC = 256 / TPL, W = pruned_width<NF>();
+    constexpr int N = NF / 2, TPL = FFTShape<NF>::TPL, CONC = 256 / TPL, BS = cols_block<NF>(),
+                  W = pruned_width<NF, BS>();
     const int64_t nrows = int64_t(batch) * NF * (planar ? 1 : NF);
     if (!rows_done)
         hipLaunchKernelGGL((nfft_rows_pruned_kernel<T, NF>), dim3(unsigned((nrows + CONC - 1) / CONC)), dim3(256),
                            0, s, fine, half_buf, nrows);
     if (planar) {
         // y, last: half_buf [b][y < NF][x < N] -> out [b][jy][jx]
-        hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, true>), dim3(N / W, 1, unsigned(batch)), dim3(256),
+        hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, true>), dim3(N / W, 1, unsigned(batch)), dim3(BS),
                            0, s, half_buf, out, int64_t(N), int64_t(0), int64_t(NF) * N, int64_t(N), int64_t(0),
                            int64_t(N) * N, inv, spec);
         return;
     }
     // y: half_buf [b][z < NF][y < NF][x < N] -> quarter_buf [b][z < NF][jy][x < N]
-    hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, false, false>), dim3(N / W, NF, unsigned(batch)), dim3(256),
+    hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, false, false>), dim3(N / W, NF, unsigned(batch)), dim3(BS),
                        0, s, half_buf, quarter_buf, int64_t(N), int64_t(NF) * N, int64_t(NF) * NF * N, int64_t(N),
                        int64_t(N) * N, int64_t(NF) * N * N, inv, spec);
     // z, last: quarter_buf [b][z < NF][jy][jx] -> out [b][jz][jy][jx]
-    hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, false>), dim3(N / W, N, unsigned(batch)), dim3(256), 0,
+    hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, false>), dim3(N / W, N, unsigned(batch)), dim3(BS), 0,
                        s, quarter_buf, out, int64_t(N) * N, int64_t(N), int64_t(NF) * N * N, int64_t(N) * N,
                        int64_t(N), int64_t(N) * N * N, inv, spec);
 }
