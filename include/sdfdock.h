@@ -391,9 +391,9 @@ int octree_samples(sdf_ctx ctx, const void *rho_moving, const void *w_moving, co
  *   spec_fixed: output of sdf_spectrum; g_fixed N^3 or N^2 x 1 with N in
  *   {8, 16, 32, 64, 128}; width in [2, 8]; 0 <= m <= 2^30 (m = 0 scores 0).
  *   quats (host): n_rot x 4 FP64.
- * Device workspace: up to 512 MiB of oversampled grids per batch of
- * rotations, one N^d grid and the binned samples (6 reals each) per rotation
- * of the batch.
+ * Device workspace: about 768 MiB per batch of rotations at N = 128 (the
+ * oversampled-grid buffers, one N^d grid and the binned samples, 6 reals
+ * each, per rotation of the batch), at least one rotation's worth.
  * Errors: SDF_EINVAL, SDF_EUNSUPPORTED (N), SDF_ENOMEM, SDF_EHIP. */
 int score_rotations_nfft(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
                          const void *pos, const void *c, int64_t m, int width,

@@ -765,7 +765,7 @@ int direct_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const double*
 
 // Nonequispaced route: batches of rotations through the type-1 transform of
 // the given samples, then the plain path's inverse FFT and peak (or real part).
-constexpr size_t kNfftFineBudget = size_t(512) << 20;  // oversampled grids per batch
+constexpr size_t kNfftBudget = size_t(768) << 20;  // per-batch workspace of the route
 
 template <typename T>
 int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos, const void* c, int64_t m, int w,
@@ -774,11 +774,12 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
     ctx->fused_cache_valid = false;
     const int N = gf->n[0];
     const bool planar = gf->n[2] == 1;
-    const int nf = 2 * N;
     const int64_t G = gsize(gf);
-    const int64_t Gf = planar ? int64_t(nf) * nf : int64_t(nf) * nf * nf;
-    const size_t fine_bytes = 2 * sizeof(T) * size_t(Gf);
-    int64_t B = std::max<int64_t>(1, std::min<int64_t>(n_rot, int64_t(kNfftFineBudget / fine_bytes)));
+    const size_t fine_bytes = sdf::nfft_grid_bytes(N, planar, sizeof(T));
+    // rotations per batch: the per-rotation grids, x-pruned buffer and binned
+    // samples within the budget
+    const size_t per_rot = fine_bytes + 2 * sizeof(T) * size_t(G) + sdf::nfft_workspace_bytes(m, 1, N, planar, sizeof(T));
+    int64_t B = std::max<int64_t>(1, std::min<int64_t>(n_rot, int64_t(kNfftBudget / per_rot)));
     if (m > 0) B = std::max<int64_t>(1, std::min<int64_t>(B, (int64_t(1) << 30) / m));  // binned samples < 2^31
     const int nparts = sdf::peak_parts<T>(N, planar);
     Carve cv{nullptr};

@@ -1163,6 +1163,14 @@ size_t nfft_workspace_bytes(int64_t m, int batch, int N, bool planar, size_t ele
     return nfft_ws_layout(m, batch, N, planar, elem).total;
 }
 
+size_t nfft_grid_bytes(int N, bool planar, size_t elem) {
+    const int nf = 2 * N;
+    const size_t full = 2 * elem * size_t(nf) * nf * (planar ? 1 : nf);
+    // with the x pass fused into the line tiles only the y pass's output,
+    // a quarter of the grid, lives there
+    return use_lines(planar, elem) && fused_x_pass(nf) ? full / 4 : full;
+}
+
 template <typename T>
 hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
                              int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s) {

@@ -157,6 +157,9 @@ hipError_t launch_es_deconv(int N, int w, T* inv, hipStream_t s);
 // transform, and write out[b] = deconvolved N^d modes times spec (ready for
 // the inverse FFT of the correlation); ws holds nfft_workspace_bytes
 size_t nfft_workspace_bytes(int64_t m, int batch, int N, bool planar, size_t elem);
+// per rotation: bytes of the `fine` grid launch_nfft_modes needs (the whole
+// (2N)^d grid, or a quarter of it where the x pass is fused into the tiles)
+size_t nfft_grid_bytes(int N, bool planar, size_t elem);
 template <typename T>
 hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
                              int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s);
