@@ -337,9 +337,12 @@ def main():
                           "share": 0.0}
         ctx.set_option("profile", 0)
         tot = sum(v["avg_us"] * v["launches"] for v in kernels.values())
-        # one call launches batches of `batch` rotations and a smaller tail batch
-        # (576 = 4 x 128 + 64): bytes and durations are both averaged over that mix
-        sizes = [min(args.batch, n_rot - i) for i in range(0, n_rot, args.batch)]
+        # one call spreads its rotations evenly over ceil(n_rot / batch) launches
+        # (even sizes, the last one takes the rest): bytes and durations are both
+        # averaged over those launches
+        n_launch = -(-n_rot // args.batch)
+        per = min(args.batch, (-(-n_rot // n_launch) + 1) // 2 * 2) if n_launch > 1 else args.batch
+        sizes = [min(per, n_rot - i) for i in range(0, n_rot, per)]
         rot_per_launch = n_rot / len(sizes)
         reach = reach_fraction(pair.quats, n_m, N)
         report["slab_reach"] = round(reach, 4)
@@ -618,7 +621,8 @@ def main():
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "mechanical_3d: box-with-hole (fixed, 15.7k samples) vs plate-with-peg (moving, "
                                    "4.1k samples), 128^3 grid h=1, 64^3 body box, 576 Hopf rotations",
-                       "rotations": n_rot, "batch": args.batch, "graph": bool(args.graph),
+                       "rotations": n_rot, "batch": args.batch, "rotations_per_launch": sizes,
+                       "graph": bool(args.graph),
                        "pencil_group": args.pencil_group, "radix": (tuned or {}).get("radix", 0),
                        "autotuned": bool(args.autotune)},
             "roofline": roofline,

@@ -237,7 +237,7 @@ typedef struct {
 int score_pairs(sdf_ctx ctx, const sdf_pair_job *jobs, int64_t n_jobs, sdf_stream stream);
 
 /* Autotuner for the fused FP32 search of one grid-size class (N, planar,
- * N_M): times every candidate plan (rotations per batch in {32, 64, 128},
+ * N_M): times every candidate plan (rotations per batch in {32, 64, 128, 256},
  * rotations per pencil block in {2, 4}, three FFT radix schedules for the
  * sizes that use them; N = 64 and 128 use fixed two-pass transforms) on
  * synthetic inputs, rejects candidates whose peaks differ from the plain

@@ -340,6 +340,12 @@ sdf::FusedPlan plan_for(sdf_ctx ctx, int N, bool planar, int64_t rots_in_class) 
     }
     if (fp.batch > rots_in_class) fp.batch = int((rots_in_class + 1) / 2 * 2);
     if (fp.batch < 2) fp.batch = 2;
+    // the same number of launches, of equal size (no short tail launch)
+    const int64_t launches = (rots_in_class + fp.batch - 1) / fp.batch;
+    if (launches > 1) {
+        const int64_t even = ((rots_in_class + launches - 1) / launches + 1) / 2 * 2;
+        if (even < fp.batch) fp.batch = int(even);
+    }
     return fp;
 }
 
@@ -554,7 +560,7 @@ int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std:
     const int64_t G = int64_t(N) * N * nz;
     const int64_t K = int64_t(n_m) * n_m * (planar ? 1 : n_m);
     const int n_probe = 8;  // rotations compared with the plain path
-    const int n_time = 128; // rotations timed per candidate
+    const int n_time = 256; // rotations timed per candidate (one launch at the largest batch)
     // synthetic pair in its own allocations (freed at the end)
     void *spec = nullptr, *rho = nullptr, *w = nullptr, *sc = nullptr, *tt = nullptr;
     void *sc_ref = nullptr, *tt_ref = nullptr;
@@ -636,7 +642,7 @@ int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std:
     std::string rep = "{\"N\": " + std::to_string(N) + ", \"n_m\": " + std::to_string(n_m) +
                       ", \"planar\": " + (planar ? "true" : "false") + ", \"candidates\": [";
     bool first = true;
-    for (int batch : {32, 64, 128}) {
+    for (int batch : {32, 64, 128, 256}) {
         for (int group : {2, 4}) {
             // N = 64 and 128 use fixed two-pass transforms: the schedule does not apply
             const int n_radix = (N == 64 || N == 128) ? 1 : 3;

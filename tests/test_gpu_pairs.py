@@ -111,7 +111,7 @@ def test_autotune_picks_a_parity_clean_plan(ctx32):
     gf, gm, rho_f, rho_m, w = rand_case(32, 14, False, 9)
     flush_print("autotune 32^3 / 14^3")
     rep = ctx32.autotune(gf, gm)
-    assert rep["N"] == 32 and len(rep["candidates"]) == 18
+    assert rep["N"] == 32 and len(rep["candidates"]) == 24  # 4 batches x 2 groups x 3 schedules
     chosen = rep["chosen"]
     assert any(c["parity"] and c["batch"] == chosen["batch"] and c["group"] == chosen["group"] and
                c["radix"] == chosen["radix"] for c in rep["candidates"])
