@@ -262,17 +262,23 @@ constexpr int kLineBlock = 1024;
 
 inline int line_pitch(int nf) { return nf + 11; }  // nf + 8 wrap slots, odd against bank aliasing of rows
 
+// 2N in {32, 64, 128, 256}: line tiles with the fused x pass, 8 (y) x 4 (z)
+// rows so that two blocks share a CU
+inline bool fused_x_pass(int nf) { return nf >= 32 && nf <= 256; }
+constexpr int kFusedRowsZ = 4;
+constexpr int kFusedBlock = 512;
+
 TileShape tile_shape(int nf, bool planar, bool line) {
     TileShape t{};
     if (line) {
         t.tx = nf;
         t.ty = kLineRows;
-        t.tz = kLineRows;
+        t.tz = fused_x_pass(nf) ? kFusedRowsZ : kLineRows;
         t.ntx = 1;
-        t.nty = nf / kLineRows;
-        t.ntz = nf / kLineRows;
+        t.nty = nf / t.ty;
+        t.ntz = nf / t.tz;
         t.py = line_pitch(nf);
-        t.pz = kLineRows * t.py;
+        t.pz = t.ty * t.py;
         return t;
     }
     if (planar) {
@@ -793,64 +799,78 @@ void launch_line_tile(const float* vbuf, const cplx<float>* cbuf, const int* cou
 }
 
 // Line tile with the x pass of the pruned transform fused in (FP32, 3D,
-// 2N >= 32): after the fixed-point accumulation the tile's 64 x lines are
-// converted to complex in the same LDS, transformed there (2N points), and
-// only the N kept modes of each line are stored, into the x-pruned buffer
-// [b][z][y][N] that the y pass reads.  The oversampled grid itself is never
-// written to memory.
+// 2N >= 32): 8 (y) x 4 (z) rows of whole x lines, 512 threads and 68 KiB of
+// LDS, so two blocks share a CU and overlap their phases.  A window of w
+// nodes reaches 1 + ceil((w - 1) / 4) z tiles, so the tile gathers the bins
+// of its own (y, z) and of the next one below in y and up to two below in z.
+// After the fixed-point accumulation the 32 x lines are converted to complex
+// in the same LDS, transformed there (2N points), and only the N kept modes
+// of each line are stored, into the x-pruned buffer [b][z][y][N] that the y
+// pass reads.  The oversampled grid itself is never written to memory.
+constexpr int kFusedRows = kLineRows * kFusedRowsZ;
+constexpr int kFusedLds = kFusedRows * (256 + 11);  // ints per plane at nf = 256
+
 template <int W, int NF>
-__global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* __restrict__ vbuf,
-                                                                   const cplx<float>* __restrict__ cbuf,
-                                                                   const int* __restrict__ counts,
-                                                                   const int* __restrict__ offsets, TileShape ts,
-                                                                   cplx<float>* __restrict__ half_buf) {
-    constexpr int nf = NF, N = NF / 2, msk = NF - 1, ROWS = kLineRows * kLineRows;
-    constexpr int PER = ROWS * NF / kLineBlock;  // converted values per thread
-    static_assert(ROWS * NF * sizeof(cplx<float>) <= 2 * kLineLds * sizeof(int), "complex rows exceed the LDS");
-    __shared__ __align__(16) int acc[2 * kLineLds];
+__global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float* __restrict__ vbuf,
+                                                                    const cplx<float>* __restrict__ cbuf,
+                                                                    const int* __restrict__ counts,
+                                                                    const int* __restrict__ offsets, TileShape ts,
+                                                                    cplx<float>* __restrict__ half_buf) {
+    constexpr int nf = NF, N = NF / 2, msk = NF - 1, RY = kLineRows, RZ = kFusedRowsZ, ROWS = kFusedRows;
+    constexpr int BS = kFusedBlock;
+    constexpr int PER = ROWS * NF / BS;  // converted values per thread
+    constexpr int NBZ = 1 + (W - 1 + RZ - 1) / RZ, NB = 2 * NBZ;
+    static_assert(ROWS * NF * sizeof(cplx<float>) <= 2 * kFusedLds * sizeof(int), "complex rows exceed the LDS");
+    __shared__ __align__(16) int acc[2 * kFusedLds];
     __shared__ cplx<float> tw[NF];
-    __shared__ float red[kLineBlock / 64];
+    __shared__ float red[BS / 64];
     int* lre = acc;
-    int* lim = acc + kLineLds;
+    int* lim = acc + kFusedLds;
     cplx<float>* cb = reinterpret_cast<cplx<float>*>(acc);
     fill_twiddles<float, NF>(tw);
     const int nbins = ts.nty * ts.ntz;
     const int tile = int(blockIdx.x), rot = int(blockIdx.y);
     const int tby = tile % ts.nty, tbz = tile / ts.nty;
-    const int y0 = tby * kLineRows, z0 = tbz * kLineRows;
+    const int y0 = tby * RY, z0 = tbz * RZ;
     const int px = ts.py;
     const float half = float(0.5 * W), beta = float(kEsBetaPerWidth * W), zs = float(2.0 / W);
-    // candidates: the samples of the tile's bin and of the bins below it in y
-    // and z, as one flat list; each thread keeps its first KC in registers
-    // from the S pass to the spreading pass (their loads issue together)
-    int bstart[4], bpre[5];
+    // candidates: the bins (tby - dy, tbz - dz), dy < 2, dz < NBZ, as one flat
+    // list; each thread keeps its first KC in registers from the S pass to the
+    // spreading pass (their loads issue together)
+    int bstart[NB], bpre[NB + 1];
     bpre[0] = 0;
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
         const int by = (tby - (nb & 1) + ts.nty) % ts.nty, bz = (tbz - (nb >> 1) + ts.ntz) % ts.ntz;
         const int64_t bin = int64_t(rot) * nbins + bz * ts.nty + by;
         bstart[nb] = offsets[bin];
         bpre[nb + 1] = bpre[nb] + counts[bin];
     }
-    const int total = bpre[4];
-    // base of candidate i's bin minus the candidates before it
-    const int base0 = bstart[0], base1 = bstart[1] - bpre[1], base2 = bstart[2] - bpre[2],
-              base3 = bstart[3] - bpre[3];
-    const int pre1 = bpre[1], pre2 = bpre[2], pre3 = bpre[3];
-    const int d1 = base1 - base0, d2 = base2 - base1, d3 = base3 - base2;
+    const int total = bpre[NB];
+    // base of candidate i's bin minus the candidates before it: the bin
+    // boundaries are ordered, so the deltas of the passed ones add up
+    int delta[NB];
+    delta[0] = bstart[0];
+#pragma unroll
+    for (int nb = 1; nb < NB; ++nb) delta[nb] = (bstart[nb] - bpre[nb]) - (bstart[nb - 1] - bpre[nb - 1]);
     auto slot = [=](int i) __attribute__((always_inline)) {
-        // the bin boundaries are ordered, so the deltas of the passed ones add up
-        const int base = base0 + int(i >= pre1) * d1 + int(i >= pre2) * d2 + int(i >= pre3) * d3;
+        int base = delta[0];
+#pragma unroll
+        for (int nb = 1; nb < NB; ++nb) base += int(i >= bpre[nb]) * delta[nb];
         return int64_t(base) + i;
     };
-    auto rel = [=](float v, int org) __attribute__((always_inline)) { return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2; };
-    auto touches = [=](int oy, int oz) __attribute__((always_inline)) { return oy > -W && oy < kLineRows && oz > -W && oz < kLineRows; };
+    auto rel = [=](float v, int org) __attribute__((always_inline)) {
+        return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2;
+    };
+    auto touches = [=](int oy, int oz) __attribute__((always_inline)) {
+        return oy > -W && oy < RY && oz > -W && oz < RZ;
+    };
     constexpr int KC = 4;
     float cvx[KC], cvy[KC], cvz[KC];
     cplx<float> cck[KC];
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const int i = int(threadIdx.x) + k * kLineBlock;
+        const int i = int(threadIdx.x) + k * BS;
         cvx[k] = cvy[k] = cvz[k] = 0.f;
         cck[k] = mk(0.f, 0.f);
         if (i < total) {
@@ -864,10 +884,10 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     float part = 0.f;
 #pragma unroll
     for (int k = 0; k < KC; ++k) {
-        const int i = int(threadIdx.x) + k * kLineBlock;
+        const int i = int(threadIdx.x) + k * BS;
         if (i < total && touches(rel(cvy[k], y0), rel(cvz[k], z0))) part += fmaxf(fabsf(cck[k].re), fabsf(cck[k].im));
     }
-    for (int i = int(threadIdx.x) + KC * kLineBlock; i < total; i += kLineBlock) {
+    for (int i = int(threadIdx.x) + KC * BS; i < total; i += BS) {
         const int64_t at = slot(i);
         if (touches(rel(vbuf[4 * at + 1], y0), rel(vbuf[4 * at + 2], z0))) {
             const cplx<float> ck = cbuf[at];
@@ -879,16 +899,18 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     __syncthreads();
     float S = 0.f;
 #pragma unroll
-    for (int i = 0; i < kLineBlock / 64; ++i) S += red[i];
+    for (int i = 0; i < BS / 64; ++i) S += red[i];
     // x-pruned rows of this tile: row r = iz * 8 + iy at [b][z0 + iz][y0 + iy][0 .. N)
     cplx<float>* hb = half_buf + int64_t(rot) * NF * NF * N;
-    auto hrow = [=](int r) __attribute__((always_inline)) { return hb + (int64_t(z0 + r / kLineRows) * NF + (y0 + r % kLineRows)) * N; };
+    auto hrow = [=](int r) __attribute__((always_inline)) {
+        return hb + (int64_t(z0 + r / RY) * NF + (y0 + r % RY)) * N;
+    };
     if (!(S > 0.f)) {  // no sample reaches the tile: its modes are zero
-        for (int e = int(threadIdx.x); e < ROWS * N; e += kLineBlock) hrow(e / N)[e % N] = mk(0.f, 0.f);
+        for (int e = int(threadIdx.x); e < ROWS * N; e += BS) hrow(e / N)[e % N] = mk(0.f, 0.f);
         return;
     }
     const int used = ROWS * px;
-    for (int e = int(threadIdx.x); e < used; e += kLineBlock) {
+    for (int e = int(threadIdx.x); e < used; e += BS) {
         lre[e] = 0;
         lim[e] = 0;
     }
@@ -917,10 +939,10 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
 #pragma unroll
             for (int bq = 0; bq < W; ++bq) {
                 const int iy = oy + bq;
-                if (unsigned(iz) < unsigned(kLineRows) && unsigned(iy) < unsigned(kLineRows)) {
+                if (unsigned(iz) < unsigned(RZ) && unsigned(iy) < unsigned(RY)) {
                     const float wyz = wy[bq] * wz[cq];
-                    int* rr = lre + (iz * kLineRows + iy) * px + xb;
-                    int* ri = lim + (iz * kLineRows + iy) * px + xb;
+                    int* rr = lre + (iz * RY + iy) * px + xb;
+                    int* ri = lim + (iz * RY + iy) * px + xb;
 #pragma unroll
                     for (int aq = 0; aq < W; ++aq) {
                         atomicAdd(rr + aq, __float2int_rn(xr[aq] * wyz));
@@ -934,7 +956,7 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     // copies down (constant indices keep them out of scratch)
 #pragma unroll 1
     for (int k = 0; k < KC; ++k) {
-        if (int(threadIdx.x) + k * kLineBlock < total) spread(cvx[0], cvy[0], cvz[0], cck[0]);
+        if (int(threadIdx.x) + k * BS < total) spread(cvx[0], cvy[0], cvz[0], cck[0]);
 #pragma unroll
         for (int j = 0; j + 1 < KC; ++j) {
             cvx[j] = cvx[j + 1];
@@ -943,7 +965,7 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
             cck[j] = cck[j + 1];
         }
     }
-    for (int i = int(threadIdx.x) + KC * kLineBlock; i < total; i += kLineBlock) {
+    for (int i = int(threadIdx.x) + KC * BS; i < total; i += BS) {
         const int64_t at = slot(i);
         spread(vbuf[4 * at], vbuf[4 * at + 1], vbuf[4 * at + 2], cbuf[at]);
     }
@@ -953,7 +975,7 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     cplx<float> val[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = int(threadIdx.x) + k * kLineBlock;
+        const int e = int(threadIdx.x) + k * BS;
         const int x = e & msk, row = e / NF;
         int ar = lre[row * px + x], ai = lim[row * px + x];
         if (x < 8) {
@@ -964,18 +986,15 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_fft_kernel(const float* 
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < PER; ++k) cb[int(threadIdx.x) + k * kLineBlock] = val[k];
+    for (int k = 0; k < PER; ++k) cb[int(threadIdx.x) + k * BS] = val[k];
     __syncthreads();
     lds_fft_lines<float, NF, -1, false>(cb, 1, NF, ROWS, tw);
     __syncthreads();
-    for (int e = int(threadIdx.x); e < ROWS * N; e += kLineBlock) {
+    for (int e = int(threadIdx.x); e < ROWS * N; e += BS) {
         const int r = e / N, j = e % N;
         hrow(r)[j] = cb[r * NF + fine_mode(j, N)];
     }
 }
-
-// 2N in {32, 64, 128, 256}: line tiles with the fused x pass
-inline bool fused_x_pass(int nf) { return nf >= 32 && nf <= 256; }
 
 template <int NF>
 void launch_line_fft_nf(const float* vbuf, const cplx<float>* cbuf, const int* counts, const int* offsets, int batch,
@@ -984,7 +1003,7 @@ void launch_line_fft_nf(const float* vbuf, const cplx<float>* cbuf, const int* c
     switch (w) {
 #define SDF_LINE_W(WW)                                                                                          \
     case WW:                                                                                                    \
-        hipLaunchKernelGGL((nfft_line_fft_kernel<WW, NF>), grid, dim3(kLineBlock), 0, s, vbuf, cbuf, counts,   \
+        hipLaunchKernelGGL((nfft_line_fft_kernel<WW, NF>), grid, dim3(kFusedBlock), 0, s, vbuf, cbuf, counts,  \
                            offsets, ts, half_buf);                                                              \
         break;
         SDF_LINE_W(2)
