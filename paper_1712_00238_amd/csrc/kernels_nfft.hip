@@ -239,14 +239,15 @@ __global__ __launch_bounds__(256) void es_deconv_kernel(int N, int w, T* __restr
 }
 
 // ------------------------------------------------------------------ tiled spreading
-// The oversampled grid is cut into tiles of at most 4096 nodes (3D 32 x 16 x 8,
-// planar 64 x 64, clipped to the grid).  Per rotation each sample is binned by
-// the tile that holds its first kernel node l0 = ceil(v - w/2), v being the
-// reflected rotated position on the 2x grid wrapped to [0, 2N).  As w is at
-// most every tile side, the sample's w nodes per axis lie in that tile or the
-// next one, so a tile gathers the samples of its own bin and of the bins just
-// below it along each axis, accumulates its nodes in LDS and stores each node
-// once (no zero pass, no global atomics).
+// The oversampled grid is cut into tiles: general tiles of at most 4096 nodes
+// (3D 32 x 16 x 8, planar 64 x 64, clipped to the grid; FP64 and planar) or,
+// for FP32 3D, line tiles of whole x lines (below).  Per rotation each sample
+// is binned by the tile that holds its first kernel node l0 = ceil(v - w/2),
+// v being the reflected rotated position on the 2x grid wrapped to [0, 2N).
+// A sample's w nodes per axis then lie in that tile or the ones just above,
+// so a tile gathers the samples of its own bin and of the bins just below it
+// (one per axis where w is at most the tile side), accumulates its nodes in
+// LDS and stores each node once (no zero pass, no global atomics).
 struct TileShape {
     int tx, ty, tz;     // tile sides in nodes
     int ntx, nty, ntz;  // tiles per axis
@@ -254,9 +255,9 @@ struct TileShape {
 };
 constexpr int kTileLds = 4352;  // >= (tz - 1) pz + (ty - 1) py + tx for every shape below
 
-// Line tiles (FP32 3D): whole periodic x lines of 8 x 8 (y, z) rows, so no x
-// tap needs a test; one block of 1024 threads per CU holds the 128 KiB of
-// integer rows.
+// Line tiles (FP32 3D): whole periodic x lines, so no x tap needs a test.
+// Without the fused x pass (2N = 16) they hold 8 x 8 (y, z) rows in one
+// 1024-thread block.
 constexpr int kLineRows = 8;
 constexpr int kLineBlock = 1024;
 
@@ -663,7 +664,8 @@ hipError_t launch_pruned(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarte
     return hipGetLastError();
 }
 
-// Line tile (FP32, 3D): one block per (8 x 8 rows of whole x lines, rotation).
+// Line tile without the fused transform (FP32, 3D, 2N = 16): one block per
+// (8 x 8 rows of whole x lines, rotation).
 // Samples of the tile's bin and of the bins below it in y and z; per
 // sample, each of its W^2 (y, z) rows that lies in the tile is one branch
 // with W unconditional integer adds at constant offsets from the row base
