@@ -11,7 +11,10 @@ in FP64, fused spread + 3D FFT + spectral product + inverse FFT + peak,
 27-neighbourhood, FP64 sub-voxel refinement), inputs resident in HBM.  The
 one-time SDF construction and spectrum, the plain FP64 path, pose-gradient
 evaluations and per-kernel roofline figures are measured around it and
-reported in the same JSON line.
+reported in the same JSON line, as are the reference search without the
+spreading window (the top rotations rescored), the same rotations through
+octree-adaptive samples and the nonequispaced transform, shape gradients,
+the protein-like pair, gradient refinement and a queue of uneven pairs.
 """
 
 from __future__ import annotations
