@@ -826,6 +826,12 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
     __shared__ __align__(16) int acc[2 * kFusedLds];
     __shared__ cplx<float> tw[NF];
     __shared__ float red[BS / 64];
+    // counting sort of the touching candidates by (z, y) row offset: oy in
+    // (-W, 8), oz in (-W, 4), W <= 8
+    constexpr int KEYS = 15 * 11;
+    __shared__ int s_hist[KEYS];
+    __shared__ int s_idx[4 * BS];
+    __shared__ int s_nsorted;
     int* lre = acc;
     int* lim = acc + kFusedLds;
     cplx<float>* cb = reinterpret_cast<cplx<float>*>(acc);
@@ -916,7 +922,60 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
         lre[e] = 0;
         lim[e] = 0;
     }
+    for (int e = int(threadIdx.x); e < KEYS; e += BS) s_hist[e] = 0;
     __syncthreads();
+    // Sort the register-held candidates that touch the tile by (oz, oy), so a
+    // wave's lanes mostly share which of the window's rows lie in the tile and
+    // the row branches run with full waves (the integer sums do not depend on
+    // the order).
+    int key[KC], rank[KC];
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        key[k] = -1;
+        rank[k] = 0;
+        if (int(threadIdx.x) + k * BS < total) {
+            const int oy = rel(cvy[k], y0), oz = rel(cvz[k], z0);
+            if (touches(oy, oz)) {
+                key[k] = (oz + 7) * 15 + (oy + 7);
+                rank[k] = atomicAdd(&s_hist[key[k]], 1);
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {  // exclusive scan of the 165 bucket sizes, 3 per lane
+        const int ln = int(threadIdx.x);
+        const int v0 = 3 * ln < KEYS ? s_hist[3 * ln] : 0, v1 = 3 * ln + 1 < KEYS ? s_hist[3 * ln + 1] : 0,
+                  v2 = 3 * ln + 2 < KEYS ? s_hist[3 * ln + 2] : 0;
+        const int sum = v0 + v1 + v2;
+        int incl = sum;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int t = __shfl_up(incl, off);
+            if (ln >= off) incl += t;
+        }
+        const int excl = incl - sum;
+        if (3 * ln < KEYS) s_hist[3 * ln] = excl;
+        if (3 * ln + 1 < KEYS) s_hist[3 * ln + 1] = excl + v0;
+        if (3 * ln + 2 < KEYS) s_hist[3 * ln + 2] = excl + v0 + v1;
+        if (ln == 63) s_nsorted = incl;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+        if (key[k] >= 0) s_idx[s_hist[key[k]] + rank[k]] = int(threadIdx.x) + k * BS;
+    __syncthreads();
+    const int nsorted = s_nsorted;
+    // the sorted candidates, reloaded (from L2) KC per thread
+#pragma unroll
+    for (int k = 0; k < KC; ++k) {
+        const int so = int(threadIdx.x) + k * BS;
+        if (so < nsorted) {
+            const int64_t at = slot(s_idx[so]);
+            cvx[k] = vbuf[4 * at];
+            cvy[k] = vbuf[4 * at + 1];
+            cvz[k] = vbuf[4 * at + 2];
+            cck[k] = cbuf[at];
+        }
+    }
     const float sc = float(TileAcc<float>::kOne) / S;
     auto spread = [=](float vx, float vy, float vz, cplx<float> ck) __attribute__((always_inline)) {
         const int oy = rel(vy, y0), oz = rel(vz, z0);
@@ -958,7 +1017,7 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
     // copies down (constant indices keep them out of scratch)
 #pragma unroll 1
     for (int k = 0; k < KC; ++k) {
-        if (int(threadIdx.x) + k * BS < total) spread(cvx[0], cvy[0], cvz[0], cck[0]);
+        if (int(threadIdx.x) + k * BS < nsorted) spread(cvx[0], cvy[0], cvz[0], cck[0]);
 #pragma unroll
         for (int j = 0; j + 1 < KC; ++j) {
             cvx[j] = cvx[j + 1];
