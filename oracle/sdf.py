@@ -91,8 +91,12 @@ def sdf_points_numpy(samples, points, params, chunk: int = 256):
     for a in range(0, len(p), chunk):
         pp = p[a:a + chunk]
         d = pp[:, None, :] - q[None, :, :]                    # p - q
-        eta = np.sqrt((d * d).sum(-1))                         # eq. 10A, pairwise distance
-        j = np.argmin(eta, axis=1)                             # first minimiser = lowest index
+        d2 = (d * d).sum(-1)
+        eta = np.sqrt(d2)                                      # eq. 10A, pairwise distance
+        # nearest sample: the minimiser of the exact distance, decided on the
+        # squared distance (two distinct squared distances can round to one
+        # square root); the first minimiser = lowest index on exact ties
+        j = np.argmin(d2, axis=1)
         xi_abs = eta[np.arange(len(pp)), j]
         dot = (d[np.arange(len(pp)), j] * nrm[j]).sum(-1)
         pmc = np.sign(dot)

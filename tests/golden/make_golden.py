@@ -7,6 +7,7 @@ seeded workloads (``workloads/``); nothing is read from the GPU path.
   python tests/golden/make_golden.py mech     # 3D mechanical pair, 576 Hopf rotations
   python tests/golden/make_golden.py protein  # protein-like pair, 64 seeded rotations
   python tests/golden/make_golden.py grad     # 32 perturbed poses of the protein-like pair
+  python tests/golden/make_golden.py uneven   # 16 sampled pairs of the uneven batch, 8 rotations each
 
 Files: <name>.txt with '#' header lines (workload, seed, parameters,
 columns) and one whitespace-separated row per rotation / pose.
@@ -72,6 +73,47 @@ def write_peaks(path, pair, quats, rows, note):
                     f"{ref[0]:.17g} {ref[1]:.17g} {ref[2]:.17g} " + " ".join(f"{v:.17g}" for v in nb) + "\n")
 
 
+UNEVEN_PAIRS = tuple(range(0, 256, 16))
+UNEVEN_ROTATIONS = 8
+
+
+def cached_fields(pair, name):
+    """Oracle fields of a pair, kept between runs under SDF_GOLDEN_CACHE."""
+    cache = os.path.join(os.environ.get("SDF_GOLDEN_CACHE", "/tmp/sdf_golden_cache"), name + "_fields.npz")
+    if os.path.exists(cache):
+        z = np.load(cache)
+        return pipeline.PairFields(z["rho_f"], z["rho_m"], z["w_m"], z["c"], int(z["n_m"]), bool(z["planar"]))
+    fields = pipeline.build_fields(pair)
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    np.savez(cache, rho_f=fields.rho_f, rho_m=fields.rho_m, w_m=fields.w_m, c=fields.c, n_m=fields.n_m,
+             planar=fields.planar)
+    return fields
+
+
+def write_uneven(path, workers, t0):
+    with open(path + ".tmp", "w") as f:
+        f.write(f"# oracle per-rotation peaks; workload uneven batch (pairs {UNEVEN_PAIRS[0]}, "
+                f"{UNEVEN_PAIRS[1]}, ..., {UNEVEN_PAIRS[-1]}), {UNEVEN_ROTATIONS} seeded rotations each "
+                f"(uneven_pair(i, n_rot={UNEVEN_ROTATIONS}))\n")
+        p = C.SDFParams()
+        f.write(f"# params lambda1={p.lambda1} lambda2={p.lambda2} sigma={p.sigma} eps={p.eps} "
+                f"xi_floor={p.xi_floor}\n")
+        f.write("# written by tests/golden/make_golden.py from oracle/ only\n")
+        f.write("# columns: pair N N_M rotation qw qx qy qz score tx ty tz refined_x refined_y refined_z nbhd[27] "
+                "(offsets dz, dy, dx in -1..1, dx fastest)\n")
+        for i in UNEVEN_PAIRS:
+            pair = C.uneven_pair(i, n_rot=UNEVEN_ROTATIONS)
+            fields = cached_fields(pair, pair.name)
+            print("fields", pair.name, pair.n_fixed, pair.n_moving, time.time() - t0, flush=True)
+            rows = score_parallel(fields, pair.quats, workers)
+            for r, (q, (s, t, nb, ref)) in enumerate(zip(pair.quats, rows)):
+                f.write(f"{i} {pair.n_fixed} {pair.n_moving} {r} {q[0]:.17g} {q[1]:.17g} {q[2]:.17g} {q[3]:.17g} "
+                        f"{s:.17g} {t[0]} {t[1]} {t[2]} {ref[0]:.17g} {ref[1]:.17g} {ref[2]:.17g} " +
+                        " ".join(f"{v:.17g}" for v in nb) + "\n")
+            f.flush()
+    os.replace(path + ".tmp", path)
+
+
 def main(which, workers):
     t0 = time.time()
     if which == "peg":
@@ -86,6 +128,8 @@ def main(which, workers):
         rows = score_parallel(fields, pair.quats, workers)
         write_peaks(os.path.join(HERE, "mechanical_3d_seed0.txt"), pair, pair.quats, rows,
                     "seed 0, 576 Hopf rotations (level 1)")
+    elif which == "uneven":
+        write_uneven(os.path.join(HERE, "uneven_pairs_seed4000.txt"), workers, t0)
     elif which in ("protein", "grad"):
         pair = C.protein_like(seed=0, n_rot=64)
         cache = os.path.join(os.environ.get("SDF_GOLDEN_CACHE", "/tmp/sdf_golden_cache"), "protein_fields.npz")

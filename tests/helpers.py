@@ -3,11 +3,17 @@ helpers.  Nothing here computes the method itself; the oracle does."""
 
 from __future__ import annotations
 
+import os
+
 import numpy as np
+import pytest
 
 from oracle import correlate as oc
 from oracle import pipeline
 from oracle import sdf as osdf
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 def flush_print(*a):
@@ -72,3 +78,39 @@ def volume_at(vol, t):
 
 def oracle_volume(fields, quat):
     return oc.score_volume(fields.rho_f, fields.c, quat, fields.n_m, fields.planar)
+
+
+def load_peaks(name):
+    path = os.path.join(GOLDEN, name)
+    if not os.path.exists(path):
+        pytest.skip(f"{name} not generated")
+    a = np.loadtxt(path)
+    return {"q": a[:, 1:5], "score": a[:, 5], "t": a[:, 6:9].astype(int), "refined": a[:, 9:12], "nbhd": a[:, 12:39]}
+
+
+def check_against_golden(gold, s, t, refined, tag, tol=1e-4, refined_tol=1e-3):
+    s = np.asarray(s, dtype=np.float64)
+    ref = gold["score"]
+    den = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    rel = np.abs(s - ref) / den
+    flush_print(tag, "max rel err", rel.max(), "median", np.median(rel))
+    assert rel.max() <= tol, (tag, int(np.argmax(rel)), rel.max())
+    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+    n_tie = 0
+    for r in range(len(s)):
+        if np.array_equal(t[r], gold["t"][r]):
+            continue
+        d = tuple(int(v) for v in (t[r] - gold["t"][r]))
+        assert d in offs, (tag, r, t[r], gold["t"][r])
+        v = gold["nbhd"][r][offs.index(d)]
+        assert abs(v - ref[r]) <= tol * den[r], (tag, r, v, ref[r])
+        n_tie += 1
+    flush_print(tag, "near-tie translations", n_tie, "of", len(s))
+    if refined is not None:
+        # FP64 sub-voxel refinement at the rotations whose integer peak matches
+        same = np.all(np.asarray(t) == gold["t"], axis=1)
+        d_ref = np.abs(np.asarray(refined, dtype=np.float64)[same] - gold["refined"][same]).max()
+        flush_print(tag, "refined t max abs diff", d_ref, "over", int(same.sum()), "rotations")
+        assert d_ref <= refined_tol, (tag, d_ref)
+    b_gpu, b_ref = int(np.argmax(s)), int(np.argmax(ref))
+    assert b_gpu == b_ref or abs(ref[b_gpu] - ref[b_ref]) <= tol * abs(ref[b_ref]), (tag, b_gpu, b_ref)

@@ -89,6 +89,32 @@ def test_sdf_build_sample_tile_edges(ctxs, dtype, count):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("order", [0, 1])
+@pytest.mark.parametrize("near_tie", [False, True])
+def test_sdf_build_nearest_sample_tie_rule(ctxs, dtype, order, near_tie):
+    """The nearest-sample rule at a node equidistant from two samples with
+    opposite membership: lowest index on an exact tie, the strictly nearer
+    sample on a near tie whose square roots coincide (the oracle pins both).
+    Compared node by node with no ambiguity exemption; the grid's end nodes
+    sit on the samples (membership 0, rho = 0)."""
+    ctx = ctxs[dtype]
+    qa = np.array([2.0, 2.0 ** -25 if near_tie else 0.0, 0.0])
+    qb = np.array([-2.0, 0.0, 0.0])
+    q = np.stack([qa, qb] if order == 0 else [qb, qa])
+    w = np.array([1.0, 0.25]) if order == 0 else np.array([0.25, 1.0])
+    s = shapes.PointSamples(q, np.tile([1.0, 0.0, 0.0], (2, 1)), w)
+    grid = C.GridSpec((5, 3, 3), (-2.0, -1.0, -1.0), 1.0)
+    params = C.SDFParams()
+    flush_print("sdf_build tie rule", dtype, order, near_tie)
+    rho = to_np(ctx.sdf_build(s.q, s.n, s.w, grid, params)).reshape(-1)
+    ref = osdf.sdf_points(s, grid.node_positions(), params)
+    centre = grid.node_positions().tolist().index([0.0, 0.0, 0.0])
+    tol = (1e-12 if dtype == "f64" else 2e-6) * np.abs(ref).max()
+    assert abs(rho[centre] - ref[centre]) <= tol, (rho[centre], ref[centre])
+    assert np.max(np.abs(rho - ref)) <= tol
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("case", ["small_3d_ragged", "sphere_257", "peg_2d"])
 def test_sdf_build_adjoint_matches_oracle(ctxs, dtype, case):
     """Shape gradients of L = Re sum_p cot(p) rho(p) with respect to the

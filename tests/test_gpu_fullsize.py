@@ -17,43 +17,13 @@ import os
 import numpy as np
 import pytest
 
-from helpers import flush_print, sdf_compare
+from helpers import check_against_golden, flush_print, load_peaks, sdf_compare
 from oracle import sdf as osdf
 from workloads import configs as C
 
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-
-
-def load_peaks(name):
-    path = os.path.join(GOLDEN, name)
-    if not os.path.exists(path):
-        pytest.skip(f"{name} not generated")
-    a = np.loadtxt(path)
-    return {"q": a[:, 1:5], "score": a[:, 5], "t": a[:, 6:9].astype(int), "refined": a[:, 9:12], "nbhd": a[:, 12:39]}
-
-
-def check_against_golden(gold, s, t, refined, tag, tol=1e-4):
-    s = np.asarray(s, dtype=np.float64)
-    ref = gold["score"]
-    den = np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
-    rel = np.abs(s - ref) / den
-    flush_print(tag, "max rel err", rel.max(), "median", np.median(rel))
-    assert rel.max() <= tol, (tag, int(np.argmax(rel)), rel.max())
-    offs = [(dx, dy, dz) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
-    n_tie = 0
-    for r in range(len(s)):
-        if np.array_equal(t[r], gold["t"][r]):
-            continue
-        d = tuple(int(v) for v in (t[r] - gold["t"][r]))
-        assert d in offs, (tag, r, t[r], gold["t"][r])
-        v = gold["nbhd"][r][offs.index(d)]
-        assert abs(v - ref[r]) <= tol * den[r], (tag, r, v, ref[r])
-        n_tie += 1
-    flush_print(tag, "near-tie translations", n_tie, "of", len(s))
-    b_gpu, b_ref = int(np.argmax(s)), int(np.argmax(ref))
-    assert b_gpu == b_ref or abs(ref[b_gpu] - ref[b_ref]) <= tol * abs(ref[b_ref]), (tag, b_gpu, b_ref)
 
 
 def build_fields_gpu(ctx, pair):
@@ -141,7 +111,7 @@ def test_mechanical_end_to_end_fp64_subset():
         out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats[idx])
         s, t = out["score"].cpu().numpy(), out["t"].cpu().numpy()
     sub = {k: v[idx] for k, v in gold.items()}
-    check_against_golden(sub, s, t, None, "mech fp64", tol=1e-8)
+    check_against_golden(sub, s, t, out["refined"].cpu().numpy(), "mech fp64", tol=1e-8, refined_tol=1e-8)
     assert np.array_equal(t, sub["t"])
 
 
@@ -157,8 +127,8 @@ def test_peg_in_hole_golden_fp32_and_fp64():
             spec = ctx.spectrum(rho_f, pair.fixed.grid)
             w = torch.ones(rho_m.shape, dtype=rho_m.real.dtype, device=rho_m.device)
             out = ctx.score_rotations(spec, pair.fixed.grid, rho_m, w, pair.moving.grid, pair.quats)
-            s, t = out["score"].cpu().numpy(), out["t"].cpu().numpy()
-        check_against_golden(gold, s, t, None, f"peg {dtype}", tol=tol)
+            s, t, ref = (out[k].cpu().numpy() for k in ("score", "t", "refined"))
+        check_against_golden(gold, s, t, ref, f"peg {dtype}", tol=tol, refined_tol=1e-3 if dtype == "f32" else 1e-8)
 
 
 def test_protein_like_end_to_end_fp32():

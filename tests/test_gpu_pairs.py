@@ -1,10 +1,13 @@
 """The uneven multi-pair search (score_pairs) and the autotuner, through the
 C ABI, against the FP64 oracle and against the FP64 GPU path."""
 
+
 import numpy as np
 import pytest
 
-from helpers import flush_print
+import os
+
+from helpers import GOLDEN, check_against_golden, flush_print
 from oracle import correlate as oc
 from oracle import peak as op
 from workloads import configs as C
@@ -160,3 +163,46 @@ def test_uneven_batch_fp32_against_fp64_on_sampled_pairs():
     finally:
         c32.close()
         c64.close()
+
+
+def test_uneven_batch_fp32_against_oracle_goldens():
+    """The uneven batch's own pairs against the FP64 oracle: 16 sampled
+    protein-like pairs (uneven_pair(i), i = 0, 16, ..., 240; fixed grids
+    96^3 and 128^3, body boxes 48^3 and 64^3), 8 seeded rotations each, SDFs
+    built on the GPU from the seeded samples and all pairs scored in one
+    score_pairs queue.  Per pair: score error <= 1e-4 (floored at 1e-3 of the
+    pair's largest score), peak translation identical or an oracle near tie,
+    sub-voxel refinement within 1e-3 grid units where the translation matches,
+    and the same best rotation or an oracle near tie.  The stored values come
+    from tests/golden/make_golden.py (oracle only)."""
+    import torch
+    from paper_1712_00238_amd.api import Context
+    path = os.path.join(GOLDEN, "uneven_pairs_seed4000.txt")
+    if not os.path.exists(path):
+        pytest.skip("uneven_pairs_seed4000.txt not generated")
+    a = np.loadtxt(path)
+    pairs = [int(v) for v in np.unique(a[:, 0])]
+    assert len(pairs) == 16
+    jobs, golds = [], []
+    with Context(0, "f32") as ctx:
+        for i in pairs:
+            rows = a[a[:, 0] == i]
+            gold = {"q": rows[:, 4:8], "score": rows[:, 8], "t": rows[:, 9:12].astype(int),
+                    "refined": rows[:, 12:15], "nbhd": rows[:, 15:42]}
+            pair = C.uneven_pair(i, n_rot=len(rows))
+            assert np.array_equal(gold["q"], pair.quats)
+            assert pair.n_fixed == int(rows[0, 1]) and pair.n_moving == int(rows[0, 2])
+            fx, mv = pair.fixed, pair.moving
+            flush_print("uneven pair", i, fx.grid.n[0], mv.grid.n[0], fx.samples.count, mv.samples.count)
+            rho_f = ctx.sdf_build(fx.samples.q, fx.samples.n, fx.samples.w, fx.grid, pair.params)
+            rho_m = ctx.sdf_build(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params)
+            w = torch.ones(rho_m.shape, dtype=torch.float32, device=rho_m.device)
+            jobs.append({"spec": ctx.spectrum(rho_f, fx.grid), "g_fixed": fx.grid, "rho_moving": rho_m,
+                         "w_moving": w, "g_moving": mv.grid, "quats": pair.quats})
+            golds.append(gold)
+        flush_print("score_pairs over", len(jobs), "uneven pairs")
+        outs = ctx.score_pairs(jobs)
+        torch.cuda.synchronize()
+        for i, gold, out in zip(pairs, golds, outs):
+            s, t, ref = (out[k].cpu().numpy() for k in ("score", "t", "refined"))
+            check_against_golden(gold, s, t, ref, f"uneven pair {i}")

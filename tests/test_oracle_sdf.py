@@ -174,3 +174,40 @@ def test_numpy_and_c_agree():
     a = osdf.sdf_points(s, pts, P)
     b = osdf.sdf_points_numpy(s, pts, P)
     assert np.max(np.abs(a - b)) < 1e-10 * np.max(np.abs(a))
+
+
+def tie_pair(order, near_tie):
+    """Two samples on either side of the origin, facing +x, so the origin is
+    inside for the sample at +x and outside for the one at -x.  Exact tie:
+    both at squared distance 4.  Near tie: the +x sample is pushed off the
+    axis by 2^-25, squared distance 4 + 2^-50 (exact in FP64) whose square
+    root still rounds to 2."""
+    qa = np.array([2.0, 2.0 ** -25 if near_tie else 0.0, 0.0])
+    qb = np.array([-2.0, 0.0, 0.0])
+    q = np.stack([qa, qb] if order == 0 else [qb, qa])
+    w = np.array([1.0, 0.25]) if order == 0 else np.array([0.25, 1.0])
+    return shapes.PointSamples(q, np.tile([1.0, 0.0, 0.0], (2, 1)), w)
+
+
+@pytest.mark.parametrize("order", [0, 1])
+def test_nearest_sample_tie_rule(order):
+    """Reading of eq. 10A for sampled boundaries: the nearest sample is the
+    exact-distance minimiser, lowest index among exact ties.  At an exact tie
+    the lowest index decides the membership sign (a highest-index rule flips
+    it); at a near tie whose distances round to the same square root, the
+    strictly nearer sample decides (an argmin over rounded distances would
+    take the lower index instead)."""
+    origin = [(0.0, 0.0, 0.0)]
+    exact = tie_pair(order, False)
+    rho, diag = osdf.sdf_points(exact, origin, P, diagnostics=True)
+    assert diag["nearest"][0] == 0
+    assert diag["xi"][0] == (-2.0 if order == 0 else 2.0)  # +x sample first -> inside
+    near = tie_pair(order, True)
+    assert math.sqrt(float(np.sum(near.q[0 if order == 0 else 1] ** 2))) == 2.0
+    rho_n, diag_n = osdf.sdf_points(near, origin, P, diagnostics=True)
+    assert diag_n["nearest"][0] == (1 if order == 0 else 0)   # the -x sample, strictly nearer
+    assert diag_n["xi"][0] == 2.0                             # outside
+    # both branches give different affinities, and NumPy follows the same rule
+    assert abs(rho[0] - rho_n[0]) > 1e-3 if order == 0 else abs(rho[0] - rho_n[0]) < 1e-12
+    for s, r in ((exact, rho[0]), (near, rho_n[0])):
+        assert abs(osdf.sdf_points_numpy(s, origin, P)[0] - r) <= 1e-12 * abs(r)
