@@ -318,6 +318,31 @@ int score_grad(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
                void *score, double *grad_pose, void *grad_w, const double *grad_scale,
                sdf_stream stream);
 
+/* Allocation-free score_grad, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight refinement or serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, semantics and outputs as
+ * score_grad, but the kernels' scratch (the per-pose partial sums, and with
+ * grad_w the per-pose-tile weight sums) lives in a fixed buffer of
+ * SDF_NOALLOC_SCRATCH_BYTES that the library holds on every device it runs
+ * on until the process ends (located once per device when a context is
+ * created), never in the context's workspace; the call allocates nothing.
+ * Limit: the problem must fit the buffer.  In FP32 with a 3D box of N_M^3
+ * nodes it needs about 56 B x B x ceil(N_M / 8)^3, plus 4 B x N_M^3 per 16
+ * poses with grad_w: 1 024 poses of a 64^3 box without grad_w fit, 256 poses
+ * with it.  A larger problem fails with SDF_ENOMEM before anything is
+ * enqueued.  Every call on one device shares that device's buffer, which
+ * keeps the last call's contents: calls that overlap in time on one device
+ * (other streams, threads or contexts) race and give wrong results.  Each
+ * call writes all of the scratch it reads, so nothing needs clearing.
+ * Errors: as score_grad; SDF_ENOMEM beyond the buffer; SDF_EHIP if the buffer
+ * could not be located on the context's device. */
+#define SDF_NOALLOC_SCRATCH_BYTES (32u << 20)
+int score_grad_noalloc(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
+                       const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
+                       const double *poses, int64_t B,
+                       void *score, double *grad_pose, void *grad_w, const double *grad_scale,
+                       sdf_stream stream);
+
 /* As score_grad, with the cotangent of the score with respect to the moving
  * part's coefficients c_k = w_k rho_M(x_k) (for gradients of rho_M itself,
  * and through sdf_build_adjoint, of the moving part's boundary samples):

@@ -18,7 +18,7 @@ EXPORTS = ["sdf_ctx_create", "sdf_ctx_destroy", "sdf_last_error", "sdf_ctx_set_o
            "sdf_ctx_stats", "sdf_ctx_stats_reset",
            "sdf_build", "sdf_spectrum", "score_rotations", "score_pairs", "sdf_autotune", "score_volume",
            "sdf_spread", "sdf_fft", "sdf_topk", "score_grad", "score_rotations_direct", "sdf_build_adjoint",
-           "score_grad_coef", "score_grad_fixed", "octree_samples", "score_rotations_nfft", "score_volume_nfft"]
+           "score_grad_noalloc", "score_grad_coef", "score_grad_fixed", "octree_samples", "score_rotations_nfft", "score_volume_nfft"]
 
 
 class SdfGrid(ctypes.Structure):
@@ -76,6 +76,7 @@ def load() -> ctypes.CDLL:
         "sdf_fft": ([vp, vp, vp, gp, ctypes.c_int, vp], ctypes.c_int),
         "sdf_topk": ([vp, vp, i64, i64, vp, vp], ctypes.c_int),
         "score_grad": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
+        "score_grad_noalloc": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "score_grad_coef": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "score_grad_fixed": ([vp, gp, vp, vp, gp, vp, i64, vp, vp, vp], ctypes.c_int),
         "octree_samples": ([vp, vp, vp, gp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp], ctypes.c_int),

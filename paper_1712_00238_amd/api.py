@@ -348,6 +348,23 @@ class Context:
                                               _ptr(poses), B, _ptr(gs), _ptr(out), _stream(self.device)))
         return out
 
+    def score_grad_noalloc(self, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, score, grad_pose=None,
+                           grad_w=None, grad_scale=None):
+        """score_grad through the allocation-free entry point: every argument is
+        a device tensor of the context's device and dtype that the caller has
+        allocated (outputs score (B,), grad_pose (B, 7) FP64 or None, grad_w
+        shaped like w_moving or None); nothing is converted or copied here."""
+        B = int(poses.shape[0])
+        for t in (rho_fixed, rho_moving, w_moving, poses, score, grad_pose, grad_w, grad_scale):
+            if t is not None and (t.device != self.device or not t.is_contiguous()):
+                raise ValueError("score_grad_noalloc takes contiguous tensors on the context's device")
+        gf, gm = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.score_grad_noalloc(self.handle, _ptr(rho_fixed), ctypes.byref(gf), _ptr(rho_moving),
+                                                _ptr(w_moving), ctypes.byref(gm), _ptr(poses), B, _ptr(score),
+                                                _ptr(grad_pose), _ptr(grad_w), _ptr(grad_scale),
+                                                _stream(self.device)))
+        return score, grad_pose, grad_w
+
     def score_grad(self, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, want_pose=True,
                    want_w=False, grad_scale=None):
         poses = self._dev(poses, torch.float64).reshape(-1, 7)

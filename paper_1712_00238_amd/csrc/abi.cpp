@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <string>
@@ -100,7 +101,17 @@ struct sdf_ctx_s {
     Profiler prof;
     int64_t graph_captures = 0;
     int64_t graph_launches = 0;
+    // device address of this device's copy of `scratch` (score_grad_noalloc)
+    void* scratch_ptr = nullptr;
+    std::string scratch_err;
 };
+
+// Fixed scratch of the allocation-free entry point (score_grad_noalloc): the
+// per-pose partial sums of the pose-gradient kernels.  Every device the
+// library runs on holds its own copy until the process ends.  On the host
+// this name is only a handle for hipGetSymbolAddress, never a device address.
+constexpr size_t kScratchBytes = SDF_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -133,6 +144,31 @@ struct DeviceGuard {
         if (prev >= 0) (void)hipSetDevice(prev);
     }
 };
+
+// Device address of `scratch` on `device`, looked up once per device (with
+// that device current) and kept for the process; nullptr with a message in
+// *err if the lookup fails.
+void* scratch_address(int device, std::string* err) {
+    static std::mutex mu;
+    static std::map<int, void*> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) return it->second;
+    DeviceGuard dg(device);
+    if (!dg.ok) {
+        *err = "cannot select the device";
+        return nullptr;
+    }
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        *err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    addr[device] = p;
+    return p;
+}
 
 bool finite(double v) { return std::isfinite(v); }
 
@@ -876,6 +912,7 @@ int sdf_ctx_create(sdf_ctx* out, int device, sdf_dtype dtype, size_t workspace_c
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->num_cu = prop.multiProcessorCount;
+    ctx->scratch_ptr = scratch_address(device, &ctx->scratch_err);
     *out = ctx;
     return SDF_OK;
 }
@@ -1221,10 +1258,12 @@ int sdf_topk(sdf_ctx ctx, const void* scores, int64_t n, int64_t k, int32_t* idx
     return SDF_OK;
 }
 
+// scratch == nullptr: the context's workspace (grown as needed); otherwise
+// the fixed scratch buffer of score_grad_noalloc, which bounds the problem.
 static int score_grad_impl(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
                            const void* w_moving, const sdf_grid* g_moving, const double* poses, int64_t B,
                            void* score, double* grad_pose, void* grad_w, void* grad_c, const double* grad_scale,
-                           sdf_stream stream) {
+                           sdf_stream stream, void* scratch_buf = nullptr) {
     if (!rho_fixed || !rho_moving || !w_moving || !poses || !score) return fail(ctx, SDF_EINVAL, "NULL array");
     if (B <= 0) return fail(ctx, SDF_EINVAL, "B must be > 0");
     if (B > (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "B too large");
@@ -1232,26 +1271,36 @@ static int score_grad_impl(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g
     if (rc) return rc;
     if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
-    ctx->fused_cache_valid = false;
+    if (!dg.ok) return fail(ctx, SDF_EHIP, "cannot select device");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const bool planar = g_fixed->n[2] == 1;
     const int N = g_fixed->n[0], nm = g_moving->n[0];
     const int wmode = grad_c ? 2 : (grad_w ? 1 : 0);
     size_t need = ctx->dtype == SDF_F64 ? sdf::grad_workspace_bytes<double>(B, N, nm, planar, wmode)
                                         : sdf::grad_workspace_bytes<float>(B, N, nm, planar, wmode);
-    rc = ensure_ws(ctx, need);
-    if (rc) return rc;
+    void* ws = scratch_buf;
+    if (scratch_buf) {
+        if (need > kScratchBytes)
+            return fail(ctx, SDF_ENOMEM, "score_grad_noalloc needs " + std::to_string(need) +
+                                             " bytes of scratch, more than its fixed " +
+                                             std::to_string(kScratchBytes) + " (fewer poses per call, or no grad_w)");
+    } else {
+        ctx->fused_cache_valid = false;
+        rc = ensure_ws(ctx, need);
+        if (rc) return rc;
+        ws = ctx->ws;
+    }
     hipError_t e;
     if (ctx->dtype == SDF_F64)
         e = sdf::launch_score_grad<double>(rho_fixed, N, planar, rho_moving, static_cast<const double*>(w_moving), nm,
                                            poses, B, static_cast<double*>(score), grad_pose,
                                            static_cast<double*>(grad_w), static_cast<double*>(grad_c), grad_scale,
-                                           ctx->ws, s);
+                                           ws, s);
     else
         e = sdf::launch_score_grad<float>(rho_fixed, N, planar, rho_moving, static_cast<const float*>(w_moving), nm,
                                           poses, B, static_cast<float*>(score), grad_pose,
                                           static_cast<float*>(grad_w), static_cast<float*>(grad_c), grad_scale,
-                                          ctx->ws, s);
+                                          ws, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "score_grad");
     return SDF_OK;
 }
@@ -1261,6 +1310,17 @@ int score_grad(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, cons
                double* grad_pose, void* grad_w, const double* grad_scale, sdf_stream stream) {
     return score_grad_impl(ctx, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, B, score, grad_pose,
                            grad_w, nullptr, grad_scale, stream);
+}
+
+int score_grad_noalloc(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
+                       const void* w_moving, const sdf_grid* g_moving, const double* poses, int64_t B, void* score,
+                       double* grad_pose, void* grad_w, const double* grad_scale, sdf_stream stream) {
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    if (!ctx->scratch_ptr)
+        return fail(ctx, SDF_EHIP, "the scratch buffer of device " + std::to_string(ctx->device) +
+                                       " was not located: " + ctx->scratch_err);
+    return score_grad_impl(ctx, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, B, score, grad_pose,
+                           grad_w, nullptr, grad_scale, stream, ctx->scratch_ptr);
 }
 
 int score_grad_coef(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
