@@ -12,6 +12,6 @@ def build(force: bool = False) -> str:
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
-                               "-fno-fast-math", "-ffp-contract=off", "-fcx-limited-range", SRC, "-o", tmp, "-lm"])
+                               "-fno-fast-math", "-ffp-contract=off", SRC, "-o", tmp, "-lm"])
         os.replace(tmp, LIB)
     return LIB
