@@ -71,6 +71,8 @@ def parse():
                     help="rotations of the protein-like pair scored 64 per launch (0: skip)")
     ap.add_argument("--uneven-pairs", type=int, default=256,
                     help="pairs in the multi-pair queue figure, 512 rotations each (0: skip)")
+    ap.add_argument("--phi-kernels", type=int, default=1,
+                    help="compare the alternative kernels of eq. 13 on the planar and mechanical pairs (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["bench", "copy"], default="bench",
                     help="copy: launch one device copy of known size (counter calibration)")
@@ -234,6 +236,63 @@ def cpu_extras(pair):
     return {"sdf_build_pairs_per_s": pairs_per_s, "sdf_build_threads": int(os.environ.get("OMP_NUM_THREADS", "0")) or
             len(os.sched_getaffinity(0)), "sdf_sample": f"20000 nodes x {fx.samples.count} samples",
             "grad_evals_per_s": g, "grad_sample": "2 poses, one process"}
+
+
+def volume_shape(vol):
+    """Support (fraction of translations with |f| > 1e-3 max |f|) and the
+    largest step between neighbouring translations relative to the peak, of
+    one rotation's score volume (the shape the Validation section compares)."""
+    import numpy as np
+    v = np.asarray(vol, dtype=np.float64)
+    peak = float(v.max())
+    steps = [np.abs(np.roll(v, -1, axis=a) - v).max() for a in range(v.ndim) if v.shape[a] > 1]
+    return {"support": round(float((np.abs(v) > 1e-3 * np.abs(v).max()).mean()), 4),
+            "max_step_over_peak": round(float(max(steps)) / peak, 4) if peak > 0 else None}
+
+
+PHI_KERNELS = (("skeletal", 0.0), ("inverse_square", 0.0), ("dsl", 2.0), ("radial", 2.0))
+
+
+def phi_kernel_section(dev):
+    """Alternative kernels of eq. 13 on the planar peg-in-hole pair (FP64) and
+    the mechanical pair (FP32): each part's affinity built on the GPU with
+    the kernel, every rotation searched, and the best pose's score volume."""
+    import numpy as np
+    import torch
+
+    from paper_1712_00238_amd.api import Context
+    from workloads import configs as C
+
+    out = {}
+    for name, pair, dtype in (("peg_in_hole_2d", C.peg_in_hole_2d(seed=0), "f64"),
+                              ("mechanical_3d", C.mechanical_3d(seed=0), "f32")):
+        fx, mv = pair.fixed, pair.moving
+        rows = []
+        with Context(0, dtype) as c:
+            for kind, R in PHI_KERNELS:
+                c.sdf_build(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params, phi=kind, radius=R)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                rf = c.sdf_build(fx.samples.q, fx.samples.n, fx.samples.w, fx.grid, pair.params, phi=kind, radius=R)
+                torch.cuda.synchronize()
+                build_ms = 1e3 * (time.perf_counter() - t0)
+                rm = c.sdf_build(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, pair.params, phi=kind, radius=R)
+                spec = c.spectrum(rf, fx.grid)
+                w = torch.ones(rm.shape, dtype=c.real, device=dev)
+                o = c.score_rotations(spec, fx.grid, rm, w, mv.grid, pair.quats)
+                s = o["score"].cpu().numpy().astype(np.float64)
+                b = int(np.argmax(s))
+                t = [int(v) for v in o["t"][b].cpu().numpy()]
+                vol = c.score_volume(spec, fx.grid, rm, w, mv.grid, pair.quats[b:b + 1])[0].cpu().numpy()
+                row = {"kernel": kind, "radius": R or None, "fixed_build_ms": round(build_ms, 2),
+                       "best_rotation": b, "best_t": t, "best_score": float(s[b])}
+                if name == "peg_in_hole_2d":
+                    row["seated"] = (b, t[:2]) in ((0, [64, 84]), (18, [63, 83]))
+                row.update(volume_shape(vol))
+                rows.append(row)
+                del rf, rm, spec, w, o
+        out[name] = rows
+    return out
 
 
 def copy_bandwidth(dev) -> float:
@@ -585,6 +644,11 @@ def main():
             ctx.set_option("batch", args.batch)
             del rf, rm, psp, pw, pout
 
+        # --- alternative kernels of eq. 13 (the Validation section's comparison of
+        # the DSL and skeletal affinities): best poses and score-volume shapes
+        if args.phi_kernels:
+            report["phi_kernels"] = phi_kernel_section(dev)
+
         # --- uneven multi-pair queue: pairs cycle through the three grid classes
         # the uneven batch picks by extent (128^3 / 64^3, 96^3 / 48^3, 64^3 / 32^3);
         # seeded random fields, since the work does not depend on the values
@@ -644,6 +708,7 @@ def main():
             "protein_like": report.get("protein_like"),
             "refinement": report.get("refinement"),
             "uneven_batch": report.get("uneven_batch"),
+            "phi_kernels": report.get("phi_kernels"),
             "kernels": report["kernels"]}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(pair, args.cpu_rotations)

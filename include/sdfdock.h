@@ -156,6 +156,51 @@ int sdf_ctx_stats_reset(sdf_ctx ctx);
 int sdf_build(sdf_ctx ctx, const void *q, const void *nrm, const void *w, int64_t n,
               const sdf_grid *g, const sdf_params *p, void *rho_out, sdf_stream stream);
 
+/* Alternative kernels of eq. 13.  The paper presents eq. 13 as a platform on
+ * which scoring schemes differ only in the kernel phi, and compares its own
+ * (eq. 15) with radial-basis and double-skin-layer affinities (Our Approach
+ * section; Formulation section, the discussion before eq. 15 and Figure 8).
+ * gb(x) below is g_sigma(x) = exp(-x^2 / (2 sigma^2)) / (sqrt(2 pi) sigma)
+ * truncated to |x| <= eps (the truncated Gaussian the Formulation section
+ * defines next to eq. 17t); R = radius > 0 is the probe radius of eq. 2 / 3a.
+ *   SDF_PHI_SKELETAL        eq. 15 (sdf_build).
+ *   SDF_PHI_INVERSE_SQUARE  phi = lambda(zeta) g_sigma(0) / (sqrt(2 pi) zeta^2):
+ *                           eq. 15 with its medial Gaussian at its peak value, so
+ *                           |phi| ~ |zeta|^-2 (Figure 8, middle) with the phase
+ *                           -2 arg(zeta); membership, xi_floor and the
+ *                           contact-region truncation as for the skeletal kernel.
+ *   SDF_PHI_RADIAL          eq. 2 in its continuum form: skin and core are the
+ *                           +R and -R offsets of the boundary, each point a
+ *                           Gaussian shell of radius R:
+ *                           rho(p) = sum_j w_j [lambda1 gb(|p - q_j - R n_j| / R - 1)
+ *                                     + i lambda2 gb(|p - q_j + R n_j| / R - 1)];
+ *                           xi_floor is not used.
+ *   SDF_PHI_DSL             eq. 3a on the signed distance xi of the nearest
+ *                           sample (as in sdf_build):
+ *                           rho(p) = lambda1 gb(xi / R - 1) + i lambda2 gb(xi / R + 1);
+ *                           defined on the boundary too, xi_floor is not used. */
+typedef enum {
+    SDF_PHI_SKELETAL = 0,
+    SDF_PHI_INVERSE_SQUARE = 1,
+    SDF_PHI_RADIAL = 2,
+    SDF_PHI_DSL = 3
+} sdf_phi_kind;
+typedef struct {
+    int32_t kind;   /* an sdf_phi_kind */
+    double radius;  /* probe radius R (> 0) of SDF_PHI_RADIAL and SDF_PHI_DSL; ignored otherwise */
+} sdf_phi;
+
+/* sdf_build with the kernel `phi` (host struct; NULL = SDF_PHI_SKELETAL).
+ * Same arguments, layout and decisions (FP64 nearest sample, membership and
+ * truncation edges) as sdf_build.  The radial kernel sums over the 2 n offset
+ * points within R (1 + eps) of a node (about 140 bytes of workspace per
+ * sample); the DSL kernel needs only the nearest sample.
+ * Errors: as sdf_build; SDF_EINVAL for an unknown kind, for the radial and
+ * DSL kernels a radius that is not finite and > 0, and for the radial kernel
+ * more than 2^29 samples. */
+int sdf_build_phi(sdf_ctx ctx, const void *q, const void *nrm, const void *w, int64_t n,
+                  const sdf_grid *g, const sdf_params *p, const sdf_phi *phi, void *rho_out, sdf_stream stream);
+
 /* Adjoint of sdf_build with respect to its boundary samples (shape
  * gradients): for a complex cotangent field cot on the grid (context
  * precision, same layout as rho), the gradients of

@@ -16,7 +16,7 @@ SDF_F32, SDF_F64 = 0, 1
 
 EXPORTS = ["sdf_ctx_create", "sdf_ctx_destroy", "sdf_last_error", "sdf_ctx_set_option", "sdf_ctx_get_option",
            "sdf_ctx_stats", "sdf_ctx_stats_reset",
-           "sdf_build", "sdf_spectrum", "score_rotations", "score_pairs", "sdf_autotune", "score_volume",
+           "sdf_build", "sdf_build_phi", "sdf_spectrum", "score_rotations", "score_pairs", "sdf_autotune", "score_volume",
            "sdf_spread", "sdf_fft", "sdf_topk", "score_grad", "score_rotations_direct", "sdf_build_adjoint",
            "score_grad_noalloc", "score_grad_coef", "score_grad_fixed", "octree_samples", "score_rotations_nfft", "score_volume_nfft"]
 
@@ -28,6 +28,13 @@ class SdfGrid(ctypes.Structure):
 class SdfParams(ctypes.Structure):
     _fields_ = [("lambda1", ctypes.c_double), ("lambda2", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("eps", ctypes.c_double), ("xi_floor", ctypes.c_double)]
+
+
+class SdfPhi(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("radius", ctypes.c_double)]
+
+
+PHI_KINDS = {"skeletal": 0, "inverse_square": 1, "radial": 2, "dsl": 3}
 
 
 class SdfPairJob(ctypes.Structure):
@@ -64,6 +71,7 @@ def load() -> ctypes.CDLL:
         "sdf_ctx_stats": ([vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], ctypes.c_int),
         "sdf_ctx_stats_reset": ([vp], ctypes.c_int),
         "sdf_build": ([vp, vp, vp, vp, i64, gp, pp, vp, vp], ctypes.c_int),
+        "sdf_build_phi": ([vp, vp, vp, vp, i64, gp, pp, ctypes.POINTER(SdfPhi), vp, vp], ctypes.c_int),
         "sdf_build_adjoint": ([vp, vp, vp, vp, i64, gp, pp, vp, vp, vp, vp, vp], ctypes.c_int),
         "sdf_spectrum": ([vp, vp, gp, vp, vp], ctypes.c_int),
         "score_rotations": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
@@ -110,3 +118,9 @@ def make_grid(spec) -> SdfGrid:
 
 def make_params(p) -> SdfParams:
     return SdfParams(float(p.lambda1), float(p.lambda2), float(p.sigma), float(p.eps), float(p.xi_floor))
+
+
+def make_phi(kind: str, radius: float = 0.0) -> SdfPhi:
+    if kind not in PHI_KINDS:
+        raise ValueError(f"unknown phi kernel {kind!r}; one of {sorted(PHI_KINDS)}")
+    return SdfPhi(PHI_KINDS[kind], float(radius))

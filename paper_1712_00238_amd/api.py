@@ -92,8 +92,10 @@ class Context:
         return a.to(device=self.device, dtype=dtype).contiguous()
 
     # ------------------------------------------------------------------ SDF
-    def sdf_build(self, q, n, w, grid, params, out=None):
-        """Skeletal density function of one solid on ``grid`` -> complex (nz, ny, nx)."""
+    def sdf_build(self, q, n, w, grid, params, out=None, phi=None, radius=0.0):
+        """Skeletal density function of one solid on ``grid`` -> complex (nz, ny, nx).
+        ``phi`` selects another kernel of eq. 13 ("inverse_square", "radial",
+        "dsl"; None or "skeletal" = eq. 15) with probe radius ``radius``."""
         q = self._dev(q, torch.float64)
         n = self._dev(n, torch.float64)
         w = self._dev(w, torch.float64)
@@ -102,8 +104,14 @@ class Context:
             out = torch.empty((nz, ny, nx), dtype=self.cplx, device=self.device)
         g = _lib.make_grid(grid)
         p = _lib.make_params(params)
-        self._check(self.lib.sdf_build(self.handle, _ptr(q), _ptr(n), _ptr(w), int(w.numel()), ctypes.byref(g),
-                                       ctypes.byref(p), _ptr(out), _stream(self.device)))
+        if phi is None:
+            self._check(self.lib.sdf_build(self.handle, _ptr(q), _ptr(n), _ptr(w), int(w.numel()), ctypes.byref(g),
+                                           ctypes.byref(p), _ptr(out), _stream(self.device)))
+        else:
+            ph = _lib.make_phi(phi, radius)
+            self._check(self.lib.sdf_build_phi(self.handle, _ptr(q), _ptr(n), _ptr(w), int(w.numel()),
+                                               ctypes.byref(g), ctypes.byref(p), ctypes.byref(ph), _ptr(out),
+                                               _stream(self.device)))
         return out
 
     def sdf_build_adjoint(self, q, n, w, grid, params, cot):

@@ -790,7 +790,8 @@ int direct_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const double*
     SDF_TRY_HIP(ctx, sdf::launch_quat_to_rot<T>(qd, n_rot, r64, RT, s), "rotations");
     for (int64_t r = 0; r < n_rot; ++r) {
         SDF_TRY_HIP(ctx, sdf::launch_rotate_samples(q, nrm, ns, r64 + 9 * r, c, qr, nr, s), "rotate samples");
-        SDF_TRY_HIP(ctx, sdf::launch_sdf_build<T>(qr, nr, w, ns, desc(gm), pd, rho, wsb, s), "box sdf");
+        SDF_TRY_HIP(ctx, sdf::launch_sdf_build<T>(qr, nr, w, ns, desc(gm), pd, sdf::kPhiSkeletal, rho, wsb, s),
+                    "box sdf");
         SDF_TRY_HIP(ctx, sdf::launch_zero<T>(grid, G, s), "zero");
         SDF_TRY_HIP(ctx, sdf::launch_place_direct<T>(rho, nm, planar, T(w_node), N, grid, s), "place");
         SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, 1, -1, 1.0, s), "forward fft");
@@ -995,8 +996,8 @@ int sdf_ctx_stats_reset(sdf_ctx ctx) {
     return SDF_OK;
 }
 
-int sdf_build(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_t n, const sdf_grid* g,
-              const sdf_params* p, void* rho_out, sdf_stream stream) {
+static int sdf_build_impl(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_t n, const sdf_grid* g,
+                          const sdf_params* p, const sdf_phi* phi, void* rho_out, sdf_stream stream) {
     if (!q || !nrm || !w || !rho_out) return fail(ctx, SDF_EINVAL, "NULL array");
     if (n <= 0) return fail(ctx, SDF_EINVAL, "sample count must be > 0");
     if (n > (int64_t(1) << 30)) return fail(ctx, SDF_EINVAL, "sample count must be <= 2^30");
@@ -1004,22 +1005,40 @@ int sdf_build(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_
     if (rc) return rc;
     rc = check_params(ctx, p);
     if (rc) return rc;
+    const int kind = phi ? phi->kind : SDF_PHI_SKELETAL;
+    if (kind < SDF_PHI_SKELETAL || kind > SDF_PHI_DSL) return fail(ctx, SDF_EINVAL, "unknown phi kernel");
+    const bool probe = kind == SDF_PHI_RADIAL || kind == SDF_PHI_DSL;
+    if (probe && !(phi->radius > 0 && std::isfinite(phi->radius)))
+        return fail(ctx, SDF_EINVAL, "the radial and DSL kernels need a finite probe radius > 0");
+    if (kind == SDF_PHI_RADIAL && n > (int64_t(1) << 29))
+        return fail(ctx, SDF_EINVAL, "the radial kernel takes at most 2^29 samples (2^30 offset points)");
     if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(ctx, SDF_EHIP, "cannot select device");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const sdf::ParamDesc pd{p->lambda1, p->lambda2, p->sigma, p->eps, p->xi_floor};
+    sdf::ParamDesc pd{p->lambda1, p->lambda2, p->sigma, p->eps, p->xi_floor};
+    pd.radius = probe ? phi->radius : 0.0;
     const double* qd = static_cast<const double*>(q);
     const double* nd = static_cast<const double*>(nrm);
     const double* wd = static_cast<const double*>(w);
     ctx->fused_cache_valid = false;  // the Morton-ordered samples share the workspace
-    rc = ensure_ws(ctx, sdf::sdf_build_workspace_bytes(n));
+    rc = ensure_ws(ctx, sdf::sdf_build_workspace_bytes(n, kind));
     if (rc) return rc;
     hipError_t e = ctx->dtype == SDF_F64
-                       ? sdf::launch_sdf_build<double>(qd, nd, wd, n, desc(g), pd, rho_out, ctx->ws, s)
-                       : sdf::launch_sdf_build<float>(qd, nd, wd, n, desc(g), pd, rho_out, ctx->ws, s);
+                       ? sdf::launch_sdf_build<double>(qd, nd, wd, n, desc(g), pd, kind, rho_out, ctx->ws, s)
+                       : sdf::launch_sdf_build<float>(qd, nd, wd, n, desc(g), pd, kind, rho_out, ctx->ws, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "sdf_build");
     return SDF_OK;
+}
+
+int sdf_build(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_t n, const sdf_grid* g,
+              const sdf_params* p, void* rho_out, sdf_stream stream) {
+    return sdf_build_impl(ctx, q, nrm, w, n, g, p, nullptr, rho_out, stream);
+}
+
+int sdf_build_phi(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_t n, const sdf_grid* g,
+                  const sdf_params* p, const sdf_phi* phi, void* rho_out, sdf_stream stream) {
+    return sdf_build_impl(ctx, q, nrm, w, n, g, p, phi, rho_out, stream);
 }
 
 int sdf_build_adjoint(sdf_ctx ctx, const void* q, const void* nrm, const void* w, int64_t n, const sdf_grid* g,

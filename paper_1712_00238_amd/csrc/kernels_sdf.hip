@@ -166,7 +166,11 @@ __device__ __forceinline__ void nearest_pass(const SampleTiles& st, int64_t ns, 
     }
 }
 
-template <typename T>
+// PHI: the kernel of eq. 13 (kPhi* in launch.hpp): skeletal (eq. 15),
+// inverse-square (eq. 15 with the medial Gaussian at its peak: the pair
+// term without the exponential), or the double skin layer of eq. 3a, which
+// needs only the signed distance of pass 1.
+template <typename T, int PHI>
 __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __restrict__ q,
                                                               const double* __restrict__ nrm, SampleTiles st,
                                                               int64_t ns, GridDesc g, ParamDesc prm,
@@ -203,6 +207,20 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                        (pz - q[3 * jb + 2]) * nrm[3 * jb + 2];
     const int pmc = dot > 0.0 ? 1 : (dot < 0.0 ? -1 : 0);
     const double xi_abs64 = sqrt(best);
+    if constexpr (PHI == kPhiDsl) {
+        // eq. 3a: lambda1 gb(xi / R - 1) + i lambda2 gb(xi / R + 1), FP64, defined
+        // on the boundary too (no floor); gb truncates at |x| > eps
+        if (valid) {
+            const double xi = pmc * xi_abs64;
+            const double x1 = xi / prm.radius - 1.0, x2 = xi / prm.radius + 1.0;
+            const double c = 1.0 / (2.5066282746310002 * prm.sigma);
+            const double h = -0.5 / (prm.sigma * prm.sigma);
+            const double re = fabs(x1) <= prm.eps ? prm.lambda1 * c * exp(h * x1 * x1) : 0.0;
+            const double im = fabs(x2) <= prm.eps ? prm.lambda2 * c * exp(h * x2 * x2) : 0.0;
+            out[(int64_t(k) * g.ny + j) * g.nx + i] = mk(T(re), T(im));
+        }
+        return;
+    }
     const bool live = valid && pmc != 0 && xi_abs64 >= prm.xi_floor;
 
     // ---- pass 2 (T): truncated kernel sum over the contact ball
@@ -255,8 +273,11 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                             const T eta = d2 * inv_eta;
                             const T r = eta * inv_xi;
                             const T wcos = (dx * nv.x + dy * nv.y + dz * nv.z) * inv_eta;
-                            const T u = eta * inv_xi_gs - gs;
-                            const T G = dev_exp2(-u * u);
+                            T G = T(1);  // inverse-square: the medial Gaussian at its peak
+                            if constexpr (PHI == kPhiSkeletal) {
+                                const T u = eta * inv_xi_gs - gs;
+                                G = dev_exp2(-u * u);
+                            }
                             const T rr = r * r;
                             const T den = T(1) + rr;
                             const T coef = wcos * G * dev_rcp(den * den);
@@ -277,6 +298,117 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
         }
         out[(int64_t(k) * g.ny + j) * g.nx + i] = res;
     }
+}
+
+// ---- radial-basis affinity (eq. 2, continuum form): Gaussian shells of
+// radius R around the +R (skin) and -R (core) offsets of the boundary.
+// The offset points come as samples whose "w n" slot holds their complex
+// weight (lambda1 w, 0) or (0, lambda2 w); a node sums
+//   c_j g_sigma(|p - s_j| / R - 1)  over |(|p - s_j| / R - 1)| <= eps,
+// i.e. over the shell R max(0, 1 - eps) <= |p - s_j| <= R (1 + eps), whose
+// edges are decided in FP64 (squared radii within 1e-4 are re-tested).
+template <typename T>
+__global__ __launch_bounds__(kSdfBlock) void sdf_radial_kernel(SampleTiles st, int64_t ns, GridDesc g,
+                                                               ParamDesc prm, cplx<T>* __restrict__ out) {
+    __shared__ v4<double> sq[2 * kSdfTile];
+    __shared__ int sidx[kSdfTile];
+    __shared__ int tflag[kSdfBlock];
+    v4<T>* sq2 = reinterpret_cast<v4<T>*>(sq);             // (sx, sy, sz, -) relative to the brick
+    v4<T>* sn2 = reinterpret_cast<v4<T>*>(sq) + kSdfTile;  // (c.re, c.im, -, -)
+
+    const Brick br = brick_shape(g.nz);
+    const int nbx = (g.nx + br.bx - 1) / br.bx, nby = (g.ny + br.by - 1) / br.by;
+    const int blk = blockIdx.x;
+    const int i0 = (blk % nbx) * br.bx, j0 = ((blk / nbx) % nby) * br.by, k0 = (blk / (nbx * nby)) * br.bz;
+    const int li = threadIdx.x % br.bx, lj = (threadIdx.x / br.bx) % br.by, lk = threadIdx.x / (br.bx * br.by);
+    const int i = i0 + li, j = j0 + lj, k = k0 + lk;
+    const bool valid = i < g.nx && j < g.ny && k < g.nz;
+    const double cx = g.ox + g.h * i0, cy = g.oy + g.h * j0, cz = g.oz + g.h * k0;
+    const double rx = g.h * li, ry = g.h * lj, rz = g.h * lk;
+    const double px = cx + rx, py = cy + ry, pz = cz + rz;
+    const double bl[3] = {cx, cy, cz};
+    const double bh[3] = {cx + g.h * (min(br.bx, g.nx - i0) - 1), cy + g.h * (min(br.by, g.ny - j0) - 1),
+                          cz + g.h * (min(br.bz, g.nz - k0) - 1)};
+
+    const double rhi = prm.radius * (1.0 + prm.eps);
+    const double rlo = prm.eps < 1.0 ? prm.radius * (1.0 - prm.eps) : 0.0;
+    const double hi2 = rhi * rhi, lo2 = rlo * rlo;
+    const T hi2a = T(hi2 * (1.0 - 1e-4)), hi2b = T(hi2 * (1.0 + 1e-4));
+    const T lo2a = T(lo2 * (1.0 - 1e-4)), lo2b = T(lo2 * (1.0 + 1e-4));
+    // g_sigma(eta / R - 1) = 2^(-u^2) / (sqrt(2 pi) sigma), u = (eta / R - 1) gs
+    const double gs64 = std::sqrt(0.5 * 1.4426950408889634) / prm.sigma;
+    const T gs = T(gs64), inv_r_gs = T(gs64 / prm.radius);
+    const T prx = T(rx), pry = T(ry), prz = T(rz);
+    T acc_re = T(0), acc_im = T(0);
+    for (int64_t c0 = 0; c0 < st.ntile; c0 += kSdfBlock) {
+        const int64_t tc = c0 + threadIdx.x;
+        __syncthreads();
+        tflag[threadIdx.x] = tc < st.ntile && box_dmin2(bl, bh, st.box + 6 * tc) <= hi2 * (1.0 + 1e-9) &&
+                             !(box_dmax2(bl, bh, st.box + 6 * tc) < lo2 * (1.0 - 1e-9));
+        __syncthreads();
+        const int nchunk = int(st.ntile - c0 < kSdfBlock ? st.ntile - c0 : kSdfBlock);
+        for (int kk = 0; kk < nchunk; ++kk) {
+            if (!tflag[kk]) continue;  // uniform across the block
+            const int64_t t0 = (c0 + kk) * kSdfTile;
+            const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+            __syncthreads();
+            for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
+                const int64_t s = t0 + a;
+                sq2[a] = v4<T>{T(st.qs[3 * s] - cx), T(st.qs[3 * s + 1] - cy), T(st.qs[3 * s + 2] - cz), T(0)};
+                sn2[a] = v4<T>{T(st.wn[3 * s]), T(st.wn[3 * s + 1]), T(0), T(0)};
+                sidx[a] = int(s);
+            }
+            __syncthreads();
+            if (valid) {
+#pragma unroll 4
+                for (int a = 0; a < cnt; ++a) {
+                    const v4<T> sp = sq2[a];
+                    const T dx = prx - sp.x, dy = pry - sp.y, dz = prz - sp.z;
+                    const T d2 = dx * dx + dy * dy + dz * dz;
+                    bool in = d2 <= hi2a && d2 >= lo2b;
+                    if (!in && d2 <= hi2b && d2 >= lo2a) {  // near a shell edge: decide in FP64
+                        const int64_t sj = sidx[a];
+                        const double ex = px - st.qs[3 * sj], ey = py - st.qs[3 * sj + 1], ez = pz - st.qs[3 * sj + 2];
+                        const double e2 = ex * ex + ey * ey + ez * ez;
+                        in = e2 <= hi2 && e2 >= lo2;
+                    }
+                    if (in) {
+                        const v4<T> cw = sn2[a];
+                        const T u = sqrt(d2) * inv_r_gs - gs;
+                        const T G = dev_exp2(-u * u);
+                        acc_re += cw.x * G;
+                        acc_im += cw.y * G;
+                    }
+                }
+            }
+        }
+    }
+    if (valid) {
+        const T c = T(1.0 / (2.5066282746310002 * prm.sigma));
+        out[(int64_t(k) * g.ny + j) * g.nx + i] = mk(acc_re * c, acc_im * c);
+    }
+}
+
+// skin (+R n_j, weight (lambda1 w_j, 0)) and core (-R n_j, (0, lambda2 w_j))
+// offset points of the samples, FP64, as a sample set of 2n points
+__global__ void offset_points_kernel(const double* __restrict__ q, const double* __restrict__ nrm,
+                                     const double* __restrict__ w, int64_t n, double R, double l1, double l2,
+                                     double* __restrict__ q2, double* __restrict__ c2, double* __restrict__ w2) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q2[3 * j + a] = q[3 * j + a] + R * nrm[3 * j + a];
+        q2[3 * (n + j) + a] = q[3 * j + a] - R * nrm[3 * j + a];
+    }
+    c2[3 * j] = l1;
+    c2[3 * j + 1] = 0.0;
+    c2[3 * j + 2] = 0.0;
+    c2[3 * (n + j)] = 0.0;
+    c2[3 * (n + j) + 1] = l2;
+    c2[3 * (n + j) + 2] = 0.0;
+    w2[j] = w[j];
+    w2[n + j] = w[j];
 }
 
 // ---- adjoint with respect to the boundary samples
@@ -599,16 +731,39 @@ int64_t brick_count(const GridDesc& g) {
 
 }  // namespace
 
-size_t sdf_build_workspace_bytes(int64_t ns) { return sdf_ws_layout(ns).total; }
+size_t sdf_build_workspace_bytes(int64_t ns, int phi) {
+    // the radial kernel tiles the 2 n offset points, held (positions, weight
+    // slots, weights) ahead of the tile layout
+    if (phi == kPhiRadial) return al256(size_t(ns) * 2 * 7 * sizeof(double)) + sdf_ws_layout(2 * ns).total;
+    return sdf_ws_layout(ns).total;
+}
 
 template <typename T>
 hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
-                            const ParamDesc& p, void* rho_out, void* ws, hipStream_t s) {
+                            const ParamDesc& p, int phi, void* rho_out, void* ws, hipStream_t s) {
     SampleTiles st{};
+    const dim3 grid(unsigned(brick_count(g))), block(kSdfBlock);
+    auto* out = static_cast<cplx<T>*>(rho_out);
+    if (phi == kPhiRadial) {
+        double* q2 = static_cast<double*>(ws);
+        double* c2 = q2 + 6 * ns;
+        double* w2 = c2 + 6 * ns;
+        hipLaunchKernelGGL(offset_points_kernel, dim3(unsigned((ns + 255) / 256)), dim3(256), 0, s, q, n, w, ns,
+                           p.radius, p.lambda1, p.lambda2, q2, c2, w2);
+        void* ws2 = static_cast<char*>(ws) + al256(size_t(ns) * 2 * 7 * sizeof(double));
+        hipError_t e = prepare_tiles(q2, c2, w2, 2 * ns, g, ws2, s, &st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(sdf_radial_kernel<T>, grid, block, 0, s, st, 2 * ns, g, p, out);
+        return hipGetLastError();
+    }
     hipError_t e = prepare_tiles(q, n, w, ns, g, ws, s, &st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sdf_build_kernel<T>, dim3(unsigned(brick_count(g))), dim3(kSdfBlock), 0, s, q, n, st, ns, g,
-                       p, static_cast<cplx<T>*>(rho_out));
+    if (phi == kPhiDsl)
+        hipLaunchKernelGGL((sdf_build_kernel<T, kPhiDsl>), grid, block, 0, s, q, n, st, ns, g, p, out);
+    else if (phi == kPhiInverseSquare)
+        hipLaunchKernelGGL((sdf_build_kernel<T, kPhiInverseSquare>), grid, block, 0, s, q, n, st, ns, g, p, out);
+    else
+        hipLaunchKernelGGL((sdf_build_kernel<T, kPhiSkeletal>), grid, block, 0, s, q, n, st, ns, g, p, out);
     return hipGetLastError();
 }
 
@@ -635,8 +790,8 @@ template hipError_t launch_sdf_adjoint<double>(const double*, const double*, con
                                                const GridDesc&, const ParamDesc&, const void*, double*, double*,
                                                double*, void*, hipStream_t);
 template hipError_t launch_sdf_build<float>(const double*, const double*, const double*, int64_t, const GridDesc&,
-                                            const ParamDesc&, void*, void*, hipStream_t);
+                                            const ParamDesc&, int, void*, void*, hipStream_t);
 template hipError_t launch_sdf_build<double>(const double*, const double*, const double*, int64_t, const GridDesc&,
-                                             const ParamDesc&, void*, void*, hipStream_t);
+                                             const ParamDesc&, int, void*, void*, hipStream_t);
 
 }  // namespace sdf

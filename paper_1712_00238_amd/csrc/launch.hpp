@@ -15,13 +15,17 @@ struct GridDesc {
 };
 struct ParamDesc {
     double lambda1, lambda2, sigma, eps, xi_floor;
+    double radius = 0.0;  // probe radius R of the radial-basis and double-skin-layer kernels
 };
 
+// kernels of eq. 13 (the values of sdf_phi_kind)
+constexpr int kPhiSkeletal = 0, kPhiInverseSquare = 1, kPhiRadial = 2, kPhiDsl = 3;
+
 // ---- skeletal density (sdf_build): FP64 samples, output in T
-size_t sdf_build_workspace_bytes(int64_t ns);
+size_t sdf_build_workspace_bytes(int64_t ns, int phi = kPhiSkeletal);
 template <typename T>
 hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
-                            const ParamDesc& p, void* rho_out, void* ws, hipStream_t s);
+                            const ParamDesc& p, int phi, void* rho_out, void* ws, hipStream_t s);
 // adjoint of sdf_build: gradients (FP64, zeroed here) of Re sum_p cot(p) rho(p)
 // with respect to the sample positions, normals and weights
 template <typename T>
