@@ -234,7 +234,7 @@ __device__ __forceinline__ void flush_stencil(int* __restrict__ acc, int ix, int
                                               const int vi[16]) {
     using L = SlabLayout<N>;
     if constexpr (L::kFast) {
-        const int base = (iy + L::kShift) * L::kRowInts + ix + L::kShift;
+        const int base = int(__umul24(unsigned(iy + L::kShift), unsigned(L::kRowInts))) + ix + L::kShift;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
 #pragma unroll
@@ -260,9 +260,14 @@ __device__ __forceinline__ void flush_stencil(int* __restrict__ acc, int ix, int
 }
 
 // Spread the samples of one (rotation, z-slab) item into the integer planes.
+// lines of a (rotation, slab) item compacted per round; the list of their
+// runs lives in LDS next to the slab
+constexpr int kLineChunk = 4096;
+
 template <int N>
 __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRot& fr, const cf* __restrict__ c,
-                                            int n_m, float S, int z, bool planar) {
+                                            int n_m, float S, int z, bool planar, int* __restrict__ list,
+                                            int* __restrict__ nlist) {
     // reflected rotation: positions y_k = Rp (k - n_m / 2), Rp = -R
     float Rp[9];
 #pragma unroll
@@ -300,13 +305,20 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
     // Walk body lines along the axis ax most aligned with z: for each
     // (k_b1, k_b2) the samples y(ka) = y0 + ka d (d = column ax of the
     // reflected rotation) cross the slab support |z - y_z| < 2 for a short
-    // run of ka; the next coefficient is fetched one step ahead.  Lines are
-    // taken in 16 x 16 blocks by four waves: a wave covers 8 rows of the
-    // block (b2) and every other line along b1 (the axis most aligned with
-    // x), offset by one on alternate rows.  Its samples sit at nearby
+    // run of ka.  Only about half of the lines reach a given slab, so the
+    // lines are first compacted: every thread finds the runs of its lines
+    // and the lines with a non-empty run are appended to an LDS list (each
+    // wave appends its lines in lane order), then the threads take the
+    // listed lines and spread their runs, the next coefficient fetched one
+    // step ahead.  Lines are enumerated in 16 x 16 blocks by four waves: a
+    // wave covers 8 rows of the block (b2) and every other line along b1
+    // (the axis most aligned with x), offset by one on alternate rows, so the
+    // lanes of a wave spread nearby lines whose samples sit at nearby
     // heights; the stride keeps two lanes from adding to the same LDS word in
-    // one instruction, which the LDS would serialise, and the row offset
-    // spreads the lanes over odd and even banks.
+    // one instruction, which the LDS serialises (lanes on consecutive lines
+    // made the kernel 12% slower), and the row offset spreads the lanes over
+    // odd and even banks.  The order in which waves append does not matter:
+    // the integer sums do not depend on it.
     int ax = 0;
     float best = fabsf(Rp[6]);
     if (fabsf(Rp[7]) > best) { ax = 1; best = fabsf(Rp[7]); }
@@ -322,66 +334,95 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
     const int pairs = n_m * n_m;
     const bool blocks16 = (n_m & 15) == 0;
     const int nb16 = n_m >> 4;
-    for (int pidx = threadIdx.x; pidx < pairs; pidx += kSlabBlock) {
-        int i1, i2;
-        if (blocks16) {
-            const int w = pidx >> 6, l = pidx & 63;
-            const int blk = w >> 2, k = w & 3;
-            const int row = (l >> 3) + 8 * (k >> 1);  // 0 .. 15 within the block
-            i2 = (blk / nb16) * 16 + row;
-            i1 = (blk % nb16) * 16 + 2 * (l & 7) + ((row + k) & 1);
-        } else {
-            i1 = pidx % n_m;
-            i2 = pidx / n_m;
-        }
-        const float u1 = float(i1) - half, u2 = float(i2) - half, u0 = -half;
-        const float y0x = Rp[b1] * u1 + Rp[b2] * u2 + dx * u0;
-        const float y0y = Rp[3 + b1] * u1 + Rp[3 + b2] * u2 + dy * u0;
-        const float y0z = Rp[6 + b1] * u1 + Rp[6 + b2] * u2 + dzs * u0;
-        float lo_f = (zc - 2.f - y0z) * inv_dz, hi_f = (zc + 2.f - y0z) * inv_dz;
-        if (lo_f > hi_f) { const float t = lo_f; lo_f = hi_f; hi_f = t; }
-        // samples strictly inside (lo_f, hi_f); a 1e-3 margin keeps any
-        // sample that rounding could place inside, and the support test
-        // below decides
-        int lo = int(floorf(lo_f + 0.999f)), hi = int(ceilf(hi_f - 0.999f));
-        lo = lo < 0 ? 0 : lo;
-        hi = hi > n_m - 1 ? n_m - 1 : hi;
-        if (lo > hi) continue;
-        const int k0 = i1 * kstride[b1] + i2 * kstride[b2];
-        cf cnext = gload(c, k0 + lo * sax);
-        for (int ka = lo; ka <= hi; ++ka) {
-            const cf ck = cnext;
-            if (ka < hi) cnext = gload(c, k0 + (ka + 1) * sax);
-            const float fk = float(ka);
-            const float yz = y0z + fk * dzs;
-            const float ad = fabsf(zc - yz);
-            if (!(ad < 2.f)) continue;
-            const float yx = y0x + fk * dx;
-            const float yy = y0y + fk * dy;
-            float wz;
-            if (ad < 1.f) wz = 2.f / 3.f - ad * ad + 0.5f * ad * ad * ad;
-            else { const float b = 2.f - ad; wz = b * b * b * (1.f / 6.f); }
-            const float sw = wz * S;
-            const float fx = floorf(yx), fy = floorf(yy);
-            float wx[4], wy[4], xr[4], xi[4];
-            bspline3_weights(yx - fx, wx);
-            bspline3_weights(yy - fy, wy);
+    const float u0 = -half;
+    const int lane = threadIdx.x & 63;
+    for (int c0 = 0; c0 < pairs; c0 += kLineChunk) {
+        if (threadIdx.x == 0) *nlist = 0;
+        __syncthreads();
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                xr[a] = ck.re * sw * wx[a];
-                xi[a] = ck.im * sw * wx[a];
+        for (int r = 0; r < kLineChunk / kSlabBlock; ++r) {
+            const int pidx = c0 + threadIdx.x + r * kSlabBlock;
+            int entry = 0;
+            bool ne = false;
+            if (pidx < pairs) {
+                int i1, i2;
+                if (blocks16) {
+                    const int w = pidx >> 6, l = pidx & 63;
+                    const int blk = w >> 2, k = w & 3;
+                    const int row = (l >> 3) + 8 * (k >> 1);  // 0 .. 15 within the block
+                    i2 = (blk / nb16) * 16 + row;
+                    i1 = (blk % nb16) * 16 + 2 * (l & 7) + ((row + k) & 1);
+                } else {
+                    i1 = pidx % n_m;
+                    i2 = pidx / n_m;
+                }
+                const float u1 = float(i1) - half, u2 = float(i2) - half;
+                const float y0z = Rp[6 + b1] * u1 + Rp[6 + b2] * u2 + dzs * u0;
+                float lo_f = (zc - 2.f - y0z) * inv_dz, hi_f = (zc + 2.f - y0z) * inv_dz;
+                if (lo_f > hi_f) { const float t = lo_f; lo_f = hi_f; hi_f = t; }
+                // samples strictly inside (lo_f, hi_f); a 1e-3 margin keeps any
+                // sample that rounding could place inside, and the support test
+                // below decides
+                int lo = int(floorf(lo_f + 0.999f)), hi = int(ceilf(hi_f - 0.999f));
+                lo = lo < 0 ? 0 : lo;
+                hi = hi > n_m - 1 ? n_m - 1 : hi;
+                ne = lo <= hi;
+                entry = i1 | (i2 << 7) | (lo << 14) | (hi << 21);
             }
-            int vr[16], vi[16];
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            const uint64_t m = __ballot(ne);
+            if (m != 0ull) {  // uniform across the wave
+                int wbase = 0;
+                if (lane == 0) wbase = atomicAdd(nlist, int(__popcll(m)));
+                wbase = __shfl(wbase, 0);
+                if (ne) list[wbase + int(__popcll(m & ((1ull << lane) - 1ull)))] = entry;
+            }
+        }
+        __syncthreads();
+        const int nl = *nlist;
+        for (int e = threadIdx.x; e < nl; e += kSlabBlock) {
+            const int entry = list[e];
+            const int i1 = entry & 127, i2 = (entry >> 7) & 127, lo = (entry >> 14) & 127, hi = entry >> 21;
+            const float u1 = float(i1) - half, u2 = float(i2) - half;
+            const float y0x = Rp[b1] * u1 + Rp[b2] * u2 + dx * u0;
+            const float y0y = Rp[3 + b1] * u1 + Rp[3 + b2] * u2 + dy * u0;
+            const float y0z = Rp[6 + b1] * u1 + Rp[6 + b2] * u2 + dzs * u0;
+            const int k0 = i1 * kstride[b1] + i2 * kstride[b2];
+            cf cnext = gload(c, k0 + lo * sax);
+            for (int ka = lo; ka <= hi; ++ka) {
+                const cf ck = cnext;
+                if (ka < hi) cnext = gload(c, k0 + (ka + 1) * sax);
+                const float fk = float(ka);
+                const float yz = y0z + fk * dzs;
+                const float ad = fabsf(zc - yz);
+                if (!(ad < 2.f)) continue;
+                const float yx = y0x + fk * dx;
+                const float yy = y0y + fk * dy;
+                float wz;
+                if (ad < 1.f) wz = 2.f / 3.f - ad * ad + 0.5f * ad * ad * ad;
+                else { const float b = 2.f - ad; wz = b * b * b * (1.f / 6.f); }
+                const float sw = wz * S;
+                const float fx = floorf(yx), fy = floorf(yy);
+                float wx[4], wy[4], xr[4], xi[4];
+                bspline3_weights(yx - fx, wx);
+                bspline3_weights(yy - fy, wy);
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    vr[4 * b + a] = fixed_rpi(xr[a] * wy[b]);
-                    vi[4 * b + a] = fixed_rpi(xi[a] * wy[b]);
+                    xr[a] = ck.re * sw * wx[a];
+                    xi[a] = ck.im * sw * wx[a];
                 }
+                int vr[16], vi[16];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        vr[4 * b + a] = fixed_rpi(xr[a] * wy[b]);
+                        vi[4 * b + a] = fixed_rpi(xi[a] * wy[b]);
+                    }
+                }
+                flush_stencil<N>(acc, int(fx) - 1, int(fy) - 1, vr, vi);
             }
-            flush_stencil<N>(acc, int(fx) - 1, int(fy) - 1, vr, vi);
         }
+        __syncthreads();  // the list is rewritten by the next chunk
     }
 }
 
@@ -473,11 +514,15 @@ x_done:
 #pragma unroll
             for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
             dft8<float, -1>(u);
+            // 32-bit element offsets from the item's slab base (a uniform pointer)
+            const unsigned col = unsigned(grouped ? col_pos<N>(x) : x);
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 const int ky = jj + NB * r;
-                const float sg = ((x + ky) & 1) ? -1.f : 1.f;
-                out[ky * N + (grouped ? col_pos<N>(x) : x)] = u[r] * sg;
+                // the (-1)^(kx + ky) of the N / 2 shift: folded into the
+                // pair-grouped spectrum, applied here otherwise (planar)
+                const cf v = (!grouped && ((x + ky) & 1)) ? mk(-u[r].re, -u[r].im) : u[r];
+                out[unsigned(ky * N) + col] = v;
                 slab[ky * RS + px(x)] = mk(0.f, 0.f);
                 if (x < N / 16) slab[ky * RS + 17 * x + 16] = mk(0.f, 0.f);  // the gap entries
             }
@@ -494,6 +539,10 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
     using Plan = typename FusedRadix<N, P>::type;
     __shared__ int acc[L::kInts];
     __shared__ cf tw[N];
+    __shared__ int list[kLineChunk];  // packed (i1, i2, lo, hi) of the lines that reach the slab
+    __shared__ int nlist;
+    static_assert(sizeof(int) * (L::kInts + kLineChunk + 1) + sizeof(cf) * N <= 160 * 1024,
+                  "one block's LDS must fit the 160 KiB of a compute unit");
     fill_twiddles<float, N>(tw);
     const int nz = planar ? 1 : N;
     const int items = nz * n_rot;
@@ -516,7 +565,7 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
             for (int i = threadIdx.x; i < L::kInts; i += kSlabBlock) acc[i] = 0;
             __syncthreads();
         }
-        spread_item<N>(acc, fr, static_cast<const cf*>(jb.c), jb.n_m, jb.scale[0], z, planar != 0);
+        spread_item<N>(acc, fr, static_cast<const cf*>(jb.c), jb.n_m, jb.scale[0], z, planar != 0, list, &nlist);
         __syncthreads();
         cf* out = slabs + (int64_t(rot) * nz + z) * N * N;
         const float inv = jb.scale[1];
@@ -1319,12 +1368,18 @@ size_t fused_workspace_bytes(const FusedPlan& fp) { return fused_layout(fp, null
 
 size_t fused_prep_scratch_bytes(int n_jobs) { return align256(sizeof(float) * kPrepBlocks * size_t(n_jobs)); }
 
+// The copy also multiplies S(k) by (-1)^(kx + ky): the slabs of these sizes
+// are spread at positions shifted by N / 2 in x and y, so their transforms
+// carry that factor, and (-1)^(kx + ky) is the same at k and -k, so the
+// product Y(k) S(k) that the pencil pass folds is unchanged.
 template <int N>
 __global__ void spec_pair_group_kernel(const cf* __restrict__ in, cf* __restrict__ out) {
     const int64_t rows = int64_t(N) * N;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < rows * N; i += int64_t(gridDim.x) * blockDim.x) {
         const int p = int(i % N);
-        out[i] = in[i - p + col_kx<N>(p)];
+        const int kx = col_kx<N>(p), ky = int((i / N) % N);
+        const cf v = in[i - p + kx];
+        out[i] = ((kx + ky) & 1) ? mk(-v.re, -v.im) : v;
     }
 }
 
