@@ -71,6 +71,8 @@ def parse():
                     help="rotations of the protein-like pair scored 64 per launch (0: skip)")
     ap.add_argument("--uneven-pairs", type=int, default=256,
                     help="pairs in the multi-pair queue figure, 512 rotations each (0: skip)")
+    ap.add_argument("--uneven-e2e", type=int, default=1,
+                    help="also run the uneven batch end to end on its own pairs with per-pair SDF builds (0: skip)")
     ap.add_argument("--phi-kernels", type=int, default=1,
                     help="compare the alternative kernels of eq. 13 on the planar and mechanical pairs (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -295,6 +297,80 @@ def phi_kernel_section(dev):
     return out
 
 
+def sdf_build_counts(ctx, part, params, build_ms):
+    """Node-sample pairs of one sdf_build, counted by the library's counting
+    variant (a separate, untimed build): pass 1 (nearest sample), pass 2
+    (kernel sum, samples of the visited tiles) and pairs inside the contact
+    ball, with their rates over the timed build."""
+    import torch
+    ctx.set_option("sdf_stats", 1)
+    ctx.sdf_build(part.samples.q, part.samples.n, part.samples.w, part.grid, params)
+    torch.cuda.synchronize()
+    c = {k: ctx.get_option("sdf_pairs_" + k) for k in ("nearest", "sum", "in_ball")}
+    ctx.set_option("sdf_stats", 0)
+    dense = float(part.samples.count) * part.grid.size
+    sec = build_ms * 1e-3
+    return {"build_ms": round(build_ms, 3), "samples": part.samples.count, "nodes": part.grid.size,
+            "pairs_nearest": c["nearest"], "pairs_sum": c["sum"], "pairs_in_ball": c["in_ball"],
+            "frac_of_dense": {k: round(v / dense, 4) for k, v in c.items()},
+            "in_ball_pairs_per_s": c["in_ball"] / sec, "sum_pairs_per_s": c["sum"] / sec,
+            "nearest_pairs_per_s": c["nearest"] / sec}
+
+
+def uneven_end_to_end(ctx, dev, n_pairs, workers):
+    """The uneven batch end to end: its own seeded pairs (sampled on the host
+    by a process pool, outside the timing), then on the GPU both SDFs of every
+    pair, the fixed spectra and one score_pairs queue of all pairs x 512
+    rotations, timed with events on the current stream."""
+    import torch
+
+    from workloads import configs as C
+    t0 = time.perf_counter()
+    pairs = C.uneven_batch(n_pairs, 512, workers)
+    gen_s = time.perf_counter() - t0
+    stream = torch.cuda.current_stream(dev)
+
+    def run(sub):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record(stream)
+        jobs = []
+        for p in sub:
+            fx, mv = p.fixed, p.moving
+            rf = ctx.sdf_build(fx.samples.q, fx.samples.n, fx.samples.w, fx.grid, p.params)
+            rm = ctx.sdf_build(mv.samples.q, mv.samples.n, mv.samples.w, mv.grid, p.params)
+            jobs.append({"spec": ctx.spectrum(rf, fx.grid), "g_fixed": fx.grid, "rho_moving": rm,
+                         "w_moving": torch.ones(rm.shape, dtype=torch.float32, device=dev), "g_moving": mv.grid,
+                         "quats": p.quats})
+            del rf
+        ev[1].record(stream)
+        ctx.score_pairs(jobs)
+        ev[2].record(stream)
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+
+    # warm-up on one pair of each grid class (workspace, autotuned plans)
+    seen, warm = set(), []
+    for p in pairs:
+        if p.n_fixed not in seen:
+            seen.add(p.n_fixed)
+            warm.append(p)
+    run(warm)
+    build_ms, search_ms = run(pairs)
+    rots = 512 * len(pairs)
+    classes = {}
+    for p in pairs:
+        k = f"{p.n_fixed}^3/{p.n_moving}^3"
+        classes[k] = classes.get(k, 0) + 1
+    return {"pairs": len(pairs), "rotations": rots, "classes": classes,
+            "samples_total": int(sum(p.fixed.samples.count + p.moving.samples.count for p in pairs)),
+            "host_sampling_s": round(gen_s, 2), "host_workers": workers,
+            "sdf_and_spectrum_ms": round(build_ms, 2), "search_ms": round(search_ms, 2),
+            "end_to_end_ms": round(build_ms + search_ms, 2),
+            "sdf_share": round(build_ms / (build_ms + search_ms), 4),
+            "search_rotations_per_s": round(rots / (search_ms * 1e-3), 1),
+            "end_to_end_rotations_per_s": round(rots / ((build_ms + search_ms) * 1e-3), 1)}
+
+
 def copy_bandwidth(dev) -> float:
     """Device-to-device copy of 1 GiB, read + write bytes per second."""
     import torch
@@ -361,7 +437,7 @@ def main():
         e3.record(stream)
         torch.cuda.synchronize()
         report["sdf_build_fixed_ms"] = e0.elapsed_time(e1)
-        report["sdf_build_fixed_pairs_per_s"] = fx.samples.count * fx.grid.size / (e0.elapsed_time(e1) * 1e-3)
+        report["sdf_build_fixed"] = sdf_build_counts(ctx, fx, pair.params, e0.elapsed_time(e1))
         report["spectrum_ms"] = e2.elapsed_time(e3)
         w = torch.ones(rho_m.shape, dtype=torch.float32, device=dev)  # h^3 = 1
         tuned = None
@@ -607,7 +683,8 @@ def main():
                                       "rotations_per_s": round(len(pp.quats) / dt, 1),
                                       "samples": [pf.samples.count, pm.samples.count],
                                       "sdf_build_ms": [round(x, 2) for x in build_ms],
-                                      "end_to_end_ms": round(sum(build_ms) + 1e3 * dt, 2)}
+                                      "end_to_end_ms": round(sum(build_ms) + 1e3 * dt, 2),
+                                      "receptor_build": sdf_build_counts(ctx, pf, pp.params, build_ms[0])}
             # --- differentiable refinement on the protein-like pair: poses from the
             # top peaks, perturbed by N(0, 2) grid units and N(0, 10 deg), then
             # gradient ascent on the score through the adjoint kernel
@@ -677,8 +754,12 @@ def main():
             total = 512 * len(jobs)
             report["uneven_batch"] = {"pairs": len(jobs), "rotations": total,
                                       "rotations_per_s": round(total / dt, 1),
-                                      "classes": ["128^3/64^3", "96^3/48^3", "64^3/32^3"]}
+                                      "classes": ["128^3/64^3", "96^3/48^3", "64^3/32^3"],
+                                      "fields": "seeded random (the work does not depend on the values)"}
             del jobs
+            if args.uneven_e2e:
+                workers = max(1, min(16, len(os.sched_getaffinity(0))))
+                report["uneven_end_to_end"] = uneven_end_to_end(ctx, dev, args.uneven_pairs, workers)
         ctx.close()
 
     line = {"metric": "rotations scored/sec at 128^3 (FP32 fused path); FP64 path and pose-gradient evals/sec "
@@ -703,11 +784,12 @@ def main():
             "correlation_stage": report["correlation_stage"],
             "slab_reach": report["slab_reach"],
             "sdf_build_fixed_ms": round(report["sdf_build_fixed_ms"], 3),
-            "sdf_build_fixed_pairs_per_s": report["sdf_build_fixed_pairs_per_s"],
+            "sdf_build_fixed": report["sdf_build_fixed"],
             "spectrum_ms": round(report["spectrum_ms"], 4),
             "protein_like": report.get("protein_like"),
             "refinement": report.get("refinement"),
             "uneven_batch": report.get("uneven_batch"),
+            "uneven_end_to_end": report.get("uneven_end_to_end"),
             "phi_kernels": report.get("phi_kernels"),
             "kernels": report["kernels"]}
     if not args.no_cpu_baseline:

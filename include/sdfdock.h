@@ -111,13 +111,24 @@ const char *sdf_last_error(sdf_ctx ctx);
  *   "radix"         FFT radix schedule of the fused kernels for N = 8, 16, 32, 96 (0, 1, 2;
  *                   e.g. 96 = 8.4.3, 3.4.8, 4.8.3); N = 64 and 128 use fixed two-pass transforms
  *   "autotune"      1: tune each grid-size class on its first search (see sdf_autotune)
+ *   "autotune_reject" bit i set: the autotuner treats its i-th candidate (in the order
+ *                   batch, then group, then schedule, as in its report) as failing the
+ *                   parity probe (for testing the failure path; default 0)
+ *   "sdf_stats"     1: sdf_build (skeletal kernel) runs a counting variant that adds its
+ *                   node-sample pairs to three counters (setting the option clears them):
+ *                   "sdf_pairs_nearest" (pass 1: valid nodes x samples of the tiles
+ *                   visited for the nearest sample), "sdf_pairs_sum" (pass 2: live nodes x
+ *                   samples of the tiles visited for the kernel sum) and "sdf_pairs_in_ball"
+ *                   (pairs inside the contact ball), read with sdf_ctx_get_option (which
+ *                   synchronises the device).  For measurement, not for timed builds.
  * With "graph" = 1 the fused launch sequence of a score_rotations call is
  * captured once and replayed while the buffers, shapes and stream stay the
  * same; the null stream cannot be captured and runs without a graph.
  * Errors: SDF_EINVAL for an unknown key or out-of-range value. */
 int sdf_ctx_set_option(sdf_ctx ctx, const char *key, int64_t value);
 /* Read an option, the device's compute-unit count "num_cu", or one of the
- * counters "graph_captures", "graph_launches". */
+ * counters "graph_captures", "graph_launches", "sdf_pairs_nearest",
+ * "sdf_pairs_sum", "sdf_pairs_in_ball". */
 int sdf_ctx_get_option(sdf_ctx ctx, const char *key, int64_t *value);
 
 /* Kernel timing.  With the option "profile" = 1 every kernel of the fused
@@ -414,6 +425,33 @@ int score_grad_coef(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
 int score_grad_fixed(sdf_ctx ctx, const sdf_grid *g_fixed, const void *rho_moving, const void *w_moving,
                      const sdf_grid *g_moving, const double *poses, int64_t B, const double *grad_scale,
                      void *grad_f, sdf_stream stream);
+
+/* Backward pass of the pose scores for automatic differentiation (the
+ * gradient-based refinement of the validation section): for an incoming
+ * gradient g_b = grad_score[b] (FP64, device) of a loss L of the scores f_b,
+ *   grad_pose[b]       = g_b d f_b / d pose_b          (FP64 B x 7, may be NULL)
+ *   grad_w[k]          = sum_b g_b Re(rho_M(x_k) Phi_b(y_kb))   (real N_M^3, may be NULL)
+ *   grad_rho_moving[k] = w_k sum_b g_b Phi_b(y_kb)     (complex N_M^3, may be NULL)
+ *   grad_rho_fixed(p)  = sum_b g_b sum_k c_k B3(p - y_kb)   (complex fixed grid, may be NULL)
+ * the last two being the cotangents of the fields, so that
+ * dL = Re sum grad_rho . d rho (torch's complex gradient is their conjugate).
+ * Each is what score_grad_coef / score_grad_fixed give, with the products
+ * by g_b and w_k taken here.  Same inputs and constraints as score_grad;
+ * rho_fixed may be NULL when only grad_rho_fixed is requested.  Outputs are
+ * overwritten.
+ * Errors: SDF_EINVAL (NULL input, no output requested), as score_grad. */
+int score_grad_backward(sdf_ctx ctx, const void *rho_fixed, const sdf_grid *g_fixed,
+                        const void *rho_moving, const void *w_moving, const sdf_grid *g_moving,
+                        const double *poses, int64_t B, const double *grad_score,
+                        double *grad_pose, void *grad_w, void *grad_rho_moving, void *grad_rho_fixed,
+                        sdf_stream stream);
+
+/* Chain rule for pose gradients kept from a forward score_grad call:
+ * grad_pose_out[b][j] = grad_pose[b][j] * grad_score[b], FP64 B x 7, device
+ * (grad_pose_out may equal grad_pose).
+ * Errors: SDF_EINVAL. */
+int score_grad_pose_chain(sdf_ctx ctx, const double *grad_pose, const double *grad_score, int64_t B,
+                          double *grad_pose_out, sdf_stream stream);
 
 /* ------------------------------------------------ nonequispaced route */
 

@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsdfdock.so")
+# SDF_LIB_PATH selects another build of the same library (the host-sanitized
+# one of the CPU tests); there is no fallback if it is missing
+LIB_PATH = os.environ.get("SDF_LIB_PATH") or os.path.join(HERE, "libsdfdock.so")
 
 SDF_OK, SDF_EINVAL, SDF_EUNSUPPORTED, SDF_EHIP, SDF_ENOMEM = 0, -1, -2, -3, -4
 SDF_F32, SDF_F64 = 0, 1
@@ -18,7 +20,8 @@ EXPORTS = ["sdf_ctx_create", "sdf_ctx_destroy", "sdf_last_error", "sdf_ctx_set_o
            "sdf_ctx_stats", "sdf_ctx_stats_reset",
            "sdf_build", "sdf_build_phi", "sdf_spectrum", "score_rotations", "score_pairs", "sdf_autotune", "score_volume",
            "sdf_spread", "sdf_fft", "sdf_topk", "score_grad", "score_rotations_direct", "sdf_build_adjoint",
-           "score_grad_noalloc", "score_grad_coef", "score_grad_fixed", "octree_samples", "score_rotations_nfft", "score_volume_nfft"]
+           "score_grad_noalloc", "score_grad_coef", "score_grad_fixed", "score_grad_backward",
+           "score_grad_pose_chain", "octree_samples", "score_rotations_nfft", "score_volume_nfft"]
 
 
 class SdfGrid(ctypes.Structure):
@@ -87,6 +90,8 @@ def load() -> ctypes.CDLL:
         "score_grad_noalloc": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "score_grad_coef": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp, vp], ctypes.c_int),
         "score_grad_fixed": ([vp, gp, vp, vp, gp, vp, i64, vp, vp, vp], ctypes.c_int),
+        "score_grad_backward": ([vp, vp, gp, vp, vp, gp, vp, i64, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+        "score_grad_pose_chain": ([vp, vp, vp, i64, vp, vp], ctypes.c_int),
         "octree_samples": ([vp, vp, vp, gp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp, vp], ctypes.c_int),
         "score_rotations_nfft": ([vp, vp, gp, vp, vp, i64, ctypes.c_int, vp, i64, vp, vp, vp, vp, vp],
                                  ctypes.c_int),

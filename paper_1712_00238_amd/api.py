@@ -340,6 +340,39 @@ class Context:
                                              _ptr(gw), _ptr(gs), _stream(self.device)))
         return score, gp, gc, gw
 
+    def score_grad_backward(self, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, grad_score,
+                            want_pose=True, want_w=False, want_rho=False, want_fixed=False):
+        """Backward of the scores for an incoming gradient grad_score (B,):
+        (grad_pose (B, 7) FP64, grad_w, grad_rho_moving (cotangent w_k sum_b
+        g_b Phi_b), grad_rho_fixed (cotangent of the fixed field)), each None
+        unless asked for."""
+        poses = self._dev(poses, torch.float64).reshape(-1, 7)
+        B = poses.shape[0]
+        rm = self._dev(rho_moving, self.cplx)
+        wm = self._dev(w_moving, self.real)
+        gs = self._dev(grad_score, torch.float64)
+        side = want_pose or want_w or want_rho
+        rf = self._dev(rho_fixed, self.cplx) if side else None
+        gp = torch.empty((B, 7), dtype=torch.float64, device=self.device) if want_pose else None
+        gw = torch.empty(wm.shape, dtype=self.real, device=self.device) if want_w else None
+        gr = torch.empty(rm.shape, dtype=self.cplx, device=self.device) if want_rho else None
+        nx, ny, nz = g_fixed.n
+        gf = torch.empty((nz, ny, nx), dtype=self.cplx, device=self.device) if want_fixed else None
+        g1, g2 = _lib.make_grid(g_fixed), _lib.make_grid(g_moving)
+        self._check(self.lib.score_grad_backward(self.handle, _ptr(rf), ctypes.byref(g1), _ptr(rm), _ptr(wm),
+                                                 ctypes.byref(g2), _ptr(poses), B, _ptr(gs), _ptr(gp), _ptr(gw),
+                                                 _ptr(gr), _ptr(gf), _stream(self.device)))
+        return gp, gw, gr, gf
+
+    def score_grad_pose_chain(self, grad_pose, grad_score):
+        """grad_pose[b] * grad_score[b] (FP64, (B, 7)), computed in the library."""
+        gp = self._dev(grad_pose, torch.float64).reshape(-1, 7)
+        gs = self._dev(grad_score, torch.float64)
+        out = torch.empty_like(gp)
+        self._check(self.lib.score_grad_pose_chain(self.handle, _ptr(gp), _ptr(gs), gp.shape[0], _ptr(out),
+                                                   _stream(self.device)))
+        return out
+
     def score_grad_fixed(self, g_fixed, rho_moving, w_moving, g_moving, poses, grad_scale=None):
         """Cotangent of sum_b s_b f_b with respect to rho_F: the periodic
         spread sum_b s_b sum_k c_k B3(p - y_kb), complex, shaped like the fixed

@@ -2,15 +2,14 @@
 
 SDFScore: forward(poses, w, rho_moving) -> scores.  When the poses need a
 gradient and nothing else does (pose refinement), forward runs the
-value-and-gradient kernel once and keeps the B x 7 pose derivatives (FP64)
-for backward, which only scales them by the incoming gradient.  When the
-weights or the moving field need a gradient, backward re-runs the kernel with
-the incoming gradient as per-pose scale and takes the cotangent of the moving
-coefficients c_k = w_k rho_M(x_k), G_k = sum_b g_b Phi_b(y_k): then
-d(loss)/d(w_k) = Re(rho_M(x_k) G_k) and the moving field's cotangent is
-w_k G_k.  The fixed field's cotangent is the spread sum_b g_b sum_k c_k
-B3(p - y_kb) (score_grad_fixed).  The B-spline stencils are recomputed in every call; no spread grid
-is stored.
+value-and-gradient kernel once and keeps the B x 7 pose derivatives (FP64);
+backward scales them by the incoming gradient in the library
+(score_grad_pose_chain).  Otherwise backward calls score_grad_backward, which
+re-runs the kernel with the incoming gradient g_b as per-pose scale and
+returns the scaled pose gradient, d(loss)/d(w_k) = Re(rho_M(x_k) G_k) with
+G_k = sum_b g_b Phi_b(y_k), the moving field's cotangent w_k G_k and the
+fixed field's cotangent sum_b g_b sum_k c_k B3(p - y_kb).  The B-spline
+stencils are recomputed in every call; no spread grid is stored.
 
 SDFBuild: forward(q, n, w) -> rho (sdf_build); backward through
 sdf_build_adjoint, giving shape gradients with respect to the boundary
@@ -40,25 +39,27 @@ class SDFScore(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, grad_score):
+        # every product of the chain rule runs in the library; this only routes
+        # tensors and converts complex cotangents to torch's conjugate convention
         poses, w, rho_moving = ctx.saved_tensors
         gs = grad_score.detach().to(torch.float64).contiguous()
-        want_w, want_rho = bool(ctx.needs_input_grad[1]), bool(ctx.needs_input_grad[5])
-        want_fixed = bool(ctx.needs_input_grad[3])
+        want_pose, want_w = bool(ctx.needs_input_grad[0]), bool(ctx.needs_input_grad[1])
+        want_fixed, want_rho = bool(ctx.needs_input_grad[3]), bool(ctx.needs_input_grad[5])
         sctx, rho_fixed, g_fixed, g_moving = ctx.aux
-        grad_fixed = None
-        if want_fixed:
-            grad_fixed = torch.conj(sctx.score_grad_fixed(g_fixed, rho_moving.detach(), w.detach(), g_moving,
-                                                          poses.detach(), grad_scale=gs))
-        if ctx.gp is not None and not (want_w or want_rho):
-            return ctx.gp * gs[:, None], None, None, grad_fixed, None, None, None
-        want_pose = bool(ctx.needs_input_grad[0])
-        if not (want_pose or want_w or want_rho):
-            return None, None, None, grad_fixed, None, None, None
-        _, gp, gc, gw = sctx.score_grad_coef(rho_fixed, g_fixed, rho_moving.detach(), w.detach(), g_moving,
-                                             poses.detach(), want_pose=want_pose, want_w=want_w, grad_scale=gs)
-        grad_poses = gp * gs[:, None] if want_pose else None
-        grad_rho = torch.conj(w.detach().to(gc.real.dtype) * gc) if want_rho else None
-        return grad_poses, (gw if want_w else None), None, grad_fixed, None, grad_rho, None
+        grad_poses = None
+        if want_pose and ctx.gp is not None:
+            grad_poses = sctx.score_grad_pose_chain(ctx.gp, gs)
+        pose_here = want_pose and ctx.gp is None
+        gw = grad_rho = grad_fixed = None
+        if pose_here or want_w or want_rho or want_fixed:
+            gp, gw, gr, gf = sctx.score_grad_backward(rho_fixed.detach(), g_fixed, rho_moving.detach(), w.detach(),
+                                                      g_moving, poses.detach(), gs, want_pose=pose_here,
+                                                      want_w=want_w, want_rho=want_rho, want_fixed=want_fixed)
+            if pose_here:
+                grad_poses = gp
+            grad_rho = torch.conj(gr) if want_rho else None
+            grad_fixed = torch.conj(gf) if want_fixed else None
+        return grad_poses, gw, None, grad_fixed, None, grad_rho, None
 
 
 def sdf_score(poses, w, sctx, rho_fixed, g_fixed, rho_moving, g_moving):

@@ -71,6 +71,44 @@ def build(jobs: int = 6, debug: bool = False, force: bool = False) -> str:
     return LIB
 
 
+SAN_LIB = os.path.join(BUILD, "libsdfdock_hostsan.so")
+
+
+def sanitizer_runtime() -> str:
+    """The shared AddressSanitizer runtime of the ROCm clang (to preload into a
+    process that loads the sanitized library)."""
+    import glob
+    hits = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not hits:
+        raise RuntimeError("clang AddressSanitizer runtime not found")
+    return hits[-1]
+
+
+def build_host_sanitized() -> str:
+    """The ABI layer (abi.cpp) with AddressSanitizer and UndefinedBehavior-
+    Sanitizer on its host code only (-Xarch_host: device code is not
+    instrumented), linked with the kernel objects of the normal build, into
+    _build/libsdfdock_hostsan.so.  For the CPU-side argument-validation tests;
+    build() must have run first."""
+    objs = [os.path.join(BUILD, os.path.splitext(f)[0] + ".o") for f in SOURCES if f != "abi.cpp"]
+    if not all(os.path.exists(o) for o in objs):
+        raise RuntimeError("kernel objects missing: run build() first")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+    abi_o = os.path.join(BUILD, "abi_hostsan.o")
+    cmd = [hipcc()] + flags() + san + ["-x", "hip", "-c", os.path.join(CSRC, "abi.cpp"), "-o", abi_o]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: abi.cpp (sanitized)\n{r.stderr}")
+    clang = os.path.join(os.path.dirname(hipcc()), "..", "llvm", "bin", "clang++")
+    link = [clang, "-shared", "-fPIC", "-fsanitize=address,undefined", abi_o] + objs + \
+        ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", SAN_LIB]
+    r = subprocess.run(link, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed (sanitized)\n{' '.join(link)}\n{r.stderr}")
+    return SAN_LIB
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=6)

@@ -90,6 +90,7 @@ struct sdf_ctx_s {
     int64_t opt_profile = 0;
     int64_t opt_radix = 0;
     int64_t opt_autotune = 0;
+    int64_t opt_autotune_reject = 0;  // candidates the autotuner must treat as failing its probe
     int num_cu = 256;
     std::map<uint64_t, Tuned> tuned;
     std::string last_report;
@@ -101,6 +102,9 @@ struct sdf_ctx_s {
     Profiler prof;
     int64_t graph_captures = 0;
     int64_t graph_launches = 0;
+    // "sdf_stats": sdf_build counts its node-sample pairs into stats_dev
+    int64_t opt_sdf_stats = 0;
+    unsigned long long* stats_dev = nullptr;
     // device address of this device's copy of `scratch` (score_grad_noalloc)
     void* scratch_ptr = nullptr;
     std::string scratch_err;
@@ -678,6 +682,7 @@ int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std:
     std::string rep = "{\"N\": " + std::to_string(N) + ", \"n_m\": " + std::to_string(n_m) +
                       ", \"planar\": " + (planar ? "true" : "false") + ", \"candidates\": [";
     bool first = true;
+    int cand = 0;
     for (int batch : {32, 64, 128, 256}) {
         for (int group : {2, 4}) {
             // N = 64 and 128 use fixed two-pass transforms: the schedule does not apply
@@ -697,6 +702,8 @@ int autotune_class(sdf_ctx ctx, int N, bool planar, int n_m, hipStream_t s, std:
                     for (int r = 0; ok && r < n_probe; ++r)
                         ok = std::fabs(s_got[r] - s_ref[r]) <= 1e-4f * smax + 1e-30f;
                 }
+                if ((ctx->opt_autotune_reject >> cand) & 1) ok = false;
+                ++cand;
                 float ms = -1.f;
                 if (ok) {
                     (void)hipEventRecord(e0, s);
@@ -898,7 +905,12 @@ extern "C" {
 int sdf_ctx_create(sdf_ctx* out, int device, sdf_dtype dtype, size_t workspace_cap_bytes) {
     if (!out) return fail(nullptr, SDF_EINVAL, "out is NULL");
     *out = nullptr;
-    if (dtype != SDF_F32 && dtype != SDF_F64) return fail(nullptr, SDF_EINVAL, "unknown dtype");
+    // a C caller may pass any int: read its bytes rather than the enum value,
+    // which C++ does not define outside the enumerators' range
+    int dt = 0;
+    static_assert(sizeof(dtype) == sizeof(int), "sdf_dtype is int-sized");
+    std::memcpy(&dt, &dtype, sizeof(int));
+    if (dt != SDF_F32 && dt != SDF_F64) return fail(nullptr, SDF_EINVAL, "unknown dtype");
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || device < 0 || device >= count) {
@@ -925,6 +937,7 @@ void sdf_ctx_destroy(sdf_ctx ctx) {
     ctx->prof.release();
     drop_graph(ctx);
     if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->stats_dev) (void)hipFree(ctx->stats_dev);
     delete ctx;
 }
 
@@ -956,6 +969,16 @@ int sdf_ctx_set_option(sdf_ctx ctx, const char* key, int64_t value) {
     } else if (!std::strcmp(key, "autotune")) {
         if (value != 0 && value != 1) return fail(ctx, SDF_EINVAL, "autotune must be 0 or 1");
         ctx->opt_autotune = value;
+    } else if (!std::strcmp(key, "autotune_reject")) {
+        if (value < 0 || value >= (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "autotune_reject: 24-bit mask");
+        ctx->opt_autotune_reject = value;
+    } else if (!std::strcmp(key, "sdf_stats")) {
+        if (value != 0 && value != 1) return fail(ctx, SDF_EINVAL, "sdf_stats must be 0 or 1");
+        ctx->opt_sdf_stats = value;
+        if (ctx->stats_dev) {
+            DeviceGuard dg(ctx->device);
+            SDF_TRY_HIP(ctx, hipMemset(ctx->stats_dev, 0, 3 * sizeof(unsigned long long)), "statistics counters");
+        }
     } else {
         return fail(ctx, SDF_EINVAL, std::string("unknown option ") + key);
     }
@@ -974,7 +997,17 @@ int sdf_ctx_get_option(sdf_ctx ctx, const char* key, int64_t* value) {
     else if (!std::strcmp(key, "num_cu")) *value = ctx->num_cu;
     else if (!std::strcmp(key, "graph_captures")) *value = ctx->graph_captures;
     else if (!std::strcmp(key, "graph_launches")) *value = ctx->graph_launches;
-    else return fail(ctx, SDF_EINVAL, std::string("unknown option ") + key);
+    else if (!std::strcmp(key, "sdf_stats")) *value = ctx->opt_sdf_stats;
+    else if (!std::strcmp(key, "autotune_reject")) *value = ctx->opt_autotune_reject;
+    else if (!std::strcmp(key, "sdf_pairs_nearest") || !std::strcmp(key, "sdf_pairs_sum") ||
+             !std::strcmp(key, "sdf_pairs_in_ball")) {
+        unsigned long long c[3] = {0, 0, 0};
+        if (ctx->stats_dev) {
+            DeviceGuard dg(ctx->device);
+            SDF_TRY_HIP(ctx, hipMemcpy(c, ctx->stats_dev, sizeof(c), hipMemcpyDeviceToHost), "statistics counters");
+        }
+        *value = int64_t(c[key[10] == 'n' ? 0 : (key[10] == 's' ? 1 : 2)]);
+    } else return fail(ctx, SDF_EINVAL, std::string("unknown option ") + key);
     return SDF_OK;
 }
 
@@ -1024,9 +1057,19 @@ static int sdf_build_impl(sdf_ctx ctx, const void* q, const void* nrm, const voi
     ctx->fused_cache_valid = false;  // the Morton-ordered samples share the workspace
     rc = ensure_ws(ctx, sdf::sdf_build_workspace_bytes(n, kind));
     if (rc) return rc;
+    unsigned long long* stats = nullptr;
+    if (ctx->opt_sdf_stats && kind == SDF_PHI_SKELETAL) {
+        if (!ctx->stats_dev) {
+            SDF_TRY_HIP(ctx, hipMalloc(reinterpret_cast<void**>(&ctx->stats_dev), 3 * sizeof(unsigned long long)),
+                        "statistics counters");
+            SDF_TRY_HIP(ctx, hipMemsetAsync(ctx->stats_dev, 0, 3 * sizeof(unsigned long long), s),
+                        "statistics counters");
+        }
+        stats = ctx->stats_dev;
+    }
     hipError_t e = ctx->dtype == SDF_F64
-                       ? sdf::launch_sdf_build<double>(qd, nd, wd, n, desc(g), pd, kind, rho_out, ctx->ws, s)
-                       : sdf::launch_sdf_build<float>(qd, nd, wd, n, desc(g), pd, kind, rho_out, ctx->ws, s);
+                       ? sdf::launch_sdf_build<double>(qd, nd, wd, n, desc(g), pd, kind, rho_out, ctx->ws, s, stats)
+                       : sdf::launch_sdf_build<float>(qd, nd, wd, n, desc(g), pd, kind, rho_out, ctx->ws, s, stats);
     if (e != hipSuccess) return hip_fail(ctx, e, "sdf_build");
     return SDF_OK;
 }
@@ -1348,6 +1391,87 @@ int score_grad_coef(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed,
     if (!grad_c) return fail(ctx, SDF_EINVAL, "grad_c is NULL");
     return score_grad_impl(ctx, rho_fixed, g_fixed, rho_moving, w_moving, g_moving, poses, B, score, grad_pose,
                            grad_w, grad_c, grad_scale, stream);
+}
+
+int score_grad_backward(sdf_ctx ctx, const void* rho_fixed, const sdf_grid* g_fixed, const void* rho_moving,
+                        const void* w_moving, const sdf_grid* g_moving, const double* poses, int64_t B,
+                        const double* grad_score, double* grad_pose, void* grad_w, void* grad_rho_moving,
+                        void* grad_rho_fixed, sdf_stream stream) {
+    const bool moving_side = grad_pose || grad_w || grad_rho_moving;
+    if (!rho_moving || !w_moving || !poses || !grad_score || (moving_side && !rho_fixed))
+        return fail(ctx, SDF_EINVAL, "NULL array");
+    if (!moving_side && !grad_rho_fixed) return fail(ctx, SDF_EINVAL, "no output requested");
+    if (B <= 0) return fail(ctx, SDF_EINVAL, "B must be > 0");
+    if (B > (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "B too large");
+    int rc = check_pair(ctx, g_fixed, g_moving, false);
+    if (rc) return rc;
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(ctx, SDF_EHIP, "cannot select device");
+    ctx->fused_cache_valid = false;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool planar = g_fixed->n[2] == 1;
+    const int N = g_fixed->n[0], nm = g_moving->n[0];
+    const int64_t K = gsize(g_moving);
+    const size_t el = esize(ctx);
+    const int wmode = grad_rho_moving ? 2 : (grad_w ? 1 : 0);
+    const size_t gws = ctx->dtype == SDF_F64 ? sdf::grad_workspace_bytes<double>(B, N, nm, planar, wmode)
+                                             : sdf::grad_workspace_bytes<float>(B, N, nm, planar, wmode);
+    // workspace: the gradient kernels' scratch, the per-pose scores (not
+    // returned), the moving coefficients' cotangent; the fixed cotangent's
+    // pose table reuses the front once those kernels are done (stream order)
+    Carve cv{nullptr};
+    cv.take(gws);
+    cv.take(el * size_t(B));
+    cv.take(2 * el * size_t(K));
+    const size_t need = std::max(cv.off, sizeof(double) * 12 * size_t(B) + 256);
+    rc = ensure_ws(ctx, need);
+    if (rc) return rc;
+    Carve c2{static_cast<char*>(ctx->ws)};
+    void* gw_ws = c2.take(gws);
+    void* score_ws = c2.take(el * size_t(B));
+    void* gc = c2.take(2 * el * size_t(K));
+    hipError_t e = hipSuccess;
+    if (moving_side) {
+        void* gcp = grad_rho_moving ? gc : nullptr;
+        if (ctx->dtype == SDF_F64)
+            e = sdf::launch_score_grad<double>(rho_fixed, N, planar, rho_moving, static_cast<const double*>(w_moving),
+                                               nm, poses, B, static_cast<double*>(score_ws), grad_pose,
+                                               static_cast<double*>(grad_w), static_cast<double*>(gcp), grad_score,
+                                               gw_ws, s);
+        else
+            e = sdf::launch_score_grad<float>(rho_fixed, N, planar, rho_moving, static_cast<const float*>(w_moving), nm,
+                                              poses, B, static_cast<float*>(score_ws), grad_pose,
+                                              static_cast<float*>(grad_w), static_cast<float*>(gcp), grad_score,
+                                              gw_ws, s);
+        if (e == hipSuccess && grad_pose) e = sdf::launch_pose_chain(grad_pose, grad_score, B, grad_pose, s);
+        if (e == hipSuccess && grad_rho_moving)
+            e = ctx->dtype == SDF_F64
+                    ? sdf::launch_rho_from_c<double>(static_cast<const double*>(w_moving), gc, K, grad_rho_moving, s)
+                    : sdf::launch_rho_from_c<float>(static_cast<const float*>(w_moving), gc, K, grad_rho_moving, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "score_grad_backward");
+    }
+    if (grad_rho_fixed) {
+        e = ctx->dtype == SDF_F64
+                ? sdf::launch_fixed_cotangent<double>(rho_moving, static_cast<const double*>(w_moving), nm, planar, N,
+                                                      poses, B, grad_score, grad_rho_fixed, ctx->ws, s)
+                : sdf::launch_fixed_cotangent<float>(rho_moving, static_cast<const float*>(w_moving), nm, planar, N,
+                                                     poses, B, grad_score, grad_rho_fixed, ctx->ws, s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "score_grad_backward");
+    }
+    return SDF_OK;
+}
+
+int score_grad_pose_chain(sdf_ctx ctx, const double* grad_pose, const double* grad_score, int64_t B,
+                          double* grad_pose_out, sdf_stream stream) {
+    if (!grad_pose || !grad_score || !grad_pose_out) return fail(ctx, SDF_EINVAL, "NULL array");
+    if (B <= 0 || B > (int64_t(1) << 24)) return fail(ctx, SDF_EINVAL, "B must be in [1, 2^24]");
+    if (!ctx) return fail(nullptr, SDF_EINVAL, "ctx is NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(ctx, SDF_EHIP, "cannot select device");
+    hipError_t e = sdf::launch_pose_chain(grad_pose, grad_score, B, grad_pose_out, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(ctx, e, "score_grad_pose_chain");
+    return SDF_OK;
 }
 
 int score_grad_fixed(sdf_ctx ctx, const sdf_grid* g_fixed, const void* rho_moving, const void* w_moving,

@@ -547,6 +547,33 @@ __global__ void w_from_c_kernel(const cplx<T>* __restrict__ rho_m, const T* __re
     grad_w[k] = rho_m[k].re * grad_c[2 * k] - rho_m[k].im * grad_c[2 * k + 1];
 }
 
+// ---- chain-rule products for automatic differentiation
+// out[b][j] = gp[b][j] * s[b] (FP64; may be in place)
+__global__ void pose_chain_kernel(const double* __restrict__ gp, const double* __restrict__ s, int64_t B,
+                                  double* __restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= 7 * B) return;
+    out[i] = gp[i] * s[i / 7];
+}
+
+// cotangent of rho_M from that of c_k = w_k rho_M(x_k): w_k G_k (complex)
+template <typename T>
+__global__ void rho_from_c_kernel(const T* __restrict__ w_m, const T* __restrict__ grad_c, int64_t K,
+                                  T* __restrict__ grad_rho) {
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= K) return;
+    grad_rho[2 * k] = w_m[k] * grad_c[2 * k];
+    grad_rho[2 * k + 1] = w_m[k] * grad_c[2 * k + 1];
+}
+
+// zero `count` values of type T (a kernel rather than hipMemsetAsync, so that
+// the calls stay valid inside captured graphs)
+template <typename T>
+__global__ void zero_fill_kernel(T* __restrict__ p, int64_t count) {
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += int64_t(gridDim.x) * blockDim.x)
+        p[i] = T(0);
+}
+
 // ---- cotangent of the scores with respect to rho_F (the adjoint of the
 // gather): G(p) = sum_b s_b sum_k c_k B3(p - y_kb), periodic, y_kb = R_b x_k + t_b.
 // Per pose: R (FP64) and t split into floor and fraction, so that positions
@@ -712,7 +739,9 @@ hipError_t launch_fixed_cotangent(const void* rho_m, const T* w_m, int n_m, bool
                                   int64_t B, const double* grad_scale, void* grad_f, void* ws, hipStream_t s) {
     const int64_t K = planar ? int64_t(n_m) * n_m : int64_t(n_m) * n_m * n_m;
     const int64_t G = planar ? int64_t(N) * N : int64_t(N) * N * N;
-    hipError_t e = hipMemsetAsync(grad_f, 0, 2 * sizeof(T) * size_t(G), s);
+    hipLaunchKernelGGL(zero_fill_kernel<T>, dim3(unsigned(std::min<int64_t>((2 * G + 255) / 256, 4096))), dim3(256), 0,
+                       s, static_cast<T*>(grad_f), 2 * G);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     double* pr = static_cast<double*>(ws);
     hipLaunchKernelGGL(fixed_pose_kernel, dim3(unsigned((B + 127) / 128)), dim3(128), 0, s, poses, B, pr);
@@ -721,6 +750,26 @@ hipError_t launch_fixed_cotangent(const void* rho_m, const T* w_m, int n_m, bool
         hipLaunchKernelGGL(fixed_cot_kernel<T>, grid, dim3(256), 0, s, static_cast<const cplx<T>*>(rho_m), w_m, n_m,
                            planar ? 1 : 0, pr, grad_scale, B, int(b0), N, static_cast<T*>(grad_f));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_chain(const double* gp, const double* scale, int64_t B, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(pose_chain_kernel, dim3(unsigned((7 * B + 255) / 256)), dim3(256), 0, s, gp, scale, B, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_rho_from_c(const T* w_m, const void* grad_c, int64_t K, void* grad_rho, hipStream_t s) {
+    hipLaunchKernelGGL(rho_from_c_kernel<T>, dim3(unsigned((K + 255) / 256)), dim3(256), 0, s, w_m,
+                       static_cast<const T*>(grad_c), K, static_cast<T*>(grad_rho));
+    return hipGetLastError();
+}
+template hipError_t launch_rho_from_c<float>(const float*, const void*, int64_t, void*, hipStream_t);
+template hipError_t launch_rho_from_c<double>(const double*, const void*, int64_t, void*, hipStream_t);
+
+hipError_t launch_zero_f64(double* p, int64_t count, hipStream_t s) {
+    hipLaunchKernelGGL(zero_fill_kernel<double>, dim3(unsigned(std::min<int64_t>((count + 255) / 256, 4096))),
+                       dim3(256), 0, s, p, count);
     return hipGetLastError();
 }
 

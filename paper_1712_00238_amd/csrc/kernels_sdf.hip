@@ -128,7 +128,7 @@ __device__ __forceinline__ double block_reduce(double v, double* red) {
 // thread of the block calls it.
 __device__ __forceinline__ void nearest_pass(const SampleTiles& st, int64_t ns, const double bl[3], const double bh[3],
                                              double px, double py, double pz, v4<double>* sq, int* sidx, int* tflag,
-                                             double* red, double& best, int& jbest) {
+                                             double* red, double& best, int& jbest, int64_t* visited = nullptr) {
     double u2 = INFINITY;
     for (int64_t t = threadIdx.x; t < st.ntile; t += kSdfBlock) u2 = fmin(u2, box_dmax2(bl, bh, st.box + 6 * t));
     u2 = block_reduce<false>(u2, red) * (1.0 + 1e-9);
@@ -144,6 +144,7 @@ __device__ __forceinline__ void nearest_pass(const SampleTiles& st, int64_t ns, 
             if (!tflag[kk]) continue;  // uniform across the block
             const int64_t t0 = (c0 + kk) * kSdfTile;
             const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+            if (visited) *visited += cnt;
             __syncthreads();
             for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
                 const int64_t s = t0 + a;
@@ -170,11 +171,16 @@ __device__ __forceinline__ void nearest_pass(const SampleTiles& st, int64_t ns, 
 // inverse-square (eq. 15 with the medial Gaussian at its peak: the pair
 // term without the exponential), or the double skin layer of eq. 3a, which
 // needs only the signed distance of pass 1.
-template <typename T, int PHI>
+// STATS (measurement builds only): the block adds to stats[0..2] the
+// node-sample pairs of pass 1 (valid nodes x samples of the visited tiles),
+// of pass 2 (live nodes x samples of the visited tiles) and the pass-2 pairs
+// inside the contact ball.
+template <typename T, int PHI, bool STATS = false>
 __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __restrict__ q,
                                                               const double* __restrict__ nrm, SampleTiles st,
                                                               int64_t ns, GridDesc g, ParamDesc prm,
-                                                              cplx<T>* __restrict__ out) {
+                                                              cplx<T>* __restrict__ out,
+                                                              unsigned long long* __restrict__ stats = nullptr) {
     __shared__ v4<double> sq[2 * kSdfTile];  // pass 1: (qx, qy, qz, -); pass 2: reused as two T tiles
     __shared__ int sidx[kSdfTile];           // pass 1: original index; pass 2: Morton index
     __shared__ int tflag[kSdfBlock];         // tiles of the current chunk that the brick visits
@@ -201,7 +207,8 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
     // ---- pass 1 (FP64): nearest sample, lowest original index on exact ties
     double best;
     int jbest;
-    nearest_pass(st, ns, bl, bh, px, py, pz, sq, sidx, tflag, red, best, jbest);
+    int64_t vis1 = 0, vis2 = 0, inball = 0;
+    nearest_pass(st, ns, bl, bh, px, py, pz, sq, sidx, tflag, red, best, jbest, STATS ? &vis1 : nullptr);
     const int64_t jb = jbest;
     const double dot = (px - q[3 * jb]) * nrm[3 * jb] + (py - q[3 * jb + 1]) * nrm[3 * jb + 1] +
                        (pz - q[3 * jb + 2]) * nrm[3 * jb + 2];
@@ -246,6 +253,7 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                 if (!tflag[kk]) continue;  // uniform across the block
                 const int64_t t0 = (c0 + kk) * kSdfTile;
                 const int cnt = int(ns - t0 < kSdfTile ? ns - t0 : kSdfTile);
+                if (STATS && live) vis2 += cnt;
                 __syncthreads();
                 for (int a = threadIdx.x; a < cnt; a += kSdfBlock) {
                     const int64_t s = t0 + a;
@@ -268,6 +276,7 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                             in = ex * ex + ey * ey + ez * ez <= r2max64;
                         }
                         if (in) {
+                            if (STATS) ++inball;
                             const v4<T> nv = sn2[a];
                             const T inv_eta = fast_rsqrt(d2);
                             const T eta = d2 * inv_eta;
@@ -287,6 +296,17 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                     }
                 }
             }
+        }
+    }
+    if constexpr (STATS) {
+        // every thread walked the block's tiles: its pass-1 pairs are vis1
+        // when its node is valid, its pass-2 pairs vis2 when live
+        unsigned long long c[3] = {valid ? (unsigned long long)vis1 : 0ull, (unsigned long long)vis2,
+                                   (unsigned long long)inball};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            for (int off = 32; off > 0; off >>= 1) c[a] += __shfl_xor(c[a], off);
+            if ((threadIdx.x & 63) == 0) atomicAdd(stats + a, c[a]);
         }
     }
     if (valid) {
@@ -740,7 +760,8 @@ size_t sdf_build_workspace_bytes(int64_t ns, int phi) {
 
 template <typename T>
 hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
-                            const ParamDesc& p, int phi, void* rho_out, void* ws, hipStream_t s) {
+                            const ParamDesc& p, int phi, void* rho_out, void* ws, hipStream_t s,
+                            unsigned long long* stats) {
     SampleTiles st{};
     const dim3 grid(unsigned(brick_count(g))), block(kSdfBlock);
     auto* out = static_cast<cplx<T>*>(rho_out);
@@ -758,6 +779,11 @@ hipError_t launch_sdf_build(const double* q, const double* n, const double* w, i
     }
     hipError_t e = prepare_tiles(q, n, w, ns, g, ws, s, &st);
     if (e != hipSuccess) return e;
+    if (stats) {
+        hipLaunchKernelGGL((sdf_build_kernel<T, kPhiSkeletal, true>), grid, block, 0, s, q, n, st, ns, g, p, out,
+                           stats);
+        return hipGetLastError();
+    }
     if (phi == kPhiDsl)
         hipLaunchKernelGGL((sdf_build_kernel<T, kPhiDsl>), grid, block, 0, s, q, n, st, ns, g, p, out);
     else if (phi == kPhiInverseSquare)
@@ -771,9 +797,10 @@ template <typename T>
 hipError_t launch_sdf_adjoint(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
                               const ParamDesc& p, const void* cot, double* grad_q, double* grad_n, double* grad_w,
                               void* ws, hipStream_t s) {
-    hipError_t e = hipMemsetAsync(grad_q, 0, sizeof(double) * 3 * size_t(ns), s);
-    if (e == hipSuccess) e = hipMemsetAsync(grad_n, 0, sizeof(double) * 3 * size_t(ns), s);
-    if (e == hipSuccess) e = hipMemsetAsync(grad_w, 0, sizeof(double) * size_t(ns), s);
+    // zeroed by a kernel, not hipMemsetAsync, so the call can be captured in a graph
+    hipError_t e = launch_zero_f64(grad_q, 3 * ns, s);
+    if (e == hipSuccess) e = launch_zero_f64(grad_n, 3 * ns, s);
+    if (e == hipSuccess) e = launch_zero_f64(grad_w, ns, s);
     if (e != hipSuccess) return e;
     SampleTiles st{};
     e = prepare_tiles(q, n, w, ns, g, ws, s, &st);
@@ -790,8 +817,8 @@ template hipError_t launch_sdf_adjoint<double>(const double*, const double*, con
                                                const GridDesc&, const ParamDesc&, const void*, double*, double*,
                                                double*, void*, hipStream_t);
 template hipError_t launch_sdf_build<float>(const double*, const double*, const double*, int64_t, const GridDesc&,
-                                            const ParamDesc&, int, void*, void*, hipStream_t);
+                                            const ParamDesc&, int, void*, void*, hipStream_t, unsigned long long*);
 template hipError_t launch_sdf_build<double>(const double*, const double*, const double*, int64_t, const GridDesc&,
-                                             const ParamDesc&, int, void*, void*, hipStream_t);
+                                             const ParamDesc&, int, void*, void*, hipStream_t, unsigned long long*);
 
 }  // namespace sdf

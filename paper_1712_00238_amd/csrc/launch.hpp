@@ -23,9 +23,12 @@ constexpr int kPhiSkeletal = 0, kPhiInverseSquare = 1, kPhiRadial = 2, kPhiDsl =
 
 // ---- skeletal density (sdf_build): FP64 samples, output in T
 size_t sdf_build_workspace_bytes(int64_t ns, int phi = kPhiSkeletal);
+// stats (may be null; skeletal kernel only): three device counters that the
+// build adds its pass-1 pairs, pass-2 pairs and in-ball pairs to
 template <typename T>
 hipError_t launch_sdf_build(const double* q, const double* n, const double* w, int64_t ns, const GridDesc& g,
-                            const ParamDesc& p, int phi, void* rho_out, void* ws, hipStream_t s);
+                            const ParamDesc& p, int phi, void* rho_out, void* ws, hipStream_t s,
+                            unsigned long long* stats = nullptr);
 // adjoint of sdf_build: gradients (FP64, zeroed here) of Re sum_p cot(p) rho(p)
 // with respect to the sample positions, normals and weights
 template <typename T>
@@ -183,6 +186,13 @@ size_t grad_workspace_bytes(int64_t B, int N, int n_m, bool planar, int wmode);
 template <typename T>
 hipError_t launch_fixed_cotangent(const void* rho_m, const T* w_m, int n_m, bool planar, int N, const double* poses,
                                   int64_t B, const double* grad_scale, void* grad_f, void* ws, hipStream_t s);
+// out[b][j] = gp[b][j] * scale[b], FP64 B x 7 (may be in place)
+hipError_t launch_pose_chain(const double* gp, const double* scale, int64_t B, double* out, hipStream_t s);
+// grad_rho[k] = w_m[k] grad_c[k] (complex, context precision)
+template <typename T>
+hipError_t launch_rho_from_c(const T* w_m, const void* grad_c, int64_t K, void* grad_rho, hipStream_t s);
+// zero `count` doubles with a kernel (valid inside captured graphs)
+hipError_t launch_zero_f64(double* p, int64_t count, hipStream_t s);
 template <typename T>
 hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* rho_m, const T* w_m, int n_m,
                              const double* poses, int64_t B, T* score, double* grad_pose, T* grad_w, T* grad_c,

@@ -582,6 +582,39 @@ def test_score_grad_fixed_matches_oracle(ctxs, dtype, planar):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("n,nm", [(16, 6), (24, 8)])
+def test_score_grad_backward_matches_oracle(ctxs, dtype, n, nm):
+    """The backward entry point: for an incoming gradient g_b, the scaled pose
+    gradients g_b df_b/dpose_b, the weight gradient, the moving field's
+    cotangent w_k sum_b g_b Phi_b and the fixed field's cotangent, against the
+    oracle (tile kernel at N = 16, LDS-box kernel in 3D FP32 at N = 24); and
+    the chain rule for stored pose gradients."""
+    ctx = ctxs[dtype]
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, False, 700 + n)
+    rng = np.random.default_rng(n + 5)
+    B = 11
+    poses = np.concatenate([rng.uniform(-n, 2 * n, size=(B, 3)), wr.uniform_quaternions(B, 80 + n)], axis=1)
+    g = rng.normal(size=B)
+    flush_print("score_grad_backward", dtype, n, nm)
+    gp, gw, gr, gfix = (to_np(a) for a in ctx.score_grad_backward(rho_f, gf, rho_m, w, gm, poses, g, want_pose=True,
+                                                                     want_w=True, want_rho=True, want_fixed=True))
+    c = oc.moving_coefficients(rho_m, w)
+    xb = osp.body_positions(nm, False)
+    gp_ref = np.stack([g[b] * np.concatenate(og.pose_value_and_grad(rho_f, c, rho_m, xb, poses[b, :3],
+                                                                     poses[b, 3:])[1:3]) for b in range(B)])
+    phi = _phi_sum(rho_f, nm, poses, g)
+    gr_ref = w.reshape(-1) * phi
+    gw_ref = np.real(rho_m.reshape(-1) * phi)
+    gf_ref = og.fixed_cotangent(c, xb, poses, g, rho_f.shape)
+    tol = 1e-10 if dtype == "f64" else 2e-5
+    for got, ref in ((gp, gp_ref), (gw.reshape(-1), gw_ref), (gr.reshape(-1), gr_ref), (gfix, gf_ref)):
+        assert np.max(np.abs(got - ref)) <= tol * np.abs(ref).max()
+    # stored pose gradients times the incoming gradient, in the library
+    raw = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=True)[1]
+    assert np.max(np.abs(to_np(ctx.score_grad_pose_chain(raw, g)) - gp_ref)) <= tol * np.abs(gp_ref).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_fixed_part_shape_gradient_through_autograd(ctxs, dtype):
     """d(sum_b g_b f_b) with respect to the fixed part's boundary samples,
     through sdf_field for rho_F and sdf_score (whose backward returns the

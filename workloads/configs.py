@@ -177,6 +177,23 @@ def uneven_pair(index: int, base_seed: int = 4000, n_rot: int = 512, density: fl
                     notes={"receptor_spheres": nr, "ligand_spheres": nl, "ligand_diameter": diam})
 
 
+def _uneven_one(args):
+    index, n_rot = args
+    return uneven_pair(index, n_rot=n_rot)
+
+
+def uneven_batch(n_pairs: int = 256, n_rot: int = 512, workers: int = 1) -> list:
+    """Pairs 0 .. n_pairs - 1 of the uneven batch, generated by ``workers``
+    processes (started fresh, so a parent that already uses a GPU is not
+    forked)."""
+    jobs = [(i, n_rot) for i in range(n_pairs)]
+    if workers <= 1:
+        return [_uneven_one(j) for j in jobs]
+    import multiprocessing as mp
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_uneven_one, jobs, chunksize=1)
+
+
 # ---------------------------------------------------------------------------
 # small cases that the oracle finishes in seconds
 # ---------------------------------------------------------------------------

@@ -239,14 +239,33 @@ def random_walk_chain(count: int, box: float, rng, step: float = 3.8, min_sep: f
     radii = rng.uniform(rmin, rmax, size=count)
     cen = np.zeros((count, 3))
     cen[0] = box / 2.0
+    # Earlier centres are kept in cubic cells of side step + min_sep.  Every
+    # candidate lies within `step` of the previous centre, so the centres
+    # that can be within min_sep of a candidate lie in the 27 cells around
+    # the previous centre's; the distances are computed exactly as over all
+    # centres, so every decision (and the fallback's argmax, taken only when
+    # every in-box candidate has a centre closer than min_sep) is the same.
+    cell = step + min_sep
+    cells = {}
+
+    def key(p):
+        return (int(p[0] // cell), int(p[1] // cell), int(p[2] // cell))
+
+    cells.setdefault(key(cen[0]), []).append(0)
     for i in range(1, count):
         r = radii[i]
         d = rng.normal(size=(tries, 3))
         d /= np.linalg.norm(d, axis=1, keepdims=True)
         cand = cen[i - 1] + step * d
         inside = np.all((cand >= r) & (cand <= box - r), axis=1)
-        prev = cen[:i]
-        dmin = np.sqrt(((cand[:, None, :] - prev[None, :, :]) ** 2).sum(-1)).min(axis=1)
+        kx, ky, kz = key(cen[i - 1])
+        near = [j for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+                for j in cells.get((kx + a, ky + b, kz + c), ())]
+        if near:
+            prev = cen[sorted(near)]
+            dmin = np.sqrt(((cand[:, None, :] - prev[None, :, :]) ** 2).sum(-1)).min(axis=1)
+        else:
+            dmin = np.full(tries, np.inf)
         ok = inside & (dmin >= min_sep)
         if ok.any():
             cen[i] = cand[np.argmax(ok)]
@@ -255,6 +274,7 @@ def random_walk_chain(count: int, box: float, rng, step: float = 3.8, min_sep: f
             cen[i] = cand[np.argmax(score)]
         else:
             cen[i] = np.clip(cand[0], r, box - r)
+        cells.setdefault(key(cen[i]), []).append(i)
     return cen, radii
 
 
