@@ -801,8 +801,10 @@ void launch_line_tile(const float* vbuf, const cplx<float>* cbuf, const int* cou
 }
 
 // Line tile with the x pass of the pruned transform fused in (FP32, 3D,
-// 2N >= 32): 8 (y) x 4 (z) rows of whole x lines, 512 threads and 68 KiB of
-// LDS, so two blocks share a CU and overlap their phases.  A window of w
+// 2N >= 32): 8 (y) x 4 (z) rows of whole x lines, 512 threads and 77 KiB of
+// LDS (67 KiB of integer rows, the 256 twiddles, the candidate sort's
+// histogram and 8 KiB of sorted indices), so two blocks share a CU and
+// overlap their phases.  A window of w
 // nodes reaches 1 + ceil((w - 1) / 4) z tiles, so the tile gathers the bins
 // of its own (y, z) and of the next one below in y and up to two below in z.
 // After the fixed-point accumulation the 32 x lines are converted to complex
@@ -829,9 +831,16 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
     // counting sort of the touching candidates by (z, y) row offset: oy in
     // (-W, 8), oz in (-W, 4), W <= 8
     constexpr int KEYS = 15 * 11;
+    // each thread keeps its first KC candidates in registers (and the sort
+    // covers those KC * BS); later ones are spread unsorted
+    constexpr int KC = 4;
     __shared__ int s_hist[KEYS];
-    __shared__ int s_idx[4 * BS];
+    __shared__ int s_idx[KC * BS];
     __shared__ int s_nsorted;
+    // two blocks share a compute unit's 160 KiB only while one stays within 80 KiB
+    static_assert(sizeof(int) * (2 * kFusedLds + KEYS + KC * BS + 1) + sizeof(cplx<float>) * NF +
+                          sizeof(float) * (BS / 64) <= 80 * 1024,
+                  "the fused line tile must fit two blocks per compute unit");
     int* lre = acc;
     int* lim = acc + kFusedLds;
     cplx<float>* cb = reinterpret_cast<cplx<float>*>(acc);
@@ -873,7 +882,6 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
     auto touches = [=](int oy, int oz) __attribute__((always_inline)) {
         return oy > -W && oy < RY && oz > -W && oz < RZ;
     };
-    constexpr int KC = 4;
     float cvx[KC], cvy[KC], cvz[KC];
     cplx<float> cck[KC];
 #pragma unroll

@@ -199,6 +199,42 @@ def test_nfft_every_kernel_width_fp32_line_tiles(ctxs, w):
         assert err <= 2e-5
 
 
+@pytest.mark.parametrize("n", [32, 64])
+def test_nfft_fp32_line_tiles_crowded_tile(ctxs, n):
+    # A tight cluster of 2 600 samples puts far more than the 4 x 512
+    # candidates the fused line tile sorts into one tile's 2 x 3 bins, so the
+    # tile also runs its unsorted loop; 900 samples spread over the box fill
+    # the other tiles.  N = 64 runs the 128-point line transform and the
+    # 128-point pruned y / z passes.
+    ctx = ctxs["f32"]
+    rng = np.random.default_rng(400 + n)
+    rho_f = smooth_field(rng, n, False, damping=0.06 * n * n).astype(np.complex64)
+    centre = rng.uniform(-0.2 * n, 0.2 * n, 3)
+    pos = np.concatenate([centre + rng.normal(scale=0.7, size=(2600, 3)),
+                          rng.uniform(-0.45 * n, 0.45 * n, (900, 3))]).astype(np.float32)
+    coef = (rng.normal(size=len(pos)) + 1j * rng.normal(size=len(pos))).astype(np.complex64)
+    gf = grid_spec(n, False)
+    spec = ctx.spectrum(rho_f, gf)
+    quats = wr.uniform_quaternions(2, 500 + n)
+    # the crowded tile, counted on the host the way the bins are defined: the
+    # fine-grid tile of the first window node, 8 (y) x 4 (z) rows per tile
+    w, nf = 6, 2 * n
+    from oracle import rotation
+    for q in quats:
+        v = np.mod(-2.0 * (pos.astype(np.float64) @ rotation.quat_to_matrix(q).T), nf)
+        l0 = np.ceil(v - w / 2.0).astype(np.int64)
+        by, bz = np.mod(l0[:, 1], nf) // 8, np.mod(l0[:, 2], nf) // 4
+        bins = np.zeros((nf // 4, nf // 8), dtype=np.int64)
+        np.add.at(bins, (bz, by), 1)
+        most = max(sum(bins[(tz - dz) % (nf // 4), (ty - dy) % (nf // 8)] for dy in range(2) for dz in range(3))
+                   for tz in range(nf // 4) for ty in range(nf // 8))
+        assert most > 2048, most
+    flush_print("crowded line tile n", n, "samples", len(pos))
+    vol = to_np(ctx.score_volume_nfft(spec, gf, pos, coef, quats, width=w)).astype(np.float64)
+    check_volumes(vol, rho_f.astype(np.complex128), pos.astype(np.float64), coef.astype(np.complex128), quats,
+                  False, "f32", w)
+
+
 @pytest.mark.parametrize("dtype,planar,n", [("f32", False, 8), ("f64", False, 8), ("f64", False, 32),
                                              ("f32", True, 64), ("f64", True, 64), ("f32", True, 16)])
 def test_nfft_grid_sizes_and_tilings(ctxs, dtype, planar, n):
