@@ -77,6 +77,30 @@ __device__ __forceinline__ cplx<float> gload(const cplx<float>* p, int64_t i) {
     return mk(__uint_as_float(unsigned(v)), __uint_as_float(unsigned(v >> 32)));
 }
 
+// Raw buffer access through a gfx9 buffer descriptor of `bytes` bytes at
+// `base` (the base must be wave-uniform).  A load whose offset lies at or past
+// the end returns zeros and such a store is dropped, so an offset of
+// kBufferNone reads zeros without a branch.  The descriptor is built in
+// scalar registers; `soff` is a scalar offset added to the per-lane one.
+constexpr uint32_t kBufferNone = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), 0x00020000);
+}
+__device__ __forceinline__ cplx<float> buffer_load_cf(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), 0);
+    return mk(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+__device__ __forceinline__ void buffer_store_cf(cplx<float> x, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                uint32_t soff) {
+    using V2 = unsigned __attribute__((ext_vector_type(2)));
+    V2 v;
+    v[0] = __float_as_uint(x.re);
+    v[1] = __float_as_uint(x.im);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, int(voff), int(soff), 0);
+}
+// a value the compiler may keep in a scalar register (it must be uniform)
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ int wrap(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;

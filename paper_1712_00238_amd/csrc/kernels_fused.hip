@@ -220,6 +220,18 @@ __host__ __device__ __forceinline__ int col_kx(int p) {
     return N - (8 * b + i - 8);
 }
 
+// Column tiles (3D grids, N = 64 and 128): the spread slabs that K1 passes
+// to K2, and the fixed spectrum K2 multiplies by, are stored as tiles of one
+// row ky and one aligned block of 16 pair-grouped positions over every kz,
+// kz-major, so the pencil pass reads each tile as one contiguous 16 N * 8
+// bytes while K1 writes 128-byte pieces (HBM sustains scattered writes of
+// that size far better than scattered reads).  Element (kz, ky, p) sits at
+// ((ky (N / 16) + p / 16) N + kz) 16 + p % 16.
+template <int N>
+__host__ __device__ __forceinline__ int tile_index(int kz, int ky, int p) {
+    return ((ky * (N / 16) + (p >> 4)) * N + kz) * 16 + (p & 15);
+}
+
 __device__ __forceinline__ int fixed_rpi(float v) {
     // round to nearest (halves up) in one instruction
     int r;
@@ -438,7 +450,7 @@ __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory")
 // clears the LDS words it read for the next item.
 template <int N>
 __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const cf* __restrict__ tw, float inv,
-                                                    cf* __restrict__ out, bool grouped) {
+                                                    cf* __restrict__ out, bool grouped, int z) {
     using L = SlabLayout<N>;
     constexpr int R1 = N / 8;
     constexpr int NB = N / 8;   // radix-8 butterflies per line
@@ -514,15 +526,16 @@ x_done:
 #pragma unroll
             for (int r = 1; r < 8; ++r) u[r] = u[r] * tw[r * jj];
             dft8<float, -1>(u);
-            // 32-bit element offsets from the item's slab base (a uniform pointer)
-            const unsigned col = unsigned(grouped ? col_pos<N>(x) : x);
+            // 32-bit element offsets from a uniform base: the rotation's grid
+            // in column tiles (3D) or the item's slab (planar)
+            const unsigned col = unsigned(grouped ? tile_index<N>(z, jj, col_pos<N>(x)) : jj * N + x);
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
                 const int ky = jj + NB * r;
                 // the (-1)^(kx + ky) of the N / 2 shift: folded into the
                 // pair-grouped spectrum, applied here otherwise (planar)
                 const cf v = (!grouped && ((x + ky) & 1)) ? mk(-u[r].re, -u[r].im) : u[r];
-                out[unsigned(ky * N) + col] = v;
+                out[col + unsigned(NB * r * N * (grouped ? N : 1))] = v;
                 slab[ky * RS + px(x)] = mk(0.f, 0.f);
                 if (x < N / 16) slab[ky * RS + 17 * x + 16] = mk(0.f, 0.f);  // the gap entries
             }
@@ -570,7 +583,8 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
         cf* out = slabs + (int64_t(rot) * nz + z) * N * N;
         const float inv = jb.scale[1];
         if constexpr (L::kFast) {
-            slab_fft_store_fast<N>(acc, tw, inv, out, planar == 0);
+            // 3D grids: the rotation's column tiles; planar: the slab
+            slab_fft_store_fast<N>(acc, tw, inv, planar ? out : slabs + int64_t(rot) * nz * N * N, planar == 0, z);
         } else {
             // planes -> interleaved complex, in place: read everything, then write
             cf* slab = reinterpret_cast<cf*>(acc);
@@ -628,21 +642,97 @@ __device__ __forceinline__ PencilJob pencil_job_grouped(int j) {
     return PencilJob{j / (N / 16), (j % (N / 16)) * 16};
 }
 
+// Rotation (within its group of GR) of the line group q = l / W, for lines
+// l = ((r & 1) GR + (r >> 1) 2 + tile) W + cc: groups 2 p and 2 p + 1 (the
+// two tiles) belong to the same rotation.
+template <int GR>
+__device__ __forceinline__ int pencil_group_rot(int q) {
+    return 2 * ((q % GR) / 2) + q / GR;
+}
+
+// Pass-A chunk ch of an item (pencil job, rotations g0 ..): the 2 W lines of
+// one rotation (both tiles) at two values of j, with the R1 values
+// kz = j + 8 r of each line.  The rotation, its slab range and the buffer
+// descriptor are wave-uniform; slabs outside the rotation's range were never
+// written and read as zeros through out-of-range offsets, as do rotations
+// past n_rot.
+template <int N, int GR>
+struct PencilChunk {
+    static constexpr int W = pencil_width<N>();
+    static constexpr int NL = 2 * W * GR;
+    static constexpr int R1 = N / 8;
+    static constexpr int kChunks = NL * 8 / 64;
+    static_assert(NL * 8 % 64 == 0 && 2 * W == 32, "pass A chunks are 32 lines x 2 values of j");
+    int l, j, cc, tt;
+    __device__ __forceinline__ PencilChunk(int ch, int lane) {
+        const int qp = ch % (NL / 32), jg = ch / (NL / 32);
+        l = 32 * qp + (lane & 31);
+        j = 2 * jg + (lane >> 5);
+        cc = l % W;
+        tt = (l / W) % 2;
+    }
+    __device__ __forceinline__ static int rot_in_group(int ch) { return pencil_group_rot<GR>(2 * (ch % (NL / 32))); }
+};
+
+template <int N, int GR>
+__device__ __forceinline__ void pencil_load_chunk(const cf* __restrict__ slabs, const FusedRot* __restrict__ rots,
+                                                  int n_rot, const PencilJob job, int g0, int ch, int lane,
+                                                  cf (&v)[N / 8]) {
+    using C = PencilChunk<N, GR>;
+    constexpr int64_t G = int64_t(N) * N * N;
+    constexpr uint32_t kGridBytes = uint32_t(G * sizeof(cf));
+    static_assert(G * sizeof(cf) < (int64_t(1) << 31), "buffer offsets are 32-bit");
+    const C c(ch, lane);
+    const int rot = uniform(g0 + C::rot_in_group(ch));
+    if (rot < n_rot) {
+        const int zlo = uniform(rots[rot].zlo), span = uniform(rots[rot].zhi) - zlo;
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(slabs + int64_t(rot) * G, kGridBytes);
+        const int ky = c.tt ? (N - job.ky) % N : job.ky;
+        const uint32_t vo = uint32_t(tile_index<N>(c.j, ky, job.x0 + c.cc) * int(sizeof(cf)));
+        const int d = c.j - zlo;
+#pragma unroll
+        for (int r = 0; r < C::R1; ++r) {
+            // centred height of kz = j + 8 r, minus zlo
+            const int dz = d + 8 * r - (8 * r < N / 2 ? 0 : N);
+            const bool reached = unsigned(dz) <= unsigned(span);
+            v[r] = buffer_load_cf(rs, reached ? vo : kBufferNone, uint32_t(8 * r * 16 * sizeof(cf)));
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < C::R1; ++r) v[r] = mk(0.f, 0.f);
+    }
+}
+
 // Fast pencil pass for NZ = N = 8 R1 (R1 = 8 or 16).  LDS holds the NL
 // lines of the item at row stride NL + 8 (element kz of line l at
 // kz (NL + 8) + l).
-//  A  forward radix-R1 pass along z, read straight from global memory;
+//  A  forward radix-R1 pass along z.  With GR = 2 the item's raw columns are
+//     already in LDS (rows j R1 + r of line l hold kz = j + 8 r), loaded
+//     during the previous item's inverse passes by the waves those passes
+//     leave idle; with GR = 4 each wave loads its chunks here;
 //  B  forward radix-8 pass in place, times the fixed spectrum;
 //  F  Hermitian folding in place: the unit (pair, column, kz) reads the k
 //     lines a0, b0 at kz and the -k lines a1, b1 at -kz and writes Z to a0
 //     at kz and a1 at -kz, positions no other unit touches;
 //  I  inverse radix-R1 and radix-8 passes over the Z lines, 8 lines per
 //     wave (no block barrier between them), the last pass writing global
-//     memory.
+//     memory.  With GR = 2 half of the waves run them while the other half
+//     load the next item's columns, which are written to LDS after a barrier.
 // The spectrum values of a thread's pass-B units (GR = 2: two units of 8
-// values) are kept in registers: they are requested before the pass-A loads
-// so both round trips to memory overlap, and consecutive items of a block
-// that share the pencil job and the spectra reuse them.
+// values) are kept in registers, and consecutive items of a block that share
+// the pencil job and the spectra reuse them.
+// GR = 2 with 16-column tiles: the inverse passes occupy GR W / 8 = 4 of the
+// 8 waves, and the other 4 load the next item's 8 chunks, two each
+template <int N, int GR>
+constexpr bool pencil_pipe() {
+    if constexpr (pencil_width<N>() != 16 || GR != 2) {
+        return false;
+    } else {
+        constexpr int IW = GR * pencil_width<N>() / 8;
+        return IW < kPencilBlock / 64 && PencilChunk<N, GR>::kChunks == 2 * (kPencilBlock / 64 - IW);
+    }
+}
+
 template <int N, int GR>
 struct PencilSpec {
     static constexpr int NL = 2 * pencil_width<N>() * GR;
@@ -650,38 +740,58 @@ struct PencilSpec {
     static constexpr int PB = (NL * NB + kPencilBlock - 1) / kPencilBlock;
     static constexpr bool kKeep = GR == 2 && PB * kPencilBlock == NL * NB;
     static constexpr int kRows = kKeep ? PB : 1;
+    // waves that run the inverse passes; the others load ahead when PIPE
+    static constexpr int IW = GR * pencil_width<N>() / 8;
+    static constexpr bool kPipe = pencil_pipe<N, GR>();
+};
+
+// next item of the block, for the loads ahead
+struct PencilNext {
+    PencilJob job;
+    int g0;
+    bool valid;
 };
 
 template <int N, int GR>
-__device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict__ slabs, cf* __restrict__ packed,
+__device__ __forceinline__ void pencil_store_raw(cf* __restrict__ buf, int ch, int lane, const cf (&v)[N / 8]) {
+    using C = PencilChunk<N, GR>;
+    constexpr int NLP = C::NL + 8;
+    const C c(ch, lane);
+#pragma unroll
+    for (int r = 0; r < C::R1; ++r) buf[(c.j * C::R1 + r) * NLP + c.l] = v[r];
+}
+
+template <int N, int GR>
+__device__ __forceinline__ void pencil_item_fast(int n_rot, const FusedRot* __restrict__ rots,
+                                                 const cf* __restrict__ slabs, cf* __restrict__ packed,
                                                  cf* __restrict__ buf, const cf* __restrict__ tw,
-                                                 const cf* const* spec_of, const int (*zr_of)[2], const PencilJob job,
-                                                 int g0, cf (&spre)[PencilSpec<N, GR>::kRows][8], bool reload) {
+                                                 const cf* const* spec_of, const PencilJob job, int g0,
+                                                 const PencilNext nx, cf (&spre)[PencilSpec<N, GR>::kRows][8],
+                                                 bool reload) {
+    using PS = PencilSpec<N, GR>;
+    using C = PencilChunk<N, GR>;
     constexpr int W = pencil_width<N>();
     constexpr int NL = 2 * W * GR;
     constexpr int NLP = NL + 8;
     constexpr int R1 = N / 8;
     constexpr int NB = N / 8;
     constexpr int64_t G = int64_t(N) * N * N;
+    constexpr uint32_t kGridBytes = uint32_t(G * sizeof(cf));
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
+    const int lane = t & 63, wave = uniform(t >> 6);
     const int kyt[2] = {job.ky, (N - job.ky) % N};
     // both tiles cover positions x0 .. x0 + 15 of the pair-grouped order; the
     // partner of position x0 + cc is x0 + (cc ^ 8), or itself for kx = 0, N/2
     auto kx_of = [&](int, int cc) { return job.x0 + cc; };
     auto partner = [&](int cc) { return (job.x0 == 0 && (cc & 7) == 0) ? cc : (cc ^ 8); };
-    // line l = ((r & 1) GR + (r >> 1) 2 + tile) W + cc
-    auto line_rot = [](int l) {
-        const int q = l / W;
-        return 2 * ((q % GR) / 2) + q / GR;
-    };
-    constexpr int PB = PencilSpec<N, GR>::PB;
-    constexpr bool kPre = PencilSpec<N, GR>::kKeep;
+    constexpr int PB = PS::PB;
+    constexpr bool kPre = PS::kKeep;
     auto spec_at = [&](int b, int r) {
         const int l = b % NL, jj = b / NL;
         const int cc = l % W, tt = (l / W) % 2;
-        const cf* sp = spec_of[line_rot(l)];
-        return sp ? gload(sp, int64_t(jj + NB * r) * N * N + int64_t(kyt[tt]) * N + kx_of(tt, cc)) : mk(0.f, 0.f);
+        const cf* sp = spec_of[pencil_group_rot<GR>(l / W)];
+        return sp ? gload(sp, tile_index<N>(jj + NB * r, kyt[tt], kx_of(tt, cc))) : mk(0.f, 0.f);
     };
     if constexpr (kPre) {
         if (reload) {
@@ -692,31 +802,21 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
         }
     }
     // ---- A
-    for (int b = t; b < NL * 8; b += kPencilBlock) {
-        const int l = b % NL, j = b / NL;
-        const int cc = l % W, tt = (l / W) % 2;
-        const int lr = line_rot(l);
-        const int rot = g0 + lr;
+    for (int ch = wave; ch < C::kChunks; ch += kPencilBlock / 64) {
+        const C c(ch, lane);
         cf v[R1];
-        if (rot < n_rot) {
-            // slabs outside the rotation's range were never written: zeros
-            const int zlo = zr_of[lr][0], zhi = zr_of[lr][1];
-            const cf* src = slabs + int64_t(rot) * G + int64_t(kyt[tt]) * N + kx_of(tt, cc);
+        if constexpr (PS::kPipe) {
 #pragma unroll
-            for (int r = 0; r < R1; ++r) {
-                const int kz = j + 8 * r, zc = kz < N / 2 ? kz : kz - N;
-                v[r] = (zc >= zlo && zc <= zhi) ? src[int64_t(kz) * N * N] : mk(0.f, 0.f);
-            }
-            dftR<float, -1, R1>(v);
+            for (int r = 0; r < R1; ++r) v[r] = buf[(c.j * R1 + r) * NLP + c.l];
         } else {
-#pragma unroll
-            for (int r = 0; r < R1; ++r) v[r] = mk(0.f, 0.f);
+            pencil_load_chunk<N, GR>(slabs, rots, n_rot, job, g0, ch, lane, v);
         }
+        dftR<float, -1, R1>(v);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) buf[(j * R1 + r) * NLP + l] = v[r];
+        for (int r = 0; r < R1; ++r) buf[(c.j * R1 + r) * NLP + c.l] = v[r];
     }
     __syncthreads();
-    // ---- B
+    // ---- B (the grouped spectrum carries the fold's factor 1/2)
 #pragma unroll
     for (int m = 0; m < PB; ++m) {
         const int b = t + m * kPencilBlock;
@@ -735,50 +835,80 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const cf* __restrict
         }
     }
     __syncthreads();
-    // ---- F
-    for (int u = t; u < (GR / 2) * W * N; u += kPencilBlock) {
-        const int cc = u % W, kz = (u / W) % N, p = u / (W * N);
-        const int mkz = (N - kz) % N;
+    // ---- F: unit (pair p, column cc, kz); a thread keeps cc and walks kz in
+    // steps of KS, so its rows sit at constant offsets from two bases
+    {
+        constexpr int KS = kPencilBlock / W;  // kz step between a thread's units
+        constexpr int NM = N / KS;             // units per pair and thread
+        static_assert(kPencilBlock % W == 0 && N % KS == 0, "fold units");
+        const int cc = t % W, kz0 = t / W;
         const int pc = partner(cc);
-        const int a0 = (2 * p) * W + cc, a1 = (2 * p + 1) * W + pc;
-        const int b0 = (GR + 2 * p) * W + cc, b1 = (GR + 2 * p + 1) * W + pc;
-        const cf ya0 = buf[kz * NLP + a0], ya1 = buf[mkz * NLP + a1];
-        const cf yb0 = buf[kz * NLP + b0], yb1 = buf[mkz * NLP + b1];
-        const cf ha = (ya0 + conj(ya1)) * 0.5f;
-        const cf hb = (yb0 + conj(yb1)) * 0.5f;
-        buf[kz * NLP + a0] = mk(ha.re - hb.im, ha.im + hb.re);
-        buf[mkz * NLP + a1] = mk(ha.re + hb.im, hb.re - ha.im);
+        const int mk0 = kz0 == 0 ? 0 : N - kz0;  // -kz0 mod N
+#pragma unroll
+        for (int p = 0; p < GR / 2; ++p) {
+            const int a0 = (2 * p) * W + cc, a1 = (2 * p + 1) * W + pc;
+            const int b0 = (GR + 2 * p) * W + cc, b1 = (GR + 2 * p + 1) * W + pc;
+#pragma unroll
+            for (int s = 0; s < NM; ++s) {
+                const int kz = kz0 + KS * s;
+                const int mkz = s == 0 ? mk0 : N - kz0 - KS * s;
+                const cf ya0 = buf[kz * NLP + a0], ya1 = buf[mkz * NLP + a1];
+                const cf yb0 = buf[kz * NLP + b0], yb1 = buf[mkz * NLP + b1];
+                const cf ha = ya0 + conj(ya1);
+                const cf hb = yb0 + conj(yb1);
+                buf[kz * NLP + a0] = mk(ha.re - hb.im, ha.im + hb.re);
+                buf[mkz * NLP + a1] = mk(ha.re + hb.im, hb.re - ha.im);
+            }
+        }
     }
     __syncthreads();
-    // ---- I: Z lines are lines [0, GR W); wave w takes lines 8 w .. 8 w + 7
-    for (int wv = t >> 6; wv < GR * W / 8; wv += kPencilBlock / 64) {
-        const int lane = t & 63;
-        const int l = wv * 8 + (lane & 7), j = lane >> 3;
-        cf v[R1];
+    // ---- I: Z lines are lines [0, GR W); wave w takes lines 8 w .. 8 w + 7,
+    // which lie in one (pair, tile) group, so the stores go through one
+    // wave-uniform descriptor.  The other waves load the next item.
+    cf pre[PS::kPipe ? 2 : 1][R1];
+    const bool loader = PS::kPipe && wave >= PS::IW && nx.valid;
+    if (!PS::kPipe || wave < PS::IW) {
+        for (int wv = wave; wv < PS::IW; wv += kPencilBlock / 64) {
+            const int l = wv * 8 + (lane & 7), j = lane >> 3;
+            cf v[R1];
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = buf[(j + 8 * r) * NLP + l];
-        compiler_fence();
-        dftR<float, 1, R1>(v);
+            for (int r = 0; r < R1; ++r) v[r] = buf[(j + 8 * r) * NLP + l];
+            compiler_fence();
+            dftR<float, 1, R1>(v);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) buf[(j * R1 + r) * NLP + l] = v[r];
-        compiler_fence();
-        const int cc = l % W, q = l / W, p = q / 2, tt = q % 2;
-        const int pair = g0 / 2 + p;
-        const bool store = pair < (n_rot + 1) / 2;
-        cf* dst = packed + int64_t(pair) * G + int64_t(kyt[tt]) * N + kx_of(tt, cc);
+            for (int r = 0; r < R1; ++r) buf[(j * R1 + r) * NLP + l] = v[r];
+            compiler_fence();
+            const int cc = l % W, q = (wv * 8) / W, p = q / 2, tt = q % 2;
+            const int pair = g0 / 2 + p;
+            const bool store = pair < (n_rot + 1) / 2;
+            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(packed + int64_t(store ? pair : 0) * G, kGridBytes);
 #pragma unroll
-        for (int m = 0; m < NB / 8; ++m) {
-            const int jj = j + 8 * m;
-            cf uu[8];
+            for (int m = 0; m < NB / 8; ++m) {
+                const int jj = j + 8 * m;
+                cf uu[8];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) uu[r] = buf[(jj + NB * r) * NLP + l];
+                for (int r = 0; r < 8; ++r) uu[r] = buf[(jj + NB * r) * NLP + l];
 #pragma unroll
-            for (int r = 1; r < 8; ++r) uu[r] = uu[r] * conj(tw[r * jj]);
-            dft8<float, 1>(uu);
-            if (store) {
+                for (int r = 1; r < 8; ++r) uu[r] = uu[r] * conj(tw[r * jj]);
+                dft8<float, 1>(uu);
+                if (store) {
+                    const uint32_t vo = uint32_t(((jj * N + kyt[tt]) * N + kx_of(tt, cc)) * int(sizeof(cf)));
 #pragma unroll
-                for (int r = 0; r < 8; ++r) dst[int64_t(jj + NB * r) * N * N] = uu[r];
+                    for (int r = 0; r < 8; ++r)
+                        buffer_store_cf(uu[r], rs, vo, uint32_t(NB * r * N * N * sizeof(cf)));
+                }
             }
+        }
+    } else if (loader) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k)
+            pencil_load_chunk<N, GR>(slabs, rots, n_rot, nx.job, nx.g0, 2 * (wave - PS::IW) + k, lane, pre[k]);
+    }
+    if constexpr (PS::kPipe) {
+        __syncthreads();  // the inverse passes are done with buf
+        if (loader) {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) pencil_store_raw<N, GR>(buf, 2 * (wave - PS::IW) + k, lane, pre[k]);
         }
     }
 }
@@ -816,6 +946,18 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
     const cf* prev_spec[GR];
 #pragma unroll
     for (int k = 0; k < GR; ++k) prev_spec[k] = nullptr;
+    if constexpr (kFast && PencilSpec<N, GR>::kPipe) {
+        // raw columns of the block's first item, one chunk per wave (later
+        // items' columns are loaded during the previous item's inverse passes)
+        static_assert(PencilChunk<N, GR>::kChunks == kPencilBlock / 64, "one chunk per wave");
+        if (ibeg < iend) {
+            const int wave = uniform(int(threadIdx.x) >> 6), lane = int(threadIdx.x) & 63;
+            cf v0[N / 8];
+            pencil_load_chunk<N, GR>(slabs, rots, n_rot, pencil_job_grouped<N>(ibeg / ngroups), (ibeg % ngroups) * GR,
+                                     wave, lane, v0);
+            pencil_store_raw<N, GR>(buf, wave, lane, v0);
+        }
+    }
     for (int item = ibeg; item < iend; item += istep) {
         const int jobi = kFast ? item / ngroups : item % njobs;
         const PencilJob job = kFast ? pencil_job_grouped<N>(jobi) : pencil_job<N>(jobi);
@@ -838,7 +980,9 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
                 prev_spec[k] = spec_of[k];
             }
             prev_job = jobi;
-            pencil_item_fast<N, GR>(n_rot, slabs, packed, buf, tw, spec_of, zr_of, job, g0, spre, reload);
+            const int nitem = item + 1;
+            const PencilNext nx{pencil_job_grouped<N>(nitem / ngroups), (nitem % ngroups) * GR, nitem < iend};
+            pencil_item_fast<N, GR>(n_rot, rots, slabs, packed, buf, tw, spec_of, job, g0, nx, spre, reload);
             continue;
         }
         // load both tiles of every rotation of the group (zeros for missing
@@ -1368,18 +1512,21 @@ size_t fused_workspace_bytes(const FusedPlan& fp) { return fused_layout(fp, null
 
 size_t fused_prep_scratch_bytes(int n_jobs) { return align256(sizeof(float) * kPrepBlocks * size_t(n_jobs)); }
 
-// The copy also multiplies S(k) by (-1)^(kx + ky): the slabs of these sizes
-// are spread at positions shifted by N / 2 in x and y, so their transforms
-// carry that factor, and (-1)^(kx + ky) is the same at k and -k, so the
-// product Y(k) S(k) that the pencil pass folds is unchanged.
+// The copy also multiplies S(k) by (-1)^(kx + ky) / 2: the slabs of these
+// sizes are spread at positions shifted by N / 2 in x and y, so their
+// transforms carry the sign, and (-1)^(kx + ky) is the same at k and -k, so
+// the product Y(k) S(k) that the pencil pass folds is unchanged; the 1/2 is
+// the fold's own factor in H(k) = (Y(k) + conj(Y(-k))) / 2 (an exact power of
+// two, so the folded values are the same).
 template <int N>
 __global__ void spec_pair_group_kernel(const cf* __restrict__ in, cf* __restrict__ out) {
     const int64_t rows = int64_t(N) * N;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < rows * N; i += int64_t(gridDim.x) * blockDim.x) {
         const int p = int(i % N);
-        const int kx = col_kx<N>(p), ky = int((i / N) % N);
+        const int kx = col_kx<N>(p), ky = int((i / N) % N), kz = int(i / rows);
         const cf v = in[i - p + kx];
-        out[i] = ((kx + ky) & 1) ? mk(-v.re, -v.im) : v;
+        const float h = ((kx + ky) & 1) ? -0.5f : 0.5f;
+        out[tile_index<N>(kz, ky, p)] = mk(h * v.re, h * v.im);
     }
 }
 

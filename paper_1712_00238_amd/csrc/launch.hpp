@@ -132,8 +132,10 @@ struct FusedPlan {
 size_t fused_workspace_bytes(const FusedPlan& fp);
 // 3D grids of N = 64 and 128 pass grids between the fused kernels with their
 // x columns in pair-grouped order (each aligned block of 16 positions holds
-// 8 columns kx and their negatives); the fixed spectrum is copied into that
-// order once per call.
+// 8 columns kx and their negatives); the spread slabs go from the spread to
+// the pencil pass in column tiles (one row ky, one block of 16 positions,
+// every kz), and the fixed spectrum is copied into that order and tiling
+// once per call.
 inline bool fused_pair_grouped(int N, bool planar) { return !planar && (N == 64 || N == 128); }
 hipError_t launch_spec_pair_group(const void* spec, void* out, int N, hipStream_t s);
 // quaternions -> FusedRot descriptors (FP64 matrix, cast to FP32)

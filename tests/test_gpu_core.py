@@ -262,11 +262,15 @@ def test_score_volume_direct_sum_tiny(ctxs):
                                                     (64, 24, False, 7, 4), (64, 30, True, 5, 4),
                                                     # largest body boxes the fitting rule admits (stencil at the
                                                     # edge of the unwrapped slab; 71 is odd: generic lane map)
-                                                    (64, 34, False, 3, 2), (128, 71, False, 2, 2)])
+                                                    (64, 34, False, 3, 2), (128, 71, False, 2, 2),
+                                                    # four rotations per pencil item (group 4) at the two-pass sizes
+                                                    (64, 24, False, 7, -8), (128, 40, False, 5, -4)])
 def test_score_rotations_peaks_f32(ctxs, path, n, nm, planar, nrot, batch):
+    # batch < 0: batch |batch| with pencil groups of 4 rotations
     ctx = ctxs["f32"]
     ctx.set_option("path", path)
-    ctx.set_option("batch", batch)
+    ctx.set_option("batch", abs(batch))
+    ctx.set_option("pencil_group", 4 if batch < 0 else 2)
     try:
         gf, gm, rho_f, rho_m, w = small_case(n, nm, planar, 7 * n + nm)
         quats = wr.uniform_quaternions(nrot, n) if not planar else wr.planar_rotations(17.0, nrot)
@@ -288,6 +292,7 @@ def test_score_rotations_peaks_f32(ctxs, path, n, nm, planar, nrot, batch):
     finally:
         ctx.set_option("path", 0)
         ctx.set_option("batch", 64)
+        ctx.set_option("pencil_group", 2)
 
 
 @pytest.mark.parametrize("n,nm,planar,nrot", [(16, 6, False, 3), (32, 19, True, 4)])
