@@ -497,7 +497,7 @@ int octree_samples(sdf_ctx ctx, const void *rho_moving, const void *w_moving, co
  * 10^(1 - width)), product with spec_fixed, inverse FFT.  Peaks, 27-
  * neighbourhoods and sub-voxel offsets as in score_rotations.
  *   spec_fixed: output of sdf_spectrum; g_fixed N^3 or N^2 x 1 with N in
- *   {8, 16, 32, 64, 128}; width in [2, 8]; 0 <= m <= 2^30 (m = 0 scores 0).
+ *   {8, 16, 32, 64, 96, 128}; width in [2, 8]; 0 <= m <= 2^30 (m = 0 scores 0).
  *   quats (host): n_rot x 4 FP64.
  * Device workspace: about 768 MiB per batch of rotations at N = 128 (the
  * oversampled-grid buffers, one N^d grid and the binned samples, 6 reals

@@ -889,8 +889,8 @@ int check_nfft_args(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const voi
     const int N = gf->n[0];
     if (gf->n[1] != N || (gf->n[2] != N && gf->n[2] != 1))
         return fail(ctx, SDF_EINVAL, "g_fixed: must be N x N x N or N x N x 1");
-    if (N != 8 && N != 16 && N != 32 && N != 64 && N != 128)
-        return fail(ctx, SDF_EUNSUPPORTED, "g_fixed: the nonequispaced route needs N in {8, 16, 32, 64, 128}");
+    if (N != 8 && N != 16 && N != 32 && N != 64 && N != 96 && N != 128)
+        return fail(ctx, SDF_EUNSUPPORTED, "g_fixed: the nonequispaced route needs N in {8, 16, 32, 64, 96, 128}");
     if (m < 0 || m > (int64_t(1) << 30)) return fail(ctx, SDF_EINVAL, "sample count must be in [0, 2^30]");
     if (w < 2 || w > 8) return fail(ctx, SDF_EINVAL, "kernel width must be in [2, 8]");
     rc = check_quats(ctx, quats, n_rot);

@@ -339,7 +339,8 @@ __global__ __launch_bounds__(256) void nfft_bin_kernel(const T* __restrict__ pos
         for (int a = 0; a < DIM; ++a) {
             const T y = -T(2) * (r[3 * a] * px + r[3 * a + 1] * py + r[3 * a + 2] * pz);
             v[a] = y - dev_floor(y / fn) * fn;
-            b[a] = first_node(v[a], half) & (nf - 1);
+            const int l0 = first_node(v[a], half);  // in [-w/2, nf)
+            b[a] = l0 < 0 ? l0 + nf : l0;
         }
         const int nbins = ts.ntx * ts.nty * ts.ntz;
         bin = int64_t(rot) * nbins + (b[2] / ts.tz * ts.nty + b[1] / ts.ty) * ts.ntx + b[0] / ts.tx;
@@ -393,12 +394,22 @@ struct TileAcc<double> {
     __device__ static double back(unsigned long long a) { return double((long long)a); }
 };
 
-// per axis: do any of the W nodes o + q (mod nf) fall in [0, side)?
+// offset o in (-2 nf, nf) of a node from a tile origin, wrapped to [0, nf)
+__device__ __forceinline__ int wrap_offset(int o, int nf) {
+    o += o < 0 ? nf : 0;
+    o += o < 0 ? nf : 0;
+    return o;
+}
+// node o + q < 2 nf wrapped to [0, nf)
+__device__ __forceinline__ int wrap_once(int x, int nf) { return x >= nf ? x - nf : x; }
+
+// per axis: do any of the W nodes ow + q (mod nf) fall in [0, side)?  ow is
+// the wrapped offset of the first node
 template <int W>
-__device__ __forceinline__ bool reaches(int o, int side, int msk) {
+__device__ __forceinline__ bool reaches(int ow, int side, int nf) {
     bool hit = false;
 #pragma unroll
-    for (int q = 0; q < W; ++q) hit |= ((o + q) & msk) < side;
+    for (int q = 0; q < W; ++q) hit |= wrap_once(ow + q, nf) < side;
     return hit;
 }
 
@@ -418,7 +429,6 @@ __global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vb
     const int org[3] = {tbx * ts.tx, tby * ts.ty, tbz * ts.tz};
     const int side[3] = {ts.tx, ts.ty, ts.tz};
     const int nodes = ts.tx * ts.ty * ts.tz;
-    const int msk = nf - 1;
     const T half = T(0.5 * W), beta = T(kEsBetaPerWidth * W), zs = T(2.0 / W);
     for (int e = int(threadIdx.x); e < kTileLds; e += 256) {
         lre[e] = A(0);
@@ -445,7 +455,8 @@ __global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vb
             const T* vp = vbuf + 4 * at;
             bool hit = true;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) hit = hit && reaches<W>(first_node(vp[a], half) - org[a], side[a], msk);
+            for (int a = 0; a < DIM; ++a)
+                hit = hit && reaches<W>(wrap_offset(first_node(vp[a], half) - org[a], nf), side[a], nf);
             if (hit) {
                 const cplx<T> ck = cbuf[at];
                 part += dmax(dabs(ck.re), dabs(ck.im));
@@ -470,8 +481,8 @@ __global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vb
                 for (int a = 0; a < DIM; ++a) {
                     va[a] = vp[a];
                     l0[a] = first_node(va[a], half);
-                    o[a] = l0[a] - org[a];
-                    hit = hit && reaches<W>(o[a], side[a], msk);
+                    o[a] = wrap_offset(l0[a] - org[a], nf);
+                    hit = hit && reaches<W>(o[a], side[a], nf);
                 }
                 if (!hit) continue;
                 const cplx<T> ck = cbuf[at];
@@ -489,11 +500,11 @@ __global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vb
                 if (DIM == 2) {
 #pragma unroll
                     for (int bq = 0; bq < W; ++bq) {
-                        const int iy = (o[1] + bq) & msk;
+                        const int iy = wrap_once(o[1] + bq, nf);
                         if (iy >= ts.ty) continue;
 #pragma unroll
                         for (int aq = 0; aq < W; ++aq) {
-                            const int ix = (o[0] + aq) & msk;
+                            const int ix = wrap_once(o[0] + aq, nf);
                             if (ix >= ts.tx) continue;
                             const T wgt = wt[0][aq] * wt[1][bq];
                             atomicAdd(&lre[iy * ts.py + ix], Acc::to(cre * wgt));
@@ -503,17 +514,17 @@ __global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vb
                 } else {
 #pragma unroll
                     for (int cq = 0; cq < W; ++cq) {
-                        const int iz = (o[2] + cq) & msk;
+                        const int iz = wrap_once(o[2] + cq, nf);
                         if (iz >= ts.tz) continue;
 #pragma unroll
                         for (int bq = 0; bq < W; ++bq) {
-                            const int iy = (o[1] + bq) & msk;
+                            const int iy = wrap_once(o[1] + bq, nf);
                             if (iy >= ts.ty) continue;
                             const T wyz = wt[1][bq] * wt[2][cq];
                             const int rowo = iz * ts.pz + iy * ts.py;
 #pragma unroll
                             for (int aq = 0; aq < W; ++aq) {
-                                const int ix = (o[0] + aq) & msk;
+                                const int ix = wrap_once(o[0] + aq, nf);
                                 if (ix >= ts.tx) continue;
                                 const T wgt = wt[0][aq] * wyz;
                                 atomicAdd(&lre[rowo + ix], Acc::to(cre * wgt));
@@ -657,6 +668,7 @@ hipError_t launch_pruned(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarte
         SDF_PRUNED(32)
         SDF_PRUNED(64)
         SDF_PRUNED(128)
+        SDF_PRUNED(192)
         SDF_PRUNED(256)
 #undef SDF_PRUNED
         default: return hipErrorInvalidValue;
@@ -876,8 +888,17 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
         for (int nb = 1; nb < NB; ++nb) base += int(i >= bpre[nb]) * delta[nb];
         return int64_t(base) + i;
     };
+    // x in (-nf, 2 nf) wrapped to [0, nf)
+    auto wrapnf = [](int x) __attribute__((always_inline)) {
+        if constexpr ((NF & (NF - 1)) == 0) {
+            return x & msk;
+        } else {
+            x += x < 0 ? NF : 0;
+            return x >= NF ? x - NF : x;
+        }
+    };
     auto rel = [=](float v, int org) __attribute__((always_inline)) {
-        return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2;
+        return wrapnf(first_node(v, half) - org + nf / 2) - nf / 2;
     };
     auto touches = [=](int oy, int oz) __attribute__((always_inline)) {
         return oy > -W && oy < RY && oz > -W && oz < RZ;
@@ -1001,7 +1022,7 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
             xr[q] = ck.re * sc * wx;
             xi[q] = ck.im * sc * wx;
         }
-        const int xb = lx & msk;  // taps xb .. xb + W - 1 < nf + 8
+        const int xb = wrapnf(lx);  // taps xb .. xb + W - 1 < nf + 8
 #pragma unroll
         for (int cq = 0; cq < W; ++cq) {
             const int iz = oz + cq;
@@ -1045,7 +1066,7 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = int(threadIdx.x) + k * BS;
-        const int x = e & msk, row = e / NF;
+        const int x = e % NF, row = e / NF;
         int ar = lre[row * px + x], ai = lim[row * px + x];
         if (x < 8) {
             ar += lre[row * px + nf + x];
@@ -1094,6 +1115,7 @@ hipError_t launch_line_fft(const float* vbuf, const cplx<float>* cbuf, const int
         case 32: launch_line_fft_nf<32>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
         case 64: launch_line_fft_nf<64>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
         case 128: launch_line_fft_nf<128>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
+        case 192: launch_line_fft_nf<192>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
         case 256: launch_line_fft_nf<256>(vbuf, cbuf, counts, offsets, batch, w, ts, half_buf, s); break;
         default: return hipErrorInvalidValue;
     }

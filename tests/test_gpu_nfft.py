@@ -199,7 +199,7 @@ def test_nfft_every_kernel_width_fp32_line_tiles(ctxs, w):
         assert err <= 2e-5
 
 
-@pytest.mark.parametrize("n", [32, 64])
+@pytest.mark.parametrize("n", [32, 64, 96])
 def test_nfft_fp32_line_tiles_crowded_tile(ctxs, n):
     # A tight cluster of 2 600 samples puts far more than the 4 x 512
     # candidates the fused line tile sorts into one tile's 2 x 3 bins, so the
@@ -218,6 +218,7 @@ def test_nfft_fp32_line_tiles_crowded_tile(ctxs, n):
     quats = wr.uniform_quaternions(2, 500 + n)
     # the crowded tile, counted on the host the way the bins are defined: the
     # fine-grid tile of the first window node, 8 (y) x 4 (z) rows per tile
+    # (N = 96: 192-point lines, whose transform has a radix-3 pass)
     w, nf = 6, 2 * n
     from oracle import rotation
     for q in quats:
@@ -236,10 +237,15 @@ def test_nfft_fp32_line_tiles_crowded_tile(ctxs, n):
 
 
 @pytest.mark.parametrize("dtype,planar,n", [("f32", False, 8), ("f64", False, 8), ("f64", False, 32),
-                                             ("f32", True, 64), ("f64", True, 64), ("f32", True, 16)])
+                                             ("f32", True, 64), ("f64", True, 64), ("f32", True, 16),
+                                             ("f32", False, 96), ("f64", False, 96), ("f32", True, 96),
+                                             ("f64", True, 96)])
 def test_nfft_grid_sizes_and_tilings(ctxs, dtype, planar, n):
     # every spreading path: FP32 line tiles without the fused x pass (N = 8),
-    # general tiles split along every axis (FP64 3D N = 32, planar N = 64)
+    # general tiles split along every axis (FP64 3D N = 32, planar N = 64);
+    # N = 96 runs 192-point lines (not a power of two: wrapped offsets, a
+    # radix-3 pass) through the fused line tiles, the general tiles in 3D and
+    # in the plane, and the pruned passes
     ctx = ctxs[dtype]
     rng = np.random.default_rng(300 + n + planar)
     rho_f = smooth_field(rng, n, planar, damping=0.3 * n * n / 16)
@@ -310,10 +316,10 @@ def test_nfft_rejects_unsupported_grids(ctxs):
         ctx.score_volume_nfft(spec, gf, pos, c, q, width=9)
     with pytest.raises(SdfError):
         ctx.score_volume_nfft(spec, gf, pos, c, q, width=1)
-    g96 = grid_spec(96, False)
-    spec96 = ctx.spectrum(np.zeros((96, 96, 96), np.complex64), g96)
+    # N = 48 has no transform plan: refused before any device work (the
+    # spectrum passed is never read)
     with pytest.raises(SdfError):
-        ctx.score_volume_nfft(spec96, g96, pos, c, q)
+        ctx.score_volume_nfft(spec, grid_spec(48, False), pos, c, q)
 
 
 # ----------------------------------------------------------------------------- full size
