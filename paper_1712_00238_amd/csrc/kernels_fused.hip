@@ -22,8 +22,8 @@
 //                   has inverse transform Re f), inverse z-FFT, write.
 //  K3 islab_peak    (rotation pair, z-slab): inverse 2D FFT of the folded
 //                   slab; Re is rotation A's score slab, Im rotation B's;
-//                   per-slab max / lowest-index argmax of each.
-//  K4 finish        (rotation, dz): reduce the slab partials to the peak,
+//                   max / lowest-index argmax of each per wave and slab.
+//  K4 finish        (rotation, dz): reduce the wave partials to the peak,
 //                   evaluate the 9 scores of slab t_z + dz around it by a
 //                   separable direct inverse 2D DFT of the folded slab (FP64
 //                   accumulation); K5 assembles the 27 values and refines the
@@ -52,6 +52,7 @@ namespace {
 using cf = cplx<float>;
 
 constexpr int kSlabBlock = 1024;
+constexpr int kIslabWaves = kSlabBlock / 64;  // argmax partials per (rotation, slab)
 constexpr int kPencilBlock = 512;
 constexpr int kFinishBlock = 256;
 constexpr int kPrepBlocks = 64;
@@ -1186,8 +1187,6 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
     constexpr bool kFast = SlabLayout<N>::kFast;
     __shared__ cf slab[kFast ? N * (N + N / 16 + 4) : N * N];
     __shared__ cf tw[N];
-    __shared__ float rv[2][kSlabBlock / 64];
-    __shared__ int ri[2][kSlabBlock / 64];
     fill_twiddles<float, N>(tw);
     const int npair = (n_rot + 1) / 2;
     const int items = nz * npair;
@@ -1225,33 +1224,25 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
                 take(v.im, zoff + i, vb, ib);
             }
         }
+        // one partial per wave, reduced by the finish kernel: no barrier and
+        // no serial tail between items
         wave_argmax(va, ia);
         wave_argmax(vb, ib);
         const int lane = threadIdx.x % warpSize, wid = threadIdx.x / warpSize;
         if (lane == 0) {
-            rv[0][wid] = va;
-            ri[0][wid] = ia;
-            rv[1][wid] = vb;
-            ri[1][wid] = ib;
-        }
-        __syncthreads();
-        if (threadIdx.x < 2) {
-            const int w = threadIdx.x;
-            float bv = rv[w][0];
-            int bi = ri[w][0];
-            for (int k = 1; k < kSlabBlock / 64; ++k)
-                if (better(rv[w][k], ri[w][k], bv, bi)) { bv = rv[w][k]; bi = ri[w][k]; }
-            const int rot = 2 * pair + w;
-            if (rot < n_rot) {
-                pval[int64_t(rot) * nz + z] = bv;
-                pidx[int64_t(rot) * nz + z] = bi;
+            const int64_t at = (int64_t(2 * pair) * nz + z) * kIslabWaves + wid;
+            pval[at] = va;
+            pidx[at] = ia;
+            if (2 * pair + 1 < n_rot) {
+                pval[at + int64_t(nz) * kIslabWaves] = vb;
+                pidx[at + int64_t(nz) * kIslabWaves] = ib;
             }
         }
     }
 }
 
 // ------------------------------------------------------------------ K4
-// (dz, rotation): peak from the slab partials, then the 9 scores of slab
+// (dz, rotation): peak from the per-wave slab partials, then the 9 scores of slab
 // t_z + dz around (t_x, t_y) by a separable inverse DFT of the folded slab:
 //   h_j(ky)  = sum_kx P(kx, ky) e^{2 pi i kx x_j / N},  x_j in t_x + {-1, 0, 1}
 //   g(x_j, y_i) = sum_ky h_j(ky) e^{2 pi i ky y_i / N}
@@ -1278,9 +1269,9 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
     }
     float bv = -INFINITY;
     int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < nz; i += kFinishBlock) {
-        const float v = pval[int64_t(rot) * nz + i];
-        const int id = pidx[int64_t(rot) * nz + i];
+    for (int i = threadIdx.x; i < nz * kIslabWaves; i += kFinishBlock) {
+        const float v = pval[int64_t(rot) * nz * kIslabWaves + i];
+        const int id = pidx[int64_t(rot) * nz * kIslabWaves + i];
         if (better(v, id, bv, bi)) { bv = v; bi = id; }
     }
     sv[threadIdx.x] = bv;
@@ -1428,9 +1419,9 @@ FusedLayout fused_layout(const FusedPlan& fp, void* ws) {
     L.packed = reinterpret_cast<cf*>(base + off);
     off += align256(sizeof(cf) * G * ((fp.batch + 1) / 2));
     L.pval = reinterpret_cast<float*>(base + off);
-    off += align256(sizeof(float) * nz * fp.batch);
+    off += align256(sizeof(float) * nz * kIslabWaves * fp.batch);
     L.pidx = reinterpret_cast<int*>(base + off);
-    off += align256(sizeof(int) * nz * fp.batch);
+    off += align256(sizeof(int) * nz * kIslabWaves * fp.batch);
     L.nbbuf = reinterpret_cast<double*>(base + off);
     off += align256(sizeof(double) * 27 * fp.batch);
     L.total = off;
