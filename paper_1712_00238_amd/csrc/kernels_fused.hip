@@ -1077,8 +1077,28 @@ __device__ __forceinline__ bool better(float v, int i, float bv, int bi) {
     return v > bv || (v == bv && i < bi);
 }
 
+// one step of the (max, lowest index) reduction with a DPP lane pattern
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp_step(float& v, int& i) {
+    const float ov = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, 0xF, 0xF,
+                                                                false));
+    const int oi = __builtin_amdgcn_update_dpp(i, i, CTRL, 0xF, 0xF, false);
+    if (better(ov, oi, v, i)) {
+        v = ov;
+        i = oi;
+    }
+}
+
+// (max, lowest index) over the wave, in every lane.  Inside each row of 16
+// lanes through DPP patterns (no LDS round trip): swap neighbours, swap
+// pairs, mirror the half rows (quad 0 meets quad 1), mirror the row; then
+// across rows with two shuffles.
 __device__ __forceinline__ void wave_argmax(float& v, int& i) {
-    for (int off = warpSize / 2; off > 0; off >>= 1) {
+    argmax_dpp_step<0xB1>(v, i);   // quad_perm [1, 0, 3, 2]
+    argmax_dpp_step<0x4E>(v, i);   // quad_perm [2, 3, 0, 1]
+    argmax_dpp_step<0x141>(v, i);  // row_half_mirror
+    argmax_dpp_step<0x140>(v, i);  // row_mirror
+    for (int off = 16; off < warpSize; off <<= 1) {
         const float ov = __shfl_xor(v, off);
         const int oi = __shfl_xor(i, off);
         if (better(ov, oi, v, i)) {
