@@ -1184,18 +1184,23 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
             for (int r = 1; r < 8; ++r) u[m][r] = u[m][r] * conj(tw[r * jj]);
             dft8<float, 1>(u[m]);
         }
-        // visit the outputs in increasing index (x = j + 8 m + NB r): a strict
-        // comparison then keeps the lowest index among equal values
-        const int row = zoff + y * N + j;
+        // visit the outputs in increasing index (x = j + 8 m + NB r = j + 8 s
+        // with slot s = m + (NB / 8) r): a strict comparison then keeps the
+        // lowest index among equal values; the slot is turned into the flat
+        // index once
+        int sa = -1, sb = -1;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
 #pragma unroll
             for (int m = 0; m < NB / 8; ++m) {
-                const int idx = row + 8 * m + NB * r;
-                if (u[m][r].re > va) { va = u[m][r].re; ia = idx; }
-                if (u[m][r].im > vb) { vb = u[m][r].im; ib = idx; }
+                const int slot = m + (NB / 8) * r;
+                if (u[m][r].re > va) { va = u[m][r].re; sa = slot; }
+                if (u[m][r].im > vb) { vb = u[m][r].im; sb = slot; }
             }
         }
+        const int row = zoff + y * N + j;
+        if (sa >= 0) ia = row + 8 * sa;
+        if (sb >= 0) ib = row + 8 * sb;
     }
 }
 
