@@ -828,7 +828,11 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
     const size_t fine_bytes = sdf::nfft_grid_bytes(N, planar, sizeof(T));
     // rotations per batch: the per-rotation grids, x-pruned buffer and binned
     // samples within the budget
-    const size_t per_rot = fine_bytes + 2 * sizeof(T) * size_t(G) + sdf::nfft_workspace_bytes(m, 1, N, planar, sizeof(T));
+    // FP32 3D peaks at N = 64 and 128 go through the search path's inverse
+    // kernels (rotation pairs folded into one inverse transform)
+    const bool fused_peaks = std::is_same<T, float>::value && mode == Mode::Peaks && sdf::modes_peaks_supported(N, planar);
+    const size_t per_rot = fine_bytes + 2 * sizeof(T) * size_t(G) + sdf::nfft_workspace_bytes(m, 1, N, planar, sizeof(T)) +
+                           (fused_peaks ? sdf::modes_peaks_workspace_bytes(N, 2) / 2 : 0);
     int64_t B = std::max<int64_t>(1, std::min<int64_t>(n_rot, int64_t(kNfftBudget / per_rot)));
     if (m > 0) B = std::max<int64_t>(1, std::min<int64_t>(B, (int64_t(1) << 30) / m));  // binned samples < 2^31
     const int nparts = sdf::peak_parts<T>(N, planar);
@@ -843,6 +847,8 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
     cv.take(sizeof(int) * nparts * B);
     const size_t bin_bytes = sdf::nfft_workspace_bytes(m, int(B), N, planar, sizeof(T));
     cv.take(bin_bytes);
+    const size_t peaks_bytes = fused_peaks ? sdf::modes_peaks_workspace_bytes(N, int(B)) : 0;
+    cv.take(peaks_bytes);
     int rc = ensure_ws(ctx, cv.off);
     if (rc) return rc;
     Carve c2{static_cast<char*>(ctx->ws)};
@@ -855,6 +861,7 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
     T* pval = static_cast<T*>(c2.take(sizeof(T) * nparts * B));
     int* pidx = static_cast<int*>(c2.take(sizeof(int) * nparts * B));
     void* bins = c2.take(bin_bytes);
+    void* peaks_ws = c2.take(peaks_bytes);
     SDF_TRY_HIP(ctx, hipMemcpyAsync(qd, quats, sizeof(double) * 4 * n_rot, hipMemcpyHostToDevice, s),
                 "quaternion upload");
     SDF_TRY_HIP(ctx, sdf::launch_quat_to_rot<T>(qd, n_rot, r64, RT, s), "rotations");
@@ -863,8 +870,16 @@ int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos
         const int nb = int(std::min<int64_t>(B, n_rot - r0));
         SDF_TRY_HIP(ctx,
                     sdf::launch_nfft_modes<T>(static_cast<const T*>(pos), c, m, RT + 9 * r0, nb, N, planar, w, inv,
-                                              spec, fine, grid, bins, s),
+                                              spec, fine, grid, bins, s, fused_peaks),
                     "nonequispaced transform");
+        if (fused_peaks) {
+            SDF_TRY_HIP(ctx,
+                        sdf::launch_modes_peaks(N, grid, nb, 0, static_cast<float*>(score) + r0, t + 3 * r0,
+                                                nbhd ? static_cast<float*>(nbhd) + 27 * r0 : nullptr,
+                                                refined ? refined + 3 * r0 : nullptr, ctx->num_cu, peaks_ws, s),
+                        "folded inverse and peaks");
+            continue;
+        }
         SDF_TRY_HIP(ctx, sdf::launch_fft3<T>(grid, N, planar, nb, +1, 1.0, s), "inverse fft");
         if (mode == Mode::Volume) {
             SDF_TRY_HIP(ctx, sdf::launch_real_part<T>(grid, static_cast<T*>(vol_out) + r0 * G, G * nb, s),

@@ -101,6 +101,39 @@ __device__ __forceinline__ void buffer_store_cf(cplx<float> x, __amdgpu_buffer_r
 // a value the compiler may keep in a scalar register (it must be uniform)
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Pair-grouped column order (3D grids, N = 64 and 128).  Position p = 16 b + i
+// holds kx = 8 b + i for i < 8 and kx = -(8 b + i - 8) mod N for i >= 8,
+// except p = 8, which holds N / 2.  Every column's negative then sits in the
+// same aligned block of 16 (at p ^ 8, or at p itself for kx = 0 and N / 2),
+// so a pencil tile of row ky and its partner tile of row -ky cover the same
+// aligned 128-byte segments.
+template <int N>
+__host__ __device__ __forceinline__ int col_pos(int kx) {
+    if (kx == N / 2) return 8;
+    if (kx < N / 2) return 16 * (kx >> 3) + (kx & 7);
+    const int m = N - kx;
+    return 16 * (m >> 3) + 8 + (m & 7);
+}
+template <int N>
+__host__ __device__ __forceinline__ int col_kx(int p) {
+    const int b = p >> 4, i = p & 15;
+    if (i < 8) return 8 * b + i;
+    if (p == 8) return N / 2;
+    return N - (8 * b + i - 8);
+}
+
+// Column tiles (3D grids, N = 64 and 128): the spread slabs that K1 passes
+// to K2, and the fixed spectrum K2 multiplies by, are stored as tiles of one
+// row ky and one aligned block of 16 pair-grouped positions over every kz,
+// kz-major, so the pencil pass reads each tile as one contiguous 16 N * 8
+// bytes while K1 writes 128-byte pieces (HBM sustains scattered writes of
+// that size far better than scattered reads).  Element (kz, ky, p) sits at
+// ((ky (N / 16) + p / 16) N + kz) 16 + p % 16.
+template <int N>
+__host__ __device__ __forceinline__ int tile_index(int kz, int ky, int p) {
+    return ((ky * (N / 16) + (p >> 4)) * N + kz) * 16 + (p & 15);
+}
+
 __device__ __forceinline__ int wrap(int i, int n) {
     int r = i % n;
     return r < 0 ? r + n : r;

@@ -200,39 +200,6 @@ struct SlabLayout {
     static constexpr int kShift = kFast ? N / 2 : 0;
 };
 
-// Pair-grouped column order (3D grids, N = 64 and 128).  Position p = 16 b + i
-// holds kx = 8 b + i for i < 8 and kx = -(8 b + i - 8) mod N for i >= 8,
-// except p = 8, which holds N / 2.  Every column's negative then sits in the
-// same aligned block of 16 (at p ^ 8, or at p itself for kx = 0 and N / 2),
-// so a pencil tile of row ky and its partner tile of row -ky cover the same
-// aligned 128-byte segments.
-template <int N>
-__host__ __device__ __forceinline__ int col_pos(int kx) {
-    if (kx == N / 2) return 8;
-    if (kx < N / 2) return 16 * (kx >> 3) + (kx & 7);
-    const int m = N - kx;
-    return 16 * (m >> 3) + 8 + (m & 7);
-}
-template <int N>
-__host__ __device__ __forceinline__ int col_kx(int p) {
-    const int b = p >> 4, i = p & 15;
-    if (i < 8) return 8 * b + i;
-    if (p == 8) return N / 2;
-    return N - (8 * b + i - 8);
-}
-
-// Column tiles (3D grids, N = 64 and 128): the spread slabs that K1 passes
-// to K2, and the fixed spectrum K2 multiplies by, are stored as tiles of one
-// row ky and one aligned block of 16 pair-grouped positions over every kz,
-// kz-major, so the pencil pass reads each tile as one contiguous 16 N * 8
-// bytes while K1 writes 128-byte pieces (HBM sustains scattered writes of
-// that size far better than scattered reads).  Element (kz, ky, p) sits at
-// ((ky (N / 16) + p / 16) N + kz) 16 + p % 16.
-template <int N>
-__host__ __device__ __forceinline__ int tile_index(int kz, int ky, int p) {
-    return ((ky * (N / 16) + (p >> 4)) * N + kz) * 16 + (p & 15);
-}
-
 __device__ __forceinline__ int fixed_rpi(float v) {
     // round to nearest (halves up) in one instruction
     int r;
@@ -675,7 +642,8 @@ struct PencilChunk {
     __device__ __forceinline__ static int rot_in_group(int ch) { return pencil_group_rot<GR>(2 * (ch % (NL / 32))); }
 };
 
-template <int N, int GR>
+// ALL: every kz is present (transformed spectra rather than spread slabs)
+template <int N, int GR, bool ALL = false>
 __device__ __forceinline__ void pencil_load_chunk(const cf* __restrict__ slabs, const FusedRot* __restrict__ rots,
                                                   int n_rot, const PencilJob job, int g0, int ch, int lane,
                                                   cf (&v)[N / 8]) {
@@ -686,7 +654,7 @@ __device__ __forceinline__ void pencil_load_chunk(const cf* __restrict__ slabs, 
     const C c(ch, lane);
     const int rot = uniform(g0 + C::rot_in_group(ch));
     if (rot < n_rot) {
-        const int zlo = uniform(rots[rot].zlo), span = uniform(rots[rot].zhi) - zlo;
+        const int zlo = ALL ? -N / 2 : uniform(rots[rot].zlo), span = ALL ? N - 1 : uniform(rots[rot].zhi) - zlo;
         const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(slabs + int64_t(rot) * G, kGridBytes);
         const int ky = c.tt ? (N - job.ky) % N : job.ky;
         const uint32_t vo = uint32_t(tile_index<N>(c.j, ky, job.x0 + c.cc) * int(sizeof(cf)));
@@ -753,16 +721,27 @@ struct PencilNext {
     bool valid;
 };
 
-template <int N, int GR>
+// raw columns into LDS: for the forward pass A (row j R1 + r holds
+// kz = j + 8 r), or NATURAL: transformed spectra at row kz, times the fold's
+// factor 1/2
+template <int N, int GR, bool NATURAL = false>
 __device__ __forceinline__ void pencil_store_raw(cf* __restrict__ buf, int ch, int lane, const cf (&v)[N / 8]) {
     using C = PencilChunk<N, GR>;
     constexpr int NLP = C::NL + 8;
     const C c(ch, lane);
 #pragma unroll
-    for (int r = 0; r < C::R1; ++r) buf[(c.j * C::R1 + r) * NLP + c.l] = v[r];
+    for (int r = 0; r < C::R1; ++r) {
+        if constexpr (NATURAL)
+            buf[(c.j + 8 * r) * NLP + c.l] = v[r] * 0.5f;
+        else
+            buf[(c.j * C::R1 + r) * NLP + c.l] = v[r];
+    }
 }
 
-template <int N, int GR>
+// MODES: the input is already transformed along z and multiplied by the
+// spectrum (column tiles, every kz): passes A and B are skipped, the loader
+// waves put the next item's values straight into their rows
+template <int N, int GR, bool MODES = false>
 __device__ __forceinline__ void pencil_item_fast(int n_rot, const FusedRot* __restrict__ rots,
                                                  const cf* __restrict__ slabs, cf* __restrict__ packed,
                                                  cf* __restrict__ buf, const cf* __restrict__ tw,
@@ -794,7 +773,8 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const FusedRot* __re
         const cf* sp = spec_of[pencil_group_rot<GR>(l / W)];
         return sp ? gload(sp, tile_index<N>(jj + NB * r, kyt[tt], kx_of(tt, cc))) : mk(0.f, 0.f);
     };
-    if constexpr (kPre) {
+    static_assert(!MODES || PS::kPipe, "transformed input comes through the loader waves");
+    if constexpr (kPre && !MODES) {
         if (reload) {
 #pragma unroll
             for (int m = 0; m < PB; ++m)
@@ -803,7 +783,7 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const FusedRot* __re
         }
     }
     // ---- A
-    for (int ch = wave; ch < C::kChunks; ch += kPencilBlock / 64) {
+    for (int ch = wave; !MODES && ch < C::kChunks; ch += kPencilBlock / 64) {
         const C c(ch, lane);
         cf v[R1];
         if constexpr (PS::kPipe) {
@@ -819,7 +799,7 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const FusedRot* __re
     __syncthreads();
     // ---- B (the grouped spectrum carries the fold's factor 1/2)
 #pragma unroll
-    for (int m = 0; m < PB; ++m) {
+    for (int m = 0; m < (MODES ? 0 : PB); ++m) {
         const int b = t + m * kPencilBlock;
         if (!kPre && b >= NL * NB) break;
         const int l = b % NL, jj = b / NL;
@@ -903,13 +883,14 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const FusedRot* __re
     } else if (loader) {
 #pragma unroll
         for (int k = 0; k < 2; ++k)
-            pencil_load_chunk<N, GR>(slabs, rots, n_rot, nx.job, nx.g0, 2 * (wave - PS::IW) + k, lane, pre[k]);
+            pencil_load_chunk<N, GR, MODES>(slabs, rots, n_rot, nx.job, nx.g0, 2 * (wave - PS::IW) + k, lane,
+                                            pre[k]);
     }
     if constexpr (PS::kPipe) {
         __syncthreads();  // the inverse passes are done with buf
         if (loader) {
 #pragma unroll
-            for (int k = 0; k < 2; ++k) pencil_store_raw<N, GR>(buf, 2 * (wave - PS::IW) + k, lane, pre[k]);
+            for (int k = 0; k < 2; ++k) pencil_store_raw<N, GR, MODES>(buf, 2 * (wave - PS::IW) + k, lane, pre[k]);
         }
     }
 }
@@ -1069,6 +1050,59 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
             packed[int64_t(pair0 + p) * G + (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)] =
                 buf[kz * NL + line_of(2 * p, t, cc)];
         }
+    }
+}
+
+// K2 for spectra that arrive already transformed along every axis and
+// multiplied by the fixed spectrum (the nonequispaced route's modes, 3D,
+// N = 64 and 128, in column tiles): fold rotation pairs and run the inverse z
+// pass into the packed grids, so that K3 and K4 give the peaks as on the
+// search path.  Same items and loads as the pencil kernel with groups of 2.
+template <int N>
+__global__ __launch_bounds__(kPencilBlock, 4) void pencil_modes_kernel(const FusedRot* __restrict__ rots, int n_rot,
+                                                                    const cf* __restrict__ modes,
+                                                                    cf* __restrict__ packed) {
+    constexpr int GR = 2;
+    constexpr int NL = 2 * pencil_width<N>() * GR;
+    static_assert(SlabLayout<N>::kFast && PencilSpec<N, GR>::kPipe, "two-pass sizes");
+    __shared__ cf buf[N * (NL + 8)];
+    __shared__ cf tw[N];
+    fill_twiddles<float, N>(tw);
+    const int ngroups = (n_rot + GR - 1) / GR;
+    const int items = pencil_jobs_grouped<N>() * ngroups;
+    const int per = (items + int(gridDim.x) - 1) / int(gridDim.x);
+    const int ibeg = int(blockIdx.x) * per, iend = ibeg + per < items ? ibeg + per : items;
+    cf spre[PencilSpec<N, GR>::kRows][8];
+    if (ibeg < iend) {
+        const int wave = uniform(int(threadIdx.x) >> 6), lane = int(threadIdx.x) & 63;
+        cf v0[N / 8];
+        pencil_load_chunk<N, GR, true>(modes, rots, n_rot, pencil_job_grouped<N>(ibeg / ngroups),
+                                       (ibeg % ngroups) * GR, wave, lane, v0);
+        pencil_store_raw<N, GR, true>(buf, wave, lane, v0);
+    }
+    for (int item = ibeg; item < iend; ++item) {
+        const PencilJob job = pencil_job_grouped<N>(item / ngroups);
+        const int g0 = (item % ngroups) * GR;
+        const int nitem = item + 1;
+        const PencilNext nx{pencil_job_grouped<N>(nitem / ngroups), (nitem % ngroups) * GR, nitem < iend};
+        __syncthreads();  // the previous item's loads are in buf
+        pencil_item_fast<N, GR, true>(n_rot, rots, modes, packed, buf, tw, nullptr, job, g0, nx, spre, false);
+    }
+}
+
+// descriptors of a batch of one pair's rotations for K3 / K4: rotation i
+// writes its outputs at index i of the given arrays
+__global__ void modes_desc_kernel(FusedRot* __restrict__ rots, int n, FusedJob* __restrict__ job, float* score,
+                                  int32_t* t, float* nbhd, double* refined, int n_m) {
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i == 0) *job = FusedJob{nullptr, nullptr, nullptr, score, t, nbhd, refined, n_m, 0};
+    if (i < n) {
+        FusedRot r{};
+        r.job = 0;
+        r.local = i;
+        r.zlo = -32768;
+        r.zhi = 32767;
+        rots[i] = r;
     }
 }
 
@@ -1522,9 +1556,71 @@ __global__ void fill_random_kernel(cf* __restrict__ p, int64_t n, uint32_t seed,
     }
 }
 
+struct ModesLayout {
+    cf* packed;
+    float* pval;
+    int* pidx;
+    double* nbbuf;
+    FusedRot* rots;
+    FusedJob* job;
+    size_t total;
+};
+
+ModesLayout modes_layout(int N, int nb, void* ws) {
+    const int64_t G = int64_t(N) * N * N;
+    char* base = static_cast<char*>(ws);
+    ModesLayout L{};
+    size_t off = 0;
+    L.packed = reinterpret_cast<cf*>(base + off);
+    off += align256(sizeof(cf) * G * ((nb + 1) / 2));
+    L.pval = reinterpret_cast<float*>(base + off);
+    off += align256(sizeof(float) * N * kIslabWaves * size_t(nb));
+    L.pidx = reinterpret_cast<int*>(base + off);
+    off += align256(sizeof(int) * N * kIslabWaves * size_t(nb));
+    L.nbbuf = reinterpret_cast<double*>(base + off);
+    off += align256(sizeof(double) * 27 * size_t(nb));
+    L.rots = reinterpret_cast<FusedRot*>(base + off);
+    off += align256(sizeof(FusedRot) * size_t(nb));
+    L.job = reinterpret_cast<FusedJob*>(base + off);
+    off += align256(sizeof(FusedJob));
+    L.total = off;
+    return L;
+}
+
+template <int N>
+hipError_t modes_peaks_impl(const cf* modes, int nb, int n_m, float* score, int32_t* t, float* nbhd, double* refined,
+                            int num_cu, void* ws, hipStream_t s) {
+    const ModesLayout L = modes_layout(N, nb, ws);
+    hipLaunchKernelGGL(modes_desc_kernel, dim3(unsigned((nb + 255) / 256)), dim3(256), 0, s, L.rots, nb, L.job,
+                       score, t, nbhd, refined, n_m);
+    const int items2 = pencil_jobs_grouped<N>() * ((nb + 1) / 2);
+    hipLaunchKernelGGL(pencil_modes_kernel<N>, dim3(persistent_grid(items2, 2 * num_cu)), dim3(kPencilBlock), 0, s,
+                       L.rots, nb, modes, L.packed);
+    hipLaunchKernelGGL((islab_peak_kernel<N, 0>), dim3(persistent_grid(N * ((nb + 1) / 2), num_cu)), dim3(kSlabBlock),
+                       0, s, L.packed, N, nb, L.pval, L.pidx);
+    hipLaunchKernelGGL(finish_slab_kernel<N>, dim3(3u, unsigned(nb)), dim3(kFinishBlock), 0, s, L.packed, N, L.pval,
+                       L.pidx, L.nbbuf, L.rots, L.job);
+    hipLaunchKernelGGL(finish_rot_kernel, dim3(unsigned((nb + 63) / 64)), dim3(64), 0, s, L.nbbuf, L.rots, L.job, nb);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 size_t fused_workspace_bytes(const FusedPlan& fp) { return fused_layout(fp, nullptr).total; }
+
+bool modes_peaks_supported(int N, bool planar) { return fused_pair_grouped(N, planar); }
+
+size_t modes_peaks_workspace_bytes(int N, int nb) { return modes_layout(N, nb, nullptr).total; }
+
+hipError_t launch_modes_peaks(int N, const void* modes, int nb, int n_m, float* score, int32_t* t, float* nbhd,
+                              double* refined, int num_cu, void* ws, hipStream_t s) {
+    const cf* m = static_cast<const cf*>(modes);
+    switch (N) {
+        case 64: return modes_peaks_impl<64>(m, nb, n_m, score, t, nbhd, refined, num_cu, ws, s);
+        case 128: return modes_peaks_impl<128>(m, nb, n_m, score, t, nbhd, refined, num_cu, ws, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 size_t fused_prep_scratch_bytes(int n_jobs) { return align256(sizeof(float) * kPrepBlocks * size_t(n_jobs)); }
 

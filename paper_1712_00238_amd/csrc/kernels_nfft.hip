@@ -597,7 +597,9 @@ constexpr int cols_block() {
 // stride es_in) and stores the N kept outputs (stride es_out).  FINAL: the
 // axis is the last one (y of a planar grid, z in 3D); outputs are the modes
 // (jx, jy[, jz]) times inv[jx] inv[jy] [inv[jz]] spec.
-template <typename T, int NF, bool FINAL, bool PLANAR, int BS = cols_block<NF>()>
+// TILED (FINAL, 3D, N = 64 or 128): outputs go to column tiles with
+// pair-grouped positions, the layout the search path's pencil pass reads
+template <typename T, int NF, bool FINAL, bool PLANAR, int BS = cols_block<NF>(), bool TILED = false>
 __global__ __launch_bounds__(BS) void nfft_cols_pruned_kernel(const cplx<T>* __restrict__ in,
                                                                cplx<T>* __restrict__ out, int64_t es_in,
                                                                int64_t os_in, int64_t bs_in, int64_t es_out,
@@ -625,14 +627,19 @@ __global__ __launch_bounds__(BS) void nfft_cols_pruned_kernel(const cplx<T>* __r
             const T sc = inv[jx] * inv[jy] * (PLANAR ? T(1) : inv[jz]);
             v = v * sc * spec[(int64_t(jz) * N + jy) * N + jx];
         }
-        dst[int64_t(j) * es_out + xl] = v;
+        if constexpr (TILED) {
+            static_assert(FINAL && !PLANAR && (N == 64 || N == 128), "column tiles: 3D, N = 64 or 128");
+            out[int64_t(b) * bs_out + tile_index<N>(j, o, col_pos<N>(x0 + xl))] = v;
+        } else {
+            dst[int64_t(j) * es_out + xl] = v;
+        }
     }
 }
 
 // rows_done: the x pass already wrote half_buf (fused into the line tiles)
 template <typename T, int NF>
 void pruned_transform(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_buf, int batch, bool planar,
-                      const T* inv, const cplx<T>* spec, cplx<T>* out, bool rows_done, hipStream_t s) {
+                      const T* inv, const cplx<T>* spec, cplx<T>* out, bool rows_done, bool tiled, hipStream_t s) {
     constexpr int N = NF / 2, TPL = FFTShape<NF>::TPL, CONC = 256 / TPL, BS = cols_block<NF>(),
                   W = pruned_width<NF, BS>();
     const int64_t nrows = int64_t(batch) * NF * (planar ? 1 : NF);
@@ -650,7 +657,15 @@ void pruned_transform(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_b
     hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, false, false>), dim3(N / W, NF, unsigned(batch)), dim3(BS),
                        0, s, half_buf, quarter_buf, int64_t(N), int64_t(NF) * N, int64_t(NF) * NF * N, int64_t(N),
                        int64_t(N) * N, int64_t(NF) * N * N, inv, spec);
-    // z, last: quarter_buf [b][z < NF][jy][jx] -> out [b][jz][jy][jx]
+    // z, last: quarter_buf [b][z < NF][jy][jx] -> out [b][jz][jy][jx] (or column tiles)
+    if constexpr (NF == 128 || NF == 256) {
+        if (tiled) {
+            hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, false, BS, true>), dim3(N / W, N, unsigned(batch)),
+                               dim3(BS), 0, s, quarter_buf, out, int64_t(N) * N, int64_t(N), int64_t(NF) * N * N,
+                               int64_t(N) * N, int64_t(N), int64_t(N) * N * N, inv, spec);
+            return;
+        }
+    }
     hipLaunchKernelGGL((nfft_cols_pruned_kernel<T, NF, true, false>), dim3(N / W, N, unsigned(batch)), dim3(BS), 0,
                        s, quarter_buf, out, int64_t(N) * N, int64_t(N), int64_t(NF) * N * N, int64_t(N) * N,
                        int64_t(N), int64_t(N) * N * N, inv, spec);
@@ -658,11 +673,11 @@ void pruned_transform(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_b
 
 template <typename T>
 hipError_t launch_pruned(const cplx<T>* fine, cplx<T>* half_buf, cplx<T>* quarter_buf, int batch, int N, bool planar,
-                         const T* inv, const cplx<T>* spec, cplx<T>* out, bool rows_done, hipStream_t s) {
+                         const T* inv, const cplx<T>* spec, cplx<T>* out, bool rows_done, bool tiled, hipStream_t s) {
     switch (2 * N) {
 #define SDF_PRUNED(NF)                                                                                             \
     case NF:                                                                                                       \
-        pruned_transform<T, NF>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, rows_done, s);          \
+        pruned_transform<T, NF>(fine, half_buf, quarter_buf, batch, planar, inv, spec, out, rows_done, tiled, s);   \
         break;
         SDF_PRUNED(16)
         SDF_PRUNED(32)
@@ -1283,7 +1298,8 @@ size_t nfft_grid_bytes(int N, bool planar, size_t elem) {
 
 template <typename T>
 hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
-                             int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s) {
+                             int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s,
+                             bool tiled) {
     const int nf = 2 * N;
     const bool lines = use_lines(planar, sizeof(T));
     const TileShape ts = tile_shape(nf, planar, lines);
@@ -1352,7 +1368,7 @@ hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R,
     if (e != hipSuccess) return e;
     // the y pass's output reuses the oversampled grids, free after the x pass
     return launch_pruned<T>(fg, reinterpret_cast<cplx<T>*>(base + L.half), fg, batch, N, planar, inv,
-                            static_cast<const cplx<T>*>(spec), static_cast<cplx<T>*>(out), rows_done, s);
+                            static_cast<const cplx<T>*>(spec), static_cast<cplx<T>*>(out), rows_done, tiled, s);
 }
 
 template hipError_t launch_octree<float>(const void*, const float*, int, bool, double, int, float*, void*, int*,
@@ -1362,8 +1378,9 @@ template hipError_t launch_octree<double>(const void*, const double*, int, bool,
 template hipError_t launch_es_deconv<float>(int, int, float*, hipStream_t);
 template hipError_t launch_es_deconv<double>(int, int, double*, hipStream_t);
 template hipError_t launch_nfft_modes<float>(const float*, const void*, int64_t, const float*, int, int, bool, int,
-                                             const float*, const void*, void*, void*, void*, hipStream_t);
+                                             const float*, const void*, void*, void*, void*, hipStream_t, bool);
 template hipError_t launch_nfft_modes<double>(const double*, const void*, int64_t, const double*, int, int, bool,
-                                              int, const double*, const void*, void*, void*, void*, hipStream_t);
+                                              int, const double*, const void*, void*, void*, void*, hipStream_t,
+                                              bool);
 
 }  // namespace sdf

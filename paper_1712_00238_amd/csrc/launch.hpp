@@ -146,6 +146,15 @@ size_t fused_prep_scratch_bytes(int n_jobs);
 // score rotations rots[0 .. n_rot) (n_rot <= fp.batch) of one grid-size class
 hipError_t launch_fused_batch(const FusedPlan& fp, const FusedRot* rots, int n_rot, const FusedJob* jobs, void* ws,
                               hipStream_t s, KernelTimer* kt = nullptr);
+// Peaks of rotations whose correlation spectra Y(k) S(k) are already formed
+// (complex64, 3D, N = 64 or 128, nb grids in column tiles with pair-grouped
+// positions, as launch_nfft_modes writes them with `tiled`): fold rotation
+// pairs, inverse FFT through the search path's pencil, inverse-slab and finish
+// kernels, outputs as score_rotations for rotation i at index i.
+bool modes_peaks_supported(int N, bool planar);
+size_t modes_peaks_workspace_bytes(int N, int nb);
+hipError_t launch_modes_peaks(int N, const void* modes, int nb, int n_m, float* score, int32_t* t, float* nbhd,
+                              double* refined, int num_cu, void* ws, hipStream_t s);
 // deterministic pseudo-random complex64 fill (autotune inputs)
 hipError_t launch_fill_random(void* data, int64_t count, uint32_t seed, float amp, hipStream_t s);
 
@@ -169,9 +178,12 @@ size_t nfft_workspace_bytes(int64_t m, int batch, int N, bool planar, size_t ele
 // per rotation: bytes of the `fine` grid launch_nfft_modes needs (the whole
 // (2N)^d grid, or a quarter of it where the x pass is fused into the tiles)
 size_t nfft_grid_bytes(int N, bool planar, size_t elem);
+// tiled (3D, N = 64 or 128): out in column tiles with pair-grouped positions
+// (the input of launch_modes_peaks) instead of [b][jz][jy][jx]
 template <typename T>
 hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R, int batch, int N, bool planar,
-                             int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s);
+                             int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s,
+                             bool tiled = false);
 
 // ---- top-k
 template <typename T>

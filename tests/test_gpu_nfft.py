@@ -294,6 +294,41 @@ def test_nfft_peaks_match_oracle_volumes(ctxs, dtype):
                     k += 1
 
 
+@pytest.mark.parametrize("n,nrot", [(64, 5), (128, 3)])
+def test_nfft_peaks_fp32_through_folded_inverse(ctxs, n, nrot):
+    """FP32 3D peaks at N = 64 and 128 take the search path's inverse kernels
+    (column-tile modes, rotation pairs folded into one inverse transform, the
+    slab argmax and the FP64 finish): peaks, 27-neighbourhoods and sub-voxel
+    refinement against the oracle's algorithm, with an odd rotation count so
+    the last pair holds one rotation."""
+    from oracle import peak as op
+    ctx = ctxs["f32"]
+    rng = np.random.default_rng(600 + n)
+    rho_f = smooth_field(rng, n, False, damping=0.08 * n * n).astype(np.complex64)
+    m = 2500
+    pos = rng.uniform(-0.3 * n, 0.3 * n, (m, 3)).astype(np.float32)
+    coef = (rng.normal(size=m) + 1j * rng.normal(size=m)).astype(np.complex64)
+    gf = grid_spec(n, False)
+    spec = ctx.spectrum(rho_f, gf)
+    quats = wr.uniform_quaternions(nrot, 700 + n)
+    flush_print("nfft fused peaks n", n, "rotations", nrot)
+    out = ctx.score_rotations_nfft(spec, gf, pos, coef, quats, width=6)
+    s, t = to_np(out["score"]).astype(np.float64), to_np(out["t"])
+    nb, ref_t = to_np(out["nbhd"]).astype(np.float64), to_np(out["refined"])
+    for r, q in enumerate(quats):
+        vol = onf.score_volume_trig(rho_f.astype(np.complex128), pos.astype(np.float64), coef.astype(np.complex128),
+                                    q, False, w=6)
+        scale = np.abs(vol).max()
+        s0, _, t0 = op.peak(vol)
+        flush_print("  rotation", r, "score", s[r], "oracle", s0, "t", tuple(t[r]), t0)
+        assert abs(s[r] - s0) <= 2e-5 * scale, (r, s[r], s0)
+        if tuple(t[r]) != t0:  # a near-tie: the oracle's value there must match the max
+            assert abs(vol[t[r][2], t[r][1], t[r][0]] - s0) <= 2e-5 * scale
+        nb0 = op.neighbourhood(vol, tuple(t[r]))
+        assert np.max(np.abs(nb[r] - nb0)) <= 2e-5 * scale
+        assert np.max(np.abs(ref_t[r] - op.subvoxel(nb0, tuple(t[r])))) <= 1e-3
+
+
 def test_nfft_without_samples_scores_zero(ctxs):
     ctx = ctxs["f32"]
     gf = grid_spec(16, False)
