@@ -499,9 +499,13 @@ int octree_samples(sdf_ctx ctx, const void *rho_moving, const void *w_moving, co
  *   spec_fixed: output of sdf_spectrum; g_fixed N^3 or N^2 x 1 with N in
  *   {8, 16, 32, 64, 96, 128}; width in [2, 8]; 0 <= m <= 2^30 (m = 0 scores 0).
  *   quats (host): n_rot x 4 FP64.
- * Device workspace: about 768 MiB per batch of rotations at N = 128 (the
- * oversampled-grid buffers, one N^d grid and the binned samples, 6 reals
- * each, per rotation of the batch), at least one rotation's worth.
+ * Device workspace: up to 4 GiB per batch of rotations (the oversampled-grid
+ * buffers, one N^d grid, the binned samples, 6 reals each, and for FP32 3D
+ * peaks at N = 64 and 128 half a grid of folded spectra, per rotation of the
+ * batch; about 60 rotations per batch at N = 128), at least one rotation's
+ * worth.  FP32 3D peaks at N = 64 and 128 run the inverse transform and the
+ * peak search through score_rotations' kernels (rotation pairs folded into
+ * one complex transform); the other cases through the plain ones.
  * Errors: SDF_EINVAL, SDF_EUNSUPPORTED (N), SDF_ENOMEM, SDF_EHIP. */
 int score_rotations_nfft(sdf_ctx ctx, const void *spec_fixed, const sdf_grid *g_fixed,
                          const void *pos, const void *c, int64_t m, int width,

@@ -815,7 +815,7 @@ int direct_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const double*
 
 // Nonequispaced route: batches of rotations through the type-1 transform of
 // the given samples, then the plain path's inverse FFT and peak (or real part).
-constexpr size_t kNfftBudget = size_t(768) << 20;  // per-batch workspace of the route
+constexpr size_t kNfftBudget = size_t(4096) << 20;  // per-batch workspace of the route
 
 template <typename T>
 int nfft_impl(sdf_ctx ctx, const void* spec, const sdf_grid* gf, const void* pos, const void* c, int64_t m, int w,
