@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libsdfdock.so")
 ARCH = os.environ.get("SDF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["abi.cpp", "kernels_sdf.hip", "kernels_plain.hip", "kernels_fused.hip", "kernels_grad.hip",
-           "kernels_topk.hip", "kernels_nfft.hip"]
+           "kernels_topk.hip", "kernels_nfft.hip", "kernels_scan.hip"]
 
 
 def hipcc() -> str:

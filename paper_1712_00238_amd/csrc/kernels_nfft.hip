@@ -14,7 +14,6 @@
 // 8^3 (planar 8^2) block in flat block order, Morton order within a block.
 #include <hip/hip_runtime.h>
 
-#include <hipcub/hipcub.hpp>
 
 #include <type_traits>
 
@@ -1174,9 +1173,7 @@ bool use_lines(bool planar, size_t elem) { return !planar && elem == sizeof(floa
 NfftWs nfft_ws_layout(int64_t m, int batch, int N, bool planar, size_t elem) {
     const TileShape ts = tile_shape(2 * N, planar, use_lines(planar, elem));
     const int64_t nb = int64_t(ts.ntx) * ts.nty * ts.ntz * batch;
-    size_t temp_bytes = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, static_cast<const int*>(nullptr),
-                                           static_cast<int*>(nullptr), int(nb));
+    const size_t temp_bytes = scan_temp_bytes(int(nb));
     const size_t nbi = size_t(nb) * sizeof(int), ns = size_t(m) * size_t(batch);
     NfftWs L{};
     size_t off = 0;
@@ -1212,9 +1209,7 @@ size_t al256(size_t v) { return (v + 255) / 256 * 256; }
 OctWs oct_ws_layout(int nm, bool planar, size_t elem) {
     const int64_t K = planar ? int64_t(nm) * nm : int64_t(nm) * nm * nm;
     const int nblk = int(K / (planar ? 64 : 512));
-    size_t temp_bytes = 0;
-    (void)hipcub::DeviceScan::ExclusiveSum(nullptr, temp_bytes, static_cast<const int*>(nullptr),
-                                           static_cast<int*>(nullptr), nblk);
+    const size_t temp_bytes = scan_temp_bytes(nblk);
     OctWs L{};
     size_t off = 0;
     L.coef = off;
@@ -1264,8 +1259,7 @@ hipError_t launch_octree(const void* rho_m, const T* w_m, int nm, bool planar, d
     }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t tb = L.temp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(base + L.temp, tb, counts, offsets, nblk, s);
+    e = launch_exclusive_scan(counts, offsets, nblk, base + L.temp, s);
     if (e != hipSuccess) return e;
     if (planar) {
         hipLaunchKernelGGL((octree_kernel<T, 2, true>), dim3(nblk), dim3(64), 0, s, coef, nm, amax, tl, max_level,
@@ -1327,8 +1321,7 @@ hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R,
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t tb = L.temp_bytes;
-    e = hipcub::DeviceScan::ExclusiveSum(base + L.temp, tb, counts, offsets, int(nb), s);
+    e = launch_exclusive_scan(counts, offsets, int(nb), base + L.temp, s);
     if (e != hipSuccess) return e;
     if (m > 0) {
         const dim3 g(unsigned((m + 255) / 256), unsigned(batch));

@@ -31,7 +31,6 @@
 //   G = exp(-(r - 1)^2 / (2 sigma^2)),  P = (1 - i r)^2 outside, (1 + i r)^2 inside,
 // so a pair costs one reciprocal square root, one exponential and one
 // reciprocal, with no trigonometric calls.
-#include <hipcub/hipcub.hpp>
 
 #include "common.hpp"
 #include "launch.hpp"
@@ -688,10 +687,7 @@ struct SdfWs {
 inline size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 inline SdfWs sdf_ws_layout(int64_t n) {
     SdfWs L{};
-    size_t temp_bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, temp_bytes, static_cast<const unsigned*>(nullptr),
-                                             static_cast<unsigned*>(nullptr), static_cast<const int*>(nullptr),
-                                             static_cast<int*>(nullptr), int(n), 0, 30);
+    const size_t temp_bytes = sort_temp_bytes(n);
     const int64_t ntile = (n + kSdfTile - 1) / kSdfTile;
     size_t off = 0;
     L.keys_in = off;
@@ -734,13 +730,13 @@ hipError_t prepare_tiles(const double* q, const double* n, const double* w, int6
                        g.oz - 4 * g.h, 1024.0 / ext, keys_in, vals_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    size_t temp_bytes = L.temp_bytes;
-    e = hipcub::DeviceRadixSort::SortPairs(base + L.temp, temp_bytes, keys_in, keys_out, vals_in, vals_out, int(ns),
-                                           0, 30, s);
+    unsigned* keys_sorted = nullptr;
+    int* order = nullptr;
+    e = launch_sort_pairs(keys_in, vals_in, keys_out, vals_out, ns, 30, base + L.temp, s, &keys_sorted, &order);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(sample_gather_kernel, dim3(gb), dim3(256), 0, s, q, n, w, vals_out, ns, qs, wn);
+    hipLaunchKernelGGL(sample_gather_kernel, dim3(gb), dim3(256), 0, s, q, n, w, order, ns, qs, wn);
     hipLaunchKernelGGL(tile_box_kernel, dim3(unsigned((ntile + 63) / 64)), dim3(64), 0, s, qs, ns, ntile, box);
-    *st = SampleTiles{qs, wn, vals_out, box, ntile};
+    *st = SampleTiles{qs, wn, order, box, ntile};
     return hipGetLastError();
 }
 

@@ -185,6 +185,18 @@ hipError_t launch_nfft_modes(const T* pos, const void* c, int64_t m, const T* R,
                              int w, const T* inv, const void* spec, void* fine, void* out, void* ws, hipStream_t s,
                              bool tiled = false);
 
+// ---- exclusive prefix sum of n ints (out may not alias in); temp holds
+// scan_temp_bytes(n)
+size_t scan_temp_bytes(int64_t n);
+hipError_t launch_exclusive_scan(const int* in, int* out, int64_t n, void* temp, hipStream_t s);
+// ---- stable sort of (key, value) pairs by the low `bits` bits of the keys,
+// least-significant digit first over 8-bit digits, ping-ponging between the
+// given buffers; *keys_sorted / *vals_sorted name the buffers holding the
+// result.  temp holds sort_temp_bytes(n).
+size_t sort_temp_bytes(int64_t n);
+hipError_t launch_sort_pairs(unsigned* keys, int* vals, unsigned* keys_alt, int* vals_alt, int64_t n, int bits,
+                             void* temp, hipStream_t s, unsigned** keys_sorted, int** vals_sorted);
+
 // ---- top-k
 template <typename T>
 hipError_t launch_topk(const T* scores, int64_t n, int64_t k, void* ws, int32_t* idx_out, hipStream_t s);
