@@ -89,6 +89,39 @@ def test_sdf_build_sample_tile_edges(ctxs, dtype, count):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_sdf_build_crowded_morton_keys_repeatable(ctxs, dtype):
+    """12 000 samples on a small sphere, a third of them exact copies of
+    others: many share a Morton key, across several tiles of the sort (4 096
+    keys each), and exact copies tie at the nearest-sample test.  The build
+    matches the oracle and two builds are bit for bit equal (the sort keeps
+    equal keys in input order, and every sum runs in that order)."""
+    import torch
+    ctx = ctxs[dtype]
+    rng = np.random.default_rng(91)
+    v = rng.normal(size=(8000, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    dup = rng.integers(0, 8000, 4000)
+    v = np.concatenate([v, v[dup]])
+    perm = rng.permutation(len(v))
+    v = v[perm]
+    s = shapes.PointSamples(3.0 * v + 0.2, v.copy(), np.full(len(v), 4.0 * np.pi * 9.0 / len(v)))
+    grid = C.GridSpec((12, 12, 12), (-5.5, -5.5, -5.5), 1.0)
+    params = C.SDFParams(xi_floor=0.25)
+    flush_print("sdf_build crowded keys", dtype, len(v))
+    a = ctx.sdf_build(s.q, s.n, s.w, grid, params)
+    b = ctx.sdf_build(s.q, s.n, s.w, grid, params)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    rel, band = (1e-10, 1e-10) if dtype == "f64" else (2e-5, 2e-5)
+    # samples 0.05 cell apart put one within the FP32 band of the truncation
+    # sphere at about a tenth of the nodes; those are held to the edge terms'
+    # magnitude, every other node to rel
+    rep = sdf_compare(to_np(a), s, grid, params, rel, band, max_ambiguous_frac=0.15)
+    flush_print(rep)
+    assert rep["ok"], rep
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("order", [0, 1])
 @pytest.mark.parametrize("near_tie", [False, True])
 def test_sdf_build_nearest_sample_tie_rule(ctxs, dtype, order, near_tie):
