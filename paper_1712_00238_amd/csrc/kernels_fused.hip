@@ -601,13 +601,18 @@ constexpr int pencil_jobs() {
 
 // pair-grouped layout: rows ky = 0 .. N/2 (each with its partner row -ky),
 // every aligned 16-position block
+// (instantiated for every size, used only for N = 64 and 128)
+template <int N>
+constexpr int pencil_blocks16() {
+    return N >= 16 ? N / 16 : 1;
+}
 template <int N>
 constexpr int pencil_jobs_grouped() {
-    return (N / 2 + 1) * (N / 16);
+    return (N / 2 + 1) * pencil_blocks16<N>();
 }
 template <int N>
 __device__ __forceinline__ PencilJob pencil_job_grouped(int j) {
-    return PencilJob{j / (N / 16), (j % (N / 16)) * 16};
+    return PencilJob{j / pencil_blocks16<N>(), (j % pencil_blocks16<N>()) * 16};
 }
 
 // Rotation (within its group of GR) of the line group q = l / W, for lines
@@ -1254,7 +1259,7 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
     cf pre[kFast ? N / 8 : 1];
     if constexpr (kFast) {
         const int x = threadIdx.x % N, jb = threadIdx.x / N;
-        if (blockIdx.x < items && jb < 8) {
+        if (int(blockIdx.x) < items && jb < 8) {
             const cf* src = src_of(blockIdx.x);
             const int px = grouped ? col_pos<N>(x) : x;
 #pragma unroll
@@ -1337,7 +1342,7 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
     si[threadIdx.x] = bi;
     __syncthreads();
     for (int off = kFinishBlock / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off && better(sv[threadIdx.x + off], si[threadIdx.x + off], sv[threadIdx.x], si[threadIdx.x])) {
+        if (int(threadIdx.x) < off && better(sv[threadIdx.x + off], si[threadIdx.x + off], sv[threadIdx.x], si[threadIdx.x])) {
             sv[threadIdx.x] = sv[threadIdx.x + off];
             si[threadIdx.x] = si[threadIdx.x + off];
         }

@@ -261,8 +261,8 @@ __device__ __forceinline__ void block_argmax(T& v, int& idx) {
     sv[threadIdx.x] = v;
     si[threadIdx.x] = idx;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
+    for (int off = int(blockDim.x) / 2; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off) {
             T ov = sv[threadIdx.x + off];
             int oi = si[threadIdx.x + off];
             if (better(ov, oi, sv[threadIdx.x], si[threadIdx.x])) {
