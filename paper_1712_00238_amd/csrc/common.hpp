@@ -58,6 +58,16 @@ __device__ __forceinline__ void bspline3_weights(T f, T w[4]) {
     w[2] = T(2) / T(3) - g * g + T(0.5) * g * g * g;        // beta(1 - f)
     w[3] = f3 * T(1.0 / 6.0);                              // beta(2 - f)
 }
+// Six times the same 4 weights (callers fold the 1/6 into their scale).
+template <typename T>
+__device__ __forceinline__ void bspline3_weights6(T f, T w[4]) {
+    const T g = T(1) - f;
+    const T f2 = f * f, g2 = g * g;
+    w[0] = g2 * g;                            // 6 beta(1 + f)
+    w[1] = T(3) * f2 * f + (T(4) - T(6) * f2);  // 6 beta(f)
+    w[2] = T(3) * g2 * g + (T(4) - T(6) * g2);  // 6 beta(1 - f)
+    w[3] = f2 * f;                            // 6 beta(2 - f)
+}
 // d/dy of beta(node - y) for the same 4 nodes: -beta'(node - y).
 template <typename T>
 __device__ __forceinline__ void bspline3_dweights(T f, T d[4]) {

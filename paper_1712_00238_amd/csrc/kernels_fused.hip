@@ -367,6 +367,9 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
             const float y0y = Rp[3 + b1] * u1 + Rp[3 + b2] * u2 + dy * u0;
             const float y0z = Rp[6 + b1] * u1 + Rp[6 + b2] * u2 + dzs * u0;
             const int k0 = i1 * kstride[b1] + i2 * kstride[b2];
+            // the three weight factors are computed six times too large (the
+            // B-spline's 1/6 left out) and S6 = S / 216 restores them
+            const float S6 = S * (1.f / 216.f);
             cf cnext = gload(c, k0 + lo * sax);
             for (int ka = lo; ka <= hi; ++ka) {
                 const cf ck = cnext;
@@ -377,14 +380,14 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
                 if (!(ad < 2.f)) continue;
                 const float yx = y0x + fk * dx;
                 const float yy = y0y + fk * dy;
-                float wz;
-                if (ad < 1.f) wz = 2.f / 3.f - ad * ad + 0.5f * ad * ad * ad;
-                else { const float b = 2.f - ad; wz = b * b * b * (1.f / 6.f); }
-                const float sw = wz * S;
+                // 6 beta(ad) = (2 - ad)^3 - 4 (1 - ad)^3_+, without a branch
+                const float bz = 2.f - ad, az = fmaxf(1.f - ad, 0.f);
+                const float wz6 = bz * bz * bz - 4.f * (az * az * az);
+                const float sw = wz6 * S6;
                 const float fx = floorf(yx), fy = floorf(yy);
                 float wx[4], wy[4], xr[4], xi[4];
-                bspline3_weights(yx - fx, wx);
-                bspline3_weights(yy - fy, wy);
+                bspline3_weights6(yx - fx, wx);
+                bspline3_weights6(yy - fy, wy);
 #pragma unroll
                 for (int a = 0; a < 4; ++a) {
                     xr[a] = ck.re * sw * wx[a];
