@@ -856,37 +856,59 @@ __device__ __forceinline__ void pencil_item_fast(int n_rot, const FusedRot* __re
     // wave-uniform descriptor.  The other waves load the next item.
     cf pre[PS::kPipe ? 2 : 1][R1];
     const bool loader = PS::kPipe && wave >= PS::IW && nx.valid;
-    if (!PS::kPipe || wave < PS::IW) {
-        for (int wv = wave; wv < PS::IW; wv += kPencilBlock / 64) {
-            const int l = wv * 8 + (lane & 7), j = lane >> 3;
-            cf v[R1];
+    // first inverse pass (radix R1) of the lines of wave wv, in place
+    auto inv_first = [&](int wv) {
+        const int l = wv * 8 + (lane & 7), j = lane >> 3;
+        cf v[R1];
 #pragma unroll
-            for (int r = 0; r < R1; ++r) v[r] = buf[(j + 8 * r) * NLP + l];
-            compiler_fence();
-            dftR<float, 1, R1>(v);
+        for (int r = 0; r < R1; ++r) v[r] = buf[(j + 8 * r) * NLP + l];
+        compiler_fence();
+        dftR<float, 1, R1>(v);
 #pragma unroll
-            for (int r = 0; r < R1; ++r) buf[(j * R1 + r) * NLP + l] = v[r];
-            compiler_fence();
-            const int cc = l % W, q = (wv * 8) / W, p = q / 2, tt = q % 2;
-            const int pair = g0 / 2 + p;
-            const bool store = pair < (n_rot + 1) / 2;
-            const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(packed + int64_t(store ? pair : 0) * G, kGridBytes);
+        for (int r = 0; r < R1; ++r) buf[(j * R1 + r) * NLP + l] = v[r];
+        compiler_fence();
+    };
+    // second inverse pass (radix 8), butterflies m0, m0 + ms, .. of the lines
+    // of wave wv, written to global memory
+    auto inv_last = [&](int wv, int m0, int ms) {
+        const int l = wv * 8 + (lane & 7), j = lane >> 3;
+        const int cc = l % W, q = (wv * 8) / W, p = q / 2, tt = q % 2;
+        const int pair = g0 / 2 + p;
+        const bool store = pair < (n_rot + 1) / 2;
+        const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(packed + int64_t(store ? pair : 0) * G, kGridBytes);
 #pragma unroll
-            for (int m = 0; m < NB / 8; ++m) {
-                const int jj = j + 8 * m;
-                cf uu[8];
+        for (int m = m0; m < NB / 8; m += ms) {
+            const int jj = j + 8 * m;
+            cf uu[8];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) uu[r] = buf[(jj + NB * r) * NLP + l];
+            for (int r = 0; r < 8; ++r) uu[r] = buf[(jj + NB * r) * NLP + l];
 #pragma unroll
-                for (int r = 1; r < 8; ++r) uu[r] = uu[r] * conj(tw[r * jj]);
-                dft8<float, 1>(uu);
-                if (store) {
-                    const uint32_t vo = uint32_t(((jj * N + kyt[tt]) * N + kx_of(tt, cc)) * int(sizeof(cf)));
+            for (int r = 1; r < 8; ++r) uu[r] = uu[r] * conj(tw[r * jj]);
+            dft8<float, 1>(uu);
+            if (store) {
+                const uint32_t vo = uint32_t(((jj * N + kyt[tt]) * N + kx_of(tt, cc)) * int(sizeof(cf)));
 #pragma unroll
-                    for (int r = 0; r < 8; ++r)
-                        buffer_store_cf(uu[r], rs, vo, uint32_t(NB * r * N * N * sizeof(cf)));
-                }
+                for (int r = 0; r < 8; ++r) buffer_store_cf(uu[r], rs, vo, uint32_t(NB * r * N * N * sizeof(cf)));
             }
+        }
+    };
+    if constexpr (PS::kPipe && NB / 8 == 2) {
+        // every wave loads one chunk of the next item; the line groups' waves
+        // run the first pass, and the second pass's two butterfly sets are
+        // split between a line group's wave and one of the others.  The loads
+        // stay in flight through the barriers (they wait for LDS operations
+        // only)
+        if (nx.valid) pencil_load_chunk<N, GR, MODES>(slabs, rots, n_rot, nx.job, nx.g0, wave, lane, pre[0]);
+        if (wave < PS::IW) inv_first(wave);
+        __syncthreads();
+        inv_last(wave % PS::IW, wave < PS::IW ? 0 : 1, 2);
+        __syncthreads();  // the inverse passes are done with buf
+        if (nx.valid) pencil_store_raw<N, GR, MODES>(buf, wave, lane, pre[0]);
+        return;
+    } else if (!PS::kPipe || wave < PS::IW) {
+        for (int wv = wave; wv < PS::IW; wv += kPencilBlock / 64) {
+            inv_first(wv);
+            inv_last(wv, 0, 1);
         }
     } else if (loader) {
 #pragma unroll
