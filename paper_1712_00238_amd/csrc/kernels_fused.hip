@@ -316,6 +316,10 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
     const int nb16 = n_m >> 4;
     const float u0 = -half;
     const int lane = threadIdx.x & 63;
+    // the coefficients through a buffer descriptor: a 32-bit offset stepped
+    // along the line, and the read one past a run's last sample needs no
+    // branch (its value is not used; past the end of c it reads zeros)
+    const __amdgpu_buffer_rsrc_t crs = buffer_rsrc(c, uint32_t(pairs) * uint32_t(n_m) * uint32_t(sizeof(cf)));
     for (int c0 = 0; c0 < pairs; c0 += kLineChunk) {
         if (threadIdx.x == 0) *nlist = 0;
         __syncthreads();
@@ -370,10 +374,13 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
             // the three weight factors are computed six times too large (the
             // B-spline's 1/6 left out) and S6 = S / 216 restores them
             const float S6 = S * (1.f / 216.f);
-            cf cnext = gload(c, k0 + lo * sax);
+            uint32_t coff = uint32_t(k0 + lo * sax) * uint32_t(sizeof(cf));
+            const uint32_t cstep = uint32_t(sax) * uint32_t(sizeof(cf));
+            cf cnext = buffer_load_cf(crs, coff, 0);
             for (int ka = lo; ka <= hi; ++ka) {
                 const cf ck = cnext;
-                if (ka < hi) cnext = gload(c, k0 + (ka + 1) * sax);
+                coff += cstep;
+                cnext = buffer_load_cf(crs, coff, 0);
                 const float fk = float(ka);
                 const float yz = y0z + fk * dzs;
                 const float ad = fabsf(zc - yz);
