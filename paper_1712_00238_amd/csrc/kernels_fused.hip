@@ -692,21 +692,25 @@ __device__ __forceinline__ void pencil_load_chunk(const cf* __restrict__ slabs, 
 // kz (NL + 8) + l).
 //  A  forward radix-R1 pass along z.  With GR = 2 the item's raw columns are
 //     already in LDS (rows j R1 + r of line l hold kz = j + 8 r), loaded
-//     during the previous item's inverse passes by the waves those passes
-//     leave idle; with GR = 4 each wave loads its chunks here;
+//     during the previous item's inverse passes; with GR = 4 each wave loads
+//     its chunks here;
 //  B  forward radix-8 pass in place, times the fixed spectrum;
 //  F  Hermitian folding in place: the unit (pair, column, kz) reads the k
 //     lines a0, b0 at kz and the -k lines a1, b1 at -kz and writes Z to a0
 //     at kz and a1 at -kz, positions no other unit touches;
 //  I  inverse radix-R1 and radix-8 passes over the Z lines, 8 lines per
-//     wave (no block barrier between them), the last pass writing global
-//     memory.  With GR = 2 half of the waves run them while the other half
-//     load the next item's columns, which are written to LDS after a barrier.
+//     wave, the last pass writing global memory.  With GR = 2 the next
+//     item's columns are loaded meanwhile and written to LDS after a barrier:
+//     at N = 128 every wave loads one chunk, the 4 line groups' waves run the
+//     first pass, and after a barrier the second pass's two butterfly sets of
+//     each line group go to its wave and to one of the other 4; otherwise the
+//     line groups' waves run both passes (no block barrier between them)
+//     while the other 4 waves load two chunks each.
 // The spectrum values of a thread's pass-B units (GR = 2: two units of 8
 // values) are kept in registers, and consecutive items of a block that share
 // the pencil job and the spectra reuse them.
-// GR = 2 with 16-column tiles: the inverse passes occupy GR W / 8 = 4 of the
-// 8 waves, and the other 4 load the next item's 8 chunks, two each
+// GR = 2 with 16-column tiles: the Z lines form GR W / 8 = 4 line groups of
+// 8 lines, one per wave of the first 4, and the next item has 8 chunks
 template <int N, int GR>
 constexpr bool pencil_pipe() {
     if constexpr (pencil_width<N>() != 16 || GR != 2) {
