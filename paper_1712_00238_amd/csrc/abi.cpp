@@ -941,6 +941,10 @@ int sdf_ctx_create(sdf_ctx* out, int device, sdf_dtype dtype, size_t workspace_c
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         ctx->num_cu = prop.multiProcessorCount;
     ctx->scratch_ptr = scratch_address(device, &ctx->scratch_err);
+    {
+        DeviceGuard dg(device);
+        if (dg.ok) sdf::fused_query_occupancy();
+    }
     *out = ctx;
     return SDF_OK;
 }

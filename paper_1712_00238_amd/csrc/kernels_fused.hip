@@ -52,7 +52,12 @@ namespace {
 using cf = cplx<float>;
 
 constexpr int kSlabBlock = 1024;
-constexpr int kIslabWaves = kSlabBlock / 64;  // argmax partials per (rotation, slab)
+// Inverse slab pass: the fast transforms of N = 64 use 512 threads (8 lines
+// of 8 values per thread in each direction), so that size runs two blocks per
+// compute unit instead of one block with half of its waves idle.  One argmax
+// partial per wave and (rotation, slab).
+constexpr int islab_block(int N) { return N == 64 ? 512 : kSlabBlock; }
+constexpr int islab_waves(int N) { return islab_block(N) / 64; }
 constexpr int kPencilBlock = 512;
 constexpr int kFinishBlock = 256;
 constexpr int kPrepBlocks = 64;
@@ -1281,8 +1286,9 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
 
 // Work item = (z-slab, rotation pair), z fastest.
 template <int N, int P>
-__global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __restrict__ packed, int nz, int n_rot,
-                                                                float* __restrict__ pval, int* __restrict__ pidx) {
+__global__ __launch_bounds__(islab_block(N)) void islab_peak_kernel(const cf* __restrict__ packed, int nz, int n_rot,
+                                                                    float* __restrict__ pval, int* __restrict__ pidx) {
+    constexpr int B = islab_block(N), NW = islab_waves(N);
     using Plan = typename FusedRadix<N, P>::type;
     constexpr bool kFast = SlabLayout<N>::kFast;
     __shared__ cf slab[kFast ? N * (N + N / 16 + 4) : N * N];
@@ -1314,11 +1320,11 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
             islab_fft_argmax_fast<N>(pre, nx < items ? src_of(nx) : nullptr, slab, tw, zoff, va, ia, vb, ib,
                                      grouped);
         } else {
-            stage_to_lds<N * N / 2, kSlabBlock>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
+            stage_to_lds<N * N / 2, B>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
             __syncthreads();
             lds_fft_lines<float, N, 1, true, Plan>(slab, N, 1, N, tw);   // along y
             lds_fft_lines<float, N, 1, false, Plan>(slab, 1, N, N, tw);  // along x
-            for (int i = threadIdx.x; i < N * N; i += kSlabBlock) {
+            for (int i = threadIdx.x; i < N * N; i += B) {
                 const cf v = slab[i];
                 take(v.re, zoff + i, va, ia);
                 take(v.im, zoff + i, vb, ib);
@@ -1330,12 +1336,12 @@ __global__ __launch_bounds__(kSlabBlock) void islab_peak_kernel(const cf* __rest
         wave_argmax(vb, ib);
         const int lane = threadIdx.x % warpSize, wid = threadIdx.x / warpSize;
         if (lane == 0) {
-            const int64_t at = (int64_t(2 * pair) * nz + z) * kIslabWaves + wid;
+            const int64_t at = (int64_t(2 * pair) * nz + z) * NW + wid;
             pval[at] = va;
             pidx[at] = ia;
             if (2 * pair + 1 < n_rot) {
-                pval[at + int64_t(nz) * kIslabWaves] = vb;
-                pidx[at + int64_t(nz) * kIslabWaves] = ib;
+                pval[at + int64_t(nz) * NW] = vb;
+                pidx[at + int64_t(nz) * NW] = ib;
             }
         }
     }
@@ -1369,9 +1375,10 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
     }
     float bv = -INFINITY;
     int bi = 0x7fffffff;
-    for (int i = threadIdx.x; i < nz * kIslabWaves; i += kFinishBlock) {
-        const float v = pval[int64_t(rot) * nz * kIslabWaves + i];
-        const int id = pidx[int64_t(rot) * nz * kIslabWaves + i];
+    constexpr int NW = islab_waves(N);
+    for (int i = threadIdx.x; i < nz * NW; i += kFinishBlock) {
+        const float v = pval[int64_t(rot) * nz * NW + i];
+        const int id = pidx[int64_t(rot) * nz * NW + i];
         if (better(v, id, bv, bi)) { bv = v; bi = id; }
     }
     sv[threadIdx.x] = bv;
@@ -1519,9 +1526,9 @@ FusedLayout fused_layout(const FusedPlan& fp, void* ws) {
     L.packed = reinterpret_cast<cf*>(base + off);
     off += align256(sizeof(cf) * G * ((fp.batch + 1) / 2));
     L.pval = reinterpret_cast<float*>(base + off);
-    off += align256(sizeof(float) * nz * kIslabWaves * fp.batch);
+    off += align256(sizeof(float) * nz * islab_waves(fp.N) * fp.batch);
     L.pidx = reinterpret_cast<int*>(base + off);
-    off += align256(sizeof(int) * nz * kIslabWaves * fp.batch);
+    off += align256(sizeof(int) * nz * islab_waves(fp.N) * fp.batch);
     L.nbbuf = reinterpret_cast<double*>(base + off);
     off += align256(sizeof(double) * 27 * fp.batch);
     L.total = off;
@@ -1531,6 +1538,20 @@ FusedLayout fused_layout(const FusedPlan& fp, void* ws) {
 unsigned persistent_grid(int items, int cap) {
     if (cap <= 0 || items <= cap) return unsigned(items > 0 ? items : 1);
     return unsigned(cap);
+}
+
+// Inverse slab blocks resident per compute unit (N = 64: four of 512 threads),
+// from the occupancy query, so that a persistent grid never holds blocks that
+// wait for others to finish.
+template <int N, int P>
+int islab_blocks_per_cu() {
+    static const int n = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, islab_peak_kernel<N, P>, islab_block(N), 0) != hipSuccess)
+            b = 1;
+        return b < 1 ? 1 : b;
+    }();
+    return n;
 }
 
 template <int N, int P>
@@ -1557,8 +1578,9 @@ hipError_t fused_impl(const FusedPlan& fp, const FusedRot* rots, int n_rot, cons
         else
             launch_k(kt, "pencil", pencil_kernel<N, N, 2, P>, g2, b2, s, rots, jobs, n_rot, L.slabs, L.packed);
     }
-    launch_k(kt, "islab_peak", islab_peak_kernel<N, P>, dim3(persistent_grid(nz * npair, fp.max_wgs)),
-             dim3(kSlabBlock), s, L.packed, nz, n_rot, L.pval, L.pidx);
+    launch_k(kt, "islab_peak", islab_peak_kernel<N, P>,
+             dim3(persistent_grid(nz * npair, fp.max_wgs * islab_blocks_per_cu<N, P>())), dim3(islab_block(N)), s,
+             L.packed, nz, n_rot, L.pval, L.pidx);
     const dim3 g4{unsigned(fp.planar ? 1 : 3), unsigned(n_rot), 1u};
     launch_k(kt, "finish", finish_slab_kernel<N>, g4, dim3(kFinishBlock), s, L.packed, nz, L.pval, L.pidx, L.nbbuf,
              rots, jobs);
@@ -1615,9 +1637,9 @@ ModesLayout modes_layout(int N, int nb, void* ws) {
     L.packed = reinterpret_cast<cf*>(base + off);
     off += align256(sizeof(cf) * G * ((nb + 1) / 2));
     L.pval = reinterpret_cast<float*>(base + off);
-    off += align256(sizeof(float) * N * kIslabWaves * size_t(nb));
+    off += align256(sizeof(float) * N * islab_waves(N) * size_t(nb));
     L.pidx = reinterpret_cast<int*>(base + off);
-    off += align256(sizeof(int) * N * kIslabWaves * size_t(nb));
+    off += align256(sizeof(int) * N * islab_waves(N) * size_t(nb));
     L.nbbuf = reinterpret_cast<double*>(base + off);
     off += align256(sizeof(double) * 27 * size_t(nb));
     L.rots = reinterpret_cast<FusedRot*>(base + off);
@@ -1637,8 +1659,9 @@ hipError_t modes_peaks_impl(const cf* modes, int nb, int n_m, float* score, int3
     const int items2 = pencil_jobs_grouped<N>() * ((nb + 1) / 2);
     hipLaunchKernelGGL(pencil_modes_kernel<N>, dim3(persistent_grid(items2, 2 * num_cu)), dim3(kPencilBlock), 0, s,
                        L.rots, nb, modes, L.packed);
-    hipLaunchKernelGGL((islab_peak_kernel<N, 0>), dim3(persistent_grid(N * ((nb + 1) / 2), num_cu)), dim3(kSlabBlock),
-                       0, s, L.packed, N, nb, L.pval, L.pidx);
+    hipLaunchKernelGGL((islab_peak_kernel<N, 0>),
+                       dim3(persistent_grid(N * ((nb + 1) / 2), num_cu * islab_blocks_per_cu<N, 0>())),
+                       dim3(islab_block(N)), 0, s, L.packed, N, nb, L.pval, L.pidx);
     hipLaunchKernelGGL(finish_slab_kernel<N>, dim3(3u, unsigned(nb)), dim3(kFinishBlock), 0, s, L.packed, N, L.pval,
                        L.pidx, L.nbbuf, L.rots, L.job);
     hipLaunchKernelGGL(finish_rot_kernel, dim3(unsigned((nb + 63) / 64)), dim3(64), 0, s, L.nbbuf, L.rots, L.job, nb);
@@ -1648,6 +1671,24 @@ hipError_t modes_peaks_impl(const cf* modes, int nb, int n_m, float* score, int3
 }  // namespace
 
 size_t fused_workspace_bytes(const FusedPlan& fp) { return fused_layout(fp, nullptr).total; }
+
+namespace {
+template <int N>
+void query_islab() {
+    (void)islab_blocks_per_cu<N, 0>();
+    (void)islab_blocks_per_cu<N, 1>();
+    (void)islab_blocks_per_cu<N, 2>();
+}
+}  // namespace
+
+void fused_query_occupancy() {
+    query_islab<8>();
+    query_islab<16>();
+    query_islab<32>();
+    query_islab<64>();
+    query_islab<96>();
+    query_islab<128>();
+}
 
 bool modes_peaks_supported(int N, bool planar) { return fused_pair_grouped(N, planar); }
 

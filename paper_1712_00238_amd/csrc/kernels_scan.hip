@@ -31,6 +31,7 @@ constexpr int kSortBlock = 256;
 constexpr int kSortRounds = 16;
 constexpr int kSortTile = kSortBlock * kSortRounds;  // keys per block
 constexpr int kDigits = 256;
+static_assert(kScanBlock == 4 * 64, "block_exclusive sums the totals of four waves");
 
 size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 

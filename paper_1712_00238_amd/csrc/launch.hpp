@@ -130,6 +130,9 @@ struct FusedPlan {
     int max_wgs;       // persistent grid size cap (0 = one work item per block)
 };
 size_t fused_workspace_bytes(const FusedPlan& fp);
+// occupancy of the fused kernels, queried once per process (the context's
+// creation calls it, before any launch sequence can be captured)
+void fused_query_occupancy();
 // 3D grids of N = 64 and 128 pass grids between the fused kernels with their
 // x columns in pair-grouped order (each aligned block of 16 positions holds
 // 8 columns kx and their negatives); the spread slabs go from the spread to
