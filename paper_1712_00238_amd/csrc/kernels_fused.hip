@@ -52,12 +52,13 @@ namespace {
 using cf = cplx<float>;
 
 constexpr int kSlabBlock = 1024;
-// Inverse slab pass: the fast transforms of N = 64 use 512 threads (8 lines
-// of 8 values per thread in each direction), so that size runs two blocks per
-// compute unit instead of one block with half of its waves idle.  One argmax
+// Threads of the slab kernels (spread and inverse slab pass).  The fast slab
+// transforms give each thread 8 lines' worth of one radix pass, so N = 64 uses
+// 512 threads: more blocks per compute unit instead of one block with half of
+// its waves idle in the transforms.  The inverse slab pass writes one argmax
 // partial per wave and (rotation, slab).
-constexpr int islab_block(int N) { return N == 64 ? 512 : kSlabBlock; }
-constexpr int islab_waves(int N) { return islab_block(N) / 64; }
+constexpr int slab_block(int N) { return N == 64 ? 512 : kSlabBlock; }
+constexpr int islab_waves(int N) { return slab_block(N) / 64; }
 constexpr int kPencilBlock = 512;
 constexpr int kFinishBlock = 256;
 constexpr int kPrepBlocks = 64;
@@ -253,6 +254,7 @@ template <int N>
 __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRot& fr, const cf* __restrict__ c,
                                             int n_m, float S, int z, bool planar, int* __restrict__ list,
                                             int* __restrict__ nlist) {
+    constexpr int B = slab_block(N);
     // reflected rotation: positions y_k = Rp (k - n_m / 2), Rp = -R
     float Rp[9];
 #pragma unroll
@@ -260,7 +262,7 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
     const float half = 0.5f * float(n_m);
     if (planar) {
         const int K = n_m * n_m;
-        for (int k = threadIdx.x; k < K; k += kSlabBlock) {
+        for (int k = threadIdx.x; k < K; k += B) {
             const cf ck = gload(c, k);
             const float bx = float(k % n_m) - half, by = float(k / n_m) - half;
             const float yx = Rp[0] * bx + Rp[1] * by;
@@ -329,8 +331,8 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
         if (threadIdx.x == 0) *nlist = 0;
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < kLineChunk / kSlabBlock; ++r) {
-            const int pidx = c0 + threadIdx.x + r * kSlabBlock;
+        for (int r = 0; r < kLineChunk / B; ++r) {
+            const int pidx = c0 + threadIdx.x + r * B;
             int entry = 0;
             bool ne = false;
             if (pidx < pairs) {
@@ -368,7 +370,7 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
         }
         __syncthreads();
         const int nl = *nlist;
-        for (int e = threadIdx.x; e < nl; e += kSlabBlock) {
+        for (int e = threadIdx.x; e < nl; e += B) {
             const int entry = list[e];
             const int i1 = entry & 127, i2 = (entry >> 7) & 127, lo = (entry >> 14) & 127, hi = entry >> 21;
             const float u1 = float(i1) - half, u2 = float(i2) - half;
@@ -528,9 +530,10 @@ x_done:
 
 // Work item = (z-slab, rotation), z fastest.
 template <int N, int P>
-__global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot* __restrict__ rots,
-                                                                 const FusedJob* __restrict__ jobs, int n_rot,
-                                                                 int planar, cf* __restrict__ slabs) {
+__global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedRot* __restrict__ rots,
+                                                                     const FusedJob* __restrict__ jobs, int n_rot,
+                                                                     int planar, cf* __restrict__ slabs) {
+    constexpr int B = slab_block(N);
     using L = SlabLayout<N>;
     using Plan = typename FusedRadix<N, P>::type;
     __shared__ int acc[L::kInts];
@@ -543,7 +546,7 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
     const int nz = planar ? 1 : N;
     const int items = nz * n_rot;
     if constexpr (L::kFast) {
-        for (int i = threadIdx.x; i < L::kInts; i += kSlabBlock) acc[i] = 0;  // later items clear as they store
+        for (int i = threadIdx.x; i < L::kInts; i += B) acc[i] = 0;  // later items clear as they store
     }
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
         // The scatter work of a slab follows the body's cross-section at its
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
         const FusedJob jb = jobs[fr.job];
         __syncthreads();  // previous item done with the slab
         if constexpr (!L::kFast) {
-            for (int i = threadIdx.x; i < L::kInts; i += kSlabBlock) acc[i] = 0;
+            for (int i = threadIdx.x; i < L::kInts; i += B) acc[i] = 0;
             __syncthreads();
         }
         spread_item<N>(acc, fr, static_cast<const cf*>(jb.c), jb.n_m, jb.scale[0], z, planar != 0, list, &nlist);
@@ -571,23 +574,23 @@ __global__ __launch_bounds__(kSlabBlock) void spread_slab_kernel(const FusedRot*
         } else {
             // planes -> interleaved complex, in place: read everything, then write
             cf* slab = reinterpret_cast<cf*>(acc);
-            constexpr int PER = (N * N + kSlabBlock - 1) / kSlabBlock;
+            constexpr int PER = (N * N + B - 1) / B;
             cf v[PER];
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
-                const int i = threadIdx.x + p * kSlabBlock;
-                if ((N * N) % kSlabBlock == 0 || i < N * N) v[p] = mk(float(acc[i]) * inv, float(acc[N * N + i]) * inv);
+                const int i = threadIdx.x + p * B;
+                if ((N * N) % B == 0 || i < N * N) v[p] = mk(float(acc[i]) * inv, float(acc[N * N + i]) * inv);
             }
             __syncthreads();
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
-                const int i = threadIdx.x + p * kSlabBlock;
-                if ((N * N) % kSlabBlock == 0 || i < N * N) slab[i] = v[p];
+                const int i = threadIdx.x + p * B;
+                if ((N * N) % B == 0 || i < N * N) slab[i] = v[p];
             }
             __syncthreads();
             lds_fft_lines<float, N, -1, false, Plan>(slab, 1, N, N, tw);  // along x
             lds_fft_lines<float, N, -1, true, Plan>(slab, N, 1, N, tw);   // along y
-            for (int i = threadIdx.x; i < N * N; i += kSlabBlock) out[i] = slab[i];
+            for (int i = threadIdx.x; i < N * N; i += B) out[i] = slab[i];
         }
     }
 }
@@ -1286,9 +1289,9 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
 
 // Work item = (z-slab, rotation pair), z fastest.
 template <int N, int P>
-__global__ __launch_bounds__(islab_block(N)) void islab_peak_kernel(const cf* __restrict__ packed, int nz, int n_rot,
+__global__ __launch_bounds__(slab_block(N)) void islab_peak_kernel(const cf* __restrict__ packed, int nz, int n_rot,
                                                                     float* __restrict__ pval, int* __restrict__ pidx) {
-    constexpr int B = islab_block(N), NW = islab_waves(N);
+    constexpr int B = slab_block(N), NW = islab_waves(N);
     using Plan = typename FusedRadix<N, P>::type;
     constexpr bool kFast = SlabLayout<N>::kFast;
     __shared__ cf slab[kFast ? N * (N + N / 16 + 4) : N * N];
@@ -1540,14 +1543,25 @@ unsigned persistent_grid(int items, int cap) {
     return unsigned(cap);
 }
 
-// Inverse slab blocks resident per compute unit (N = 64: four of 512 threads),
-// from the occupancy query, so that a persistent grid never holds blocks that
-// wait for others to finish.
+// Slab kernel blocks resident per compute unit (N = 64: two spread blocks
+// and four inverse slab blocks of 512 threads), from the occupancy query, so
+// that a persistent grid never holds blocks that wait for others to finish.
+template <int N, int P>
+int spread_blocks_per_cu() {
+    static const int n = [] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, spread_slab_kernel<N, P>, slab_block(N), 0) != hipSuccess)
+            b = 1;
+        return b < 1 ? 1 : b;
+    }();
+    return n;
+}
+
 template <int N, int P>
 int islab_blocks_per_cu() {
     static const int n = [] {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, islab_peak_kernel<N, P>, islab_block(N), 0) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, islab_peak_kernel<N, P>, slab_block(N), 0) != hipSuccess)
             b = 1;
         return b < 1 ? 1 : b;
     }();
@@ -1560,8 +1574,9 @@ hipError_t fused_impl(const FusedPlan& fp, const FusedRot* rots, int n_rot, cons
     const int nz = fp.planar ? 1 : N;
     const int npair = (n_rot + 1) / 2;
     const FusedLayout L = fused_layout(fp, ws);
-    launch_k(kt, "spread_slab", spread_slab_kernel<N, P>, dim3(persistent_grid(nz * n_rot, fp.max_wgs)),
-             dim3(kSlabBlock), s, rots, jobs, n_rot, fp.planar ? 1 : 0, L.slabs);
+    launch_k(kt, "spread_slab", spread_slab_kernel<N, P>,
+             dim3(persistent_grid(nz * n_rot, fp.max_wgs * spread_blocks_per_cu<N, P>())), dim3(slab_block(N)), s,
+             rots, jobs, n_rot, fp.planar ? 1 : 0, L.slabs);
     const int gr = fp.pencil_group;
     const int items2 = (fused_pair_grouped(N, fp.planar) ? pencil_jobs_grouped<N>() : pencil_jobs<N>()) *
                        ((n_rot + gr - 1) / gr);
@@ -1579,7 +1594,7 @@ hipError_t fused_impl(const FusedPlan& fp, const FusedRot* rots, int n_rot, cons
             launch_k(kt, "pencil", pencil_kernel<N, N, 2, P>, g2, b2, s, rots, jobs, n_rot, L.slabs, L.packed);
     }
     launch_k(kt, "islab_peak", islab_peak_kernel<N, P>,
-             dim3(persistent_grid(nz * npair, fp.max_wgs * islab_blocks_per_cu<N, P>())), dim3(islab_block(N)), s,
+             dim3(persistent_grid(nz * npair, fp.max_wgs * islab_blocks_per_cu<N, P>())), dim3(slab_block(N)), s,
              L.packed, nz, n_rot, L.pval, L.pidx);
     const dim3 g4{unsigned(fp.planar ? 1 : 3), unsigned(n_rot), 1u};
     launch_k(kt, "finish", finish_slab_kernel<N>, g4, dim3(kFinishBlock), s, L.packed, nz, L.pval, L.pidx, L.nbbuf,
@@ -1661,7 +1676,7 @@ hipError_t modes_peaks_impl(const cf* modes, int nb, int n_m, float* score, int3
                        L.rots, nb, modes, L.packed);
     hipLaunchKernelGGL((islab_peak_kernel<N, 0>),
                        dim3(persistent_grid(N * ((nb + 1) / 2), num_cu * islab_blocks_per_cu<N, 0>())),
-                       dim3(islab_block(N)), 0, s, L.packed, N, nb, L.pval, L.pidx);
+                       dim3(slab_block(N)), 0, s, L.packed, N, nb, L.pval, L.pidx);
     hipLaunchKernelGGL(finish_slab_kernel<N>, dim3(3u, unsigned(nb)), dim3(kFinishBlock), 0, s, L.packed, N, L.pval,
                        L.pidx, L.nbbuf, L.rots, L.job);
     hipLaunchKernelGGL(finish_rot_kernel, dim3(unsigned((nb + 63) / 64)), dim3(64), 0, s, L.nbbuf, L.rots, L.job, nb);
@@ -1674,7 +1689,10 @@ size_t fused_workspace_bytes(const FusedPlan& fp) { return fused_layout(fp, null
 
 namespace {
 template <int N>
-void query_islab() {
+void query_slab_kernels() {
+    (void)spread_blocks_per_cu<N, 0>();
+    (void)spread_blocks_per_cu<N, 1>();
+    (void)spread_blocks_per_cu<N, 2>();
     (void)islab_blocks_per_cu<N, 0>();
     (void)islab_blocks_per_cu<N, 1>();
     (void)islab_blocks_per_cu<N, 2>();
@@ -1682,12 +1700,12 @@ void query_islab() {
 }  // namespace
 
 void fused_query_occupancy() {
-    query_islab<8>();
-    query_islab<16>();
-    query_islab<32>();
-    query_islab<64>();
-    query_islab<96>();
-    query_islab<128>();
+    query_slab_kernels<8>();
+    query_slab_kernels<16>();
+    query_slab_kernels<32>();
+    query_slab_kernels<64>();
+    query_slab_kernels<96>();
+    query_slab_kernels<128>();
 }
 
 bool modes_peaks_supported(int N, bool planar) { return fused_pair_grouped(N, planar); }
