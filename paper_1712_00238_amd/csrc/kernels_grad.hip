@@ -289,7 +289,11 @@ __global__ void box_pose_kernel(const double* __restrict__ poses, int64_t B, Box
     out[b] = P;
 }
 
-template <bool GRAD>
+// REAL (pose gradients without weight gradients): only Re(c_k Phi) and the
+// real parts of c_k times Phi's derivatives are needed, so the stencil
+// contracts u = Re(c_k v) per cell, one real product chain instead of a
+// complex one from the y sums on (16 fewer VALU instructions per plane).
+template <bool GRAD, bool REAL = false>
 __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float>* __restrict__ rho_f, int N,
                                                                 const cplx<float>* __restrict__ rho_m,
                                                                 const float* __restrict__ w_m, int n_m,
@@ -398,55 +402,99 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
                 if (GRAD) bspline3_dweights(y - fl, dw[a]);
             }
             const cplx<float>* base = box + lb[2] * kBoxPlane + lb[1] * kBoxRow + lb[0];
-            // separable contraction: x, then y, then z
-            cplx<float> phi = mk(0.f, 0.f), gx = phi, gy = phi, gz = phi;
+            if constexpr (REAL) {
+                // separable contraction of u = Re(c_k v): x, then y, then z
+                float phi = 0.f, gx = 0.f, gy = 0.f, gz = 0.f;
 #pragma unroll 1
-            for (int cz = 0; cz < 4; ++cz) {
-                float wz = wgt[2][0], dz = GRAD ? dw[2][0] : 0.f;
+                for (int cz = 0; cz < 4; ++cz) {
+                    float wz = wgt[2][0], dz = dw[2][0];
 #pragma unroll
-                for (int q = 1; q < 4; ++q)
-                    if (cz == q) {
-                        wz = wgt[2][q];
-                        if (GRAD) dz = dw[2][q];
-                    }
-                const cplx<float>* plane = base + cz * kBoxPlane;
-                cplx<float> ay = mk(0.f, 0.f), by = ay, cy_ = ay;
+                    for (int q = 1; q < 4; ++q)
+                        if (cz == q) {
+                            wz = wgt[2][q];
+                            dz = dw[2][q];
+                        }
+                    const cplx<float>* plane = base + cz * kBoxPlane;
+                    float ay = 0.f, by = 0.f, cy_ = 0.f;
 #pragma unroll
-                for (int cy = 0; cy < 4; ++cy) {
-                    cplx<float> rx = mk(0.f, 0.f), rdx = rx;
+                    for (int cy = 0; cy < 4; ++cy) {
+                        float rx = 0.f, rdx = 0.f;
 #pragma unroll
-                    for (int cx = 0; cx < 4; ++cx) {
-                        const cplx<float> v = plane[cy * kBoxRow + cx];
-                        rx = rx + v * wgt[0][cx];
-                        if (GRAD) rdx = rdx + v * dw[0][cx];
+                        for (int cx = 0; cx < 4; ++cx) {
+                            const cplx<float> v = plane[cy * kBoxRow + cx];
+                            const float u = ck.re * v.re - ck.im * v.im;
+                            rx += u * wgt[0][cx];
+                            rdx += u * dw[0][cx];
+                        }
+                        ay += rx * wgt[1][cy];
+                        by += rdx * wgt[1][cy];
+                        cy_ += rx * dw[1][cy];
                     }
-                    ay = ay + rx * wgt[1][cy];
-                    if (GRAD) {
-                        by = by + rdx * wgt[1][cy];
-                        cy_ = cy_ + rx * dw[1][cy];
-                    }
+                    phi += ay * wz;
+                    gx += by * wz;
+                    gy += cy_ * wz;
+                    gz += ay * dz;
                 }
-                phi = phi + ay * wz;
-                if (GRAD) {
-                    gx = gx + by * wz;
-                    gy = gy + cy_ * wz;
-                    gz = gz + ay * dz;
-                }
-            }
-            acc[0] = double((ck * phi).re);
-            if (GRAD) {
-                const double g0 = double((ck * gx).re), g1 = double((ck * gy).re), g2 = double((ck * gz).re);
+                const double g0 = double(gx), g1 = double(gy), g2 = double(gz);
                 const double w0 = double(wv[0]), w1 = double(wv[1]), w2 = double(wv[2]);
+                acc[0] = double(phi);
                 acc[1] = g0;
                 acc[2] = g1;
                 acc[3] = g2;
                 acc[4] = w1 * g2 - w2 * g1;
                 acc[5] = w2 * g0 - w0 * g2;
                 acc[6] = w0 * g1 - w1 * g0;
-                if (want_w == 1) gw += float(sc) * (rm * phi).re;
-                if (want_w == 2) {
-                    gw += float(sc) * phi.re;
-                    gwi += float(sc) * phi.im;
+            } else {
+                // separable contraction: x, then y, then z
+                cplx<float> phi = mk(0.f, 0.f), gx = phi, gy = phi, gz = phi;
+#pragma unroll 1
+                for (int cz = 0; cz < 4; ++cz) {
+                    float wz = wgt[2][0], dz = GRAD ? dw[2][0] : 0.f;
+#pragma unroll
+                    for (int q = 1; q < 4; ++q)
+                        if (cz == q) {
+                            wz = wgt[2][q];
+                            if (GRAD) dz = dw[2][q];
+                        }
+                    const cplx<float>* plane = base + cz * kBoxPlane;
+                    cplx<float> ay = mk(0.f, 0.f), by = ay, cy_ = ay;
+#pragma unroll
+                    for (int cy = 0; cy < 4; ++cy) {
+                        cplx<float> rx = mk(0.f, 0.f), rdx = rx;
+#pragma unroll
+                        for (int cx = 0; cx < 4; ++cx) {
+                            const cplx<float> v = plane[cy * kBoxRow + cx];
+                            rx = rx + v * wgt[0][cx];
+                            if (GRAD) rdx = rdx + v * dw[0][cx];
+                        }
+                        ay = ay + rx * wgt[1][cy];
+                        if (GRAD) {
+                            by = by + rdx * wgt[1][cy];
+                            cy_ = cy_ + rx * dw[1][cy];
+                        }
+                    }
+                    phi = phi + ay * wz;
+                    if (GRAD) {
+                        gx = gx + by * wz;
+                        gy = gy + cy_ * wz;
+                        gz = gz + ay * dz;
+                    }
+                }
+                acc[0] = double((ck * phi).re);
+                if (GRAD) {
+                    const double g0 = double((ck * gx).re), g1 = double((ck * gy).re), g2 = double((ck * gz).re);
+                    const double w0 = double(wv[0]), w1 = double(wv[1]), w2 = double(wv[2]);
+                    acc[1] = g0;
+                    acc[2] = g1;
+                    acc[3] = g2;
+                    acc[4] = w1 * g2 - w2 * g1;
+                    acc[5] = w2 * g0 - w0 * g2;
+                    acc[6] = w0 * g1 - w1 * g0;
+                    if (want_w == 1) gw += float(sc) * (rm * phi).re;
+                    if (want_w == 2) {
+                        gw += float(sc) * phi.re;
+                        gwi += float(sc) * phi.im;
+                    }
                 }
             }
         }
@@ -698,7 +746,10 @@ hipError_t launch_score_grad(const void* rho_f, int N, bool planar, const void* 
         const dim3 grid{unsigned(nsb), unsigned(std::min(npb - pb0, 65535)), 1u};
         if constexpr (std::is_same<T, float>::value) {
             if (use_box<T>(planar, N)) {
-                if (grad)
+                if (grad && ww == 0)
+                    hipLaunchKernelGGL((grad_box_kernel<true, true>), grid, dim3(kBoxBlock), 0, s, rf, N, rm, w_m, n_m,
+                                       bpose, B, grad_scale, part, nsb, wpart, 0, pb0);
+                else if (grad)
                     hipLaunchKernelGGL((grad_box_kernel<true>), grid, dim3(kBoxBlock), 0, s, rf, N, rm, w_m, n_m, bpose,
                                        B, grad_scale, part, nsb, wpart, ww, pb0);
                 else
