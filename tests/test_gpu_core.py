@@ -472,7 +472,8 @@ def test_score_grad_lds_box_kernel(ctxs, n, nm, B):
     assert np.max(np.abs(gw - gw_ref)) <= 2e-4 * max(1.0, np.max(np.abs(gw_ref)))
     s2, _, _ = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=False)
     assert np.allclose(to_np(s2), score, rtol=1e-6, atol=1e-6 * np.abs(score).max())
-    # pose derivatives alone (no weight gradient) match the combined call
+    # pose derivatives alone (no weight gradient: the kernel contracts
+    # Re(c_k rho_F) instead of complex sums) match the combined call
     _, gp3, _ = ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=True)
     assert np.allclose(to_np(gp3), gp, rtol=1e-6, atol=1e-6 * np.abs(gp).max())
 
