@@ -226,18 +226,18 @@ __device__ __forceinline__ double row16_sum(double v) {
 // the tile's corners bound its moved positions (widened by 1e-3 cell, far
 // above the FP32 rounding of a moved position), so the stencil floors span at
 // most ceil(7 |row of R|_1) + 1 <= 14 values and the box is at most 17 cells
-// per axis.  The box has fixed pitches (17 cells per row, 300 per plane; the
-// plane pitch spreads the stencil gathers over the LDS banks), so the 64
-// stencil reads of a sample sit at constant offsets from one address.
-// Staging gives each wave three box rows per load instruction (51 lanes,
-// row and plane on the scalar unit) and issues all of a wave's loads before
-// its LDS stores.
+// per axis.  The box has fixed pitches (20 cells per row, 352 per plane, the
+// fastest of the pitches timed for the stencil gathers' LDS bank conflicts),
+// so the 64 stencil reads of a sample sit at constant offsets from one
+// address.  Staging gives each wave three box rows per load instruction (60
+// lanes, row and plane on the scalar unit) and issues all of a wave's loads
+// before its LDS stores.
 constexpr int kBoxTile = 8;
 constexpr int kBoxBlock = kBoxTile * kBoxTile * kBoxTile;
 constexpr int kBoxWaves = kBoxBlock / 64;
 constexpr int kBoxMax = 17;
-constexpr int kBoxRow = 17;
-constexpr int kBoxPlane = 300;
+constexpr int kBoxRow = 20;
+constexpr int kBoxPlane = 352;
 constexpr int kBoxCells = kBoxPlane * kBoxMax;
 constexpr int kBoxSlotRows = 3;                                            // rows per wave load
 constexpr int kBoxSlots = kBoxMax * ((kBoxMax + kBoxSlotRows - 1) / kBoxSlotRows);
@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kBoxBlock, 2) void grad_box_kernel(const cplx<float
                 min(int(floorf(y0 + P.dmax[a] + kBoxMargin)) - fmin + 4, kBoxMax));
         }
         // stage the box: slot s holds rows 3 q .. 3 q + 2 of plane cz, with
-        // s = cz nts + q; lane = 17 j + cx covers row 3 q + j, cell cx
+        // s = cz nts + q; lane = kBoxRow j + cx covers row 3 q + j, cell cx
         {
             const unsigned Nu = unsigned(N);
             const unsigned wx = unsigned(wrap(lo[0], N)), wy = __builtin_amdgcn_readfirstlane(wrap(lo[1], N)),
