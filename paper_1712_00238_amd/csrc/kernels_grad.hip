@@ -226,18 +226,19 @@ __device__ __forceinline__ double row16_sum(double v) {
 // the tile's corners bound its moved positions (widened by 1e-3 cell, far
 // above the FP32 rounding of a moved position), so the stencil floors span at
 // most ceil(7 |row of R|_1) + 1 <= 14 values and the box is at most 17 cells
-// per axis.  The box has fixed pitches (20 cells per row, 352 per plane, the
-// fastest of the pitches timed for the stencil gathers' LDS bank conflicts),
-// so the 64 stencil reads of a sample sit at constant offsets from one
-// address.  Staging gives each wave three box rows per load instruction (60
-// lanes, row and plane on the scalar unit) and issues all of a wave's loads
-// before its LDS stores.
+// per axis.  The box has fixed pitches (18 cells per row, 312 per plane: of
+// the pitches timed, the best over both uniformly spread and clustered
+// rotations, whose stencil gathers meet different LDS bank conflicts), so the
+// 64 stencil reads of a sample sit at constant offsets from one address.
+// Staging gives each wave three box rows per load instruction (54 lanes, row
+// and plane on the scalar unit) and issues all of a wave's loads before its
+// LDS stores.
 constexpr int kBoxTile = 8;
 constexpr int kBoxBlock = kBoxTile * kBoxTile * kBoxTile;
 constexpr int kBoxWaves = kBoxBlock / 64;
 constexpr int kBoxMax = 17;
-constexpr int kBoxRow = 20;
-constexpr int kBoxPlane = 352;
+constexpr int kBoxRow = 18;
+constexpr int kBoxPlane = 312;
 constexpr int kBoxCells = kBoxPlane * kBoxMax;
 constexpr int kBoxSlotRows = 3;                                            // rows per wave load
 constexpr int kBoxSlots = kBoxMax * ((kBoxMax + kBoxSlotRows - 1) / kBoxSlotRows);
