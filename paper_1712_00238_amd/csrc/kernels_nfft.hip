@@ -393,6 +393,42 @@ struct TileAcc<double> {
     __device__ static double back(unsigned long long a) { return double((long long)a); }
 };
 
+// S is taken without depending on the order of its terms: the bins list
+// their samples in arrival order, so a floating-point sum would differ from
+// run to run, and with it the scale and every fixed-point value of the tile.
+// With M the block's largest term, each term t counts ceil(t 2^24 / M) units
+// of M 2^-24, summed exactly in 64-bit integers (the rounding up keeps S at
+// or above the exact sum, up to the final conversion's half ulp, which the
+// 2x headroom of the accumulator covers).
+template <typename T, int BS>
+__device__ __forceinline__ T block_max_nonneg(T v, T* red) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const T o = __shfl_xor(v, off);
+        v = v > o ? v : o;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T m = red[0];
+#pragma unroll
+    for (int i = 1; i < BS / 64; ++i) m = m > red[i] ? m : red[i];
+    return m;
+}
+template <int BS>
+__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v, unsigned long long* red) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    unsigned long long s = 0;
+#pragma unroll
+    for (int i = 0; i < BS / 64; ++i) s += red[i];
+    return s;
+}
+constexpr double kSumUnits = 16777216.0;  // 2^24 units per largest term
+template <typename T>
+__device__ __forceinline__ unsigned long long sum_units(T t, T per_unit) {
+    return (unsigned long long)ceil(double(t * per_unit));
+}
+
 // offset o in (-2 nf, nf) of a node from a tile origin, wrapped to [0, nf)
 __device__ __forceinline__ int wrap_offset(int o, int nf) {
     o += o < 0 ? nf : 0;
@@ -422,6 +458,7 @@ __global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vb
     using A = typename Acc::A;
     __shared__ A lre[kTileLds], lim[kTileLds];
     __shared__ T red[4];
+    __shared__ unsigned long long redi[4];
     const int nbins = ts.ntx * ts.nty * ts.ntz;
     const int tile = int(blockIdx.x), rot = int(blockIdx.y);
     const int tbx = tile % ts.ntx, tby = (tile / ts.ntx) % ts.nty, tbz = tile / (ts.ntx * ts.nty);
@@ -446,26 +483,33 @@ __global__ __launch_bounds__(256) void nfft_tile_kernel(const T* __restrict__ vb
         bcount[nbs] = counts[bin];
         ++nbs;
     }
-    // pass 1: S
-    T part = T(0);
-    for (int bi = 0; bi < nbs; ++bi) {
-        for (int p = int(threadIdx.x); p < bcount[bi]; p += 256) {
-            const int64_t at = int64_t(bstart[bi]) + p;
-            const T* vp = vbuf + 4 * at;
-            bool hit = true;
+    // pass 1: S, order-free (the largest term, then the sum in its units)
+    auto terms = [&](auto&& take) __attribute__((always_inline)) {
+        for (int bi = 0; bi < nbs; ++bi) {
+            for (int p = int(threadIdx.x); p < bcount[bi]; p += 256) {
+                const int64_t at = int64_t(bstart[bi]) + p;
+                const T* vp = vbuf + 4 * at;
+                bool hit = true;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a)
-                hit = hit && reaches<W>(wrap_offset(first_node(vp[a], half) - org[a], nf), side[a], nf);
-            if (hit) {
-                const cplx<T> ck = cbuf[at];
-                part += dmax(dabs(ck.re), dabs(ck.im));
+                for (int a = 0; a < DIM; ++a)
+                    hit = hit && reaches<W>(wrap_offset(first_node(vp[a], half) - org[a], nf), side[a], nf);
+                if (hit) {
+                    const cplx<T> ck = cbuf[at];
+                    take(dmax(dabs(ck.re), dabs(ck.im)));
+                }
             }
         }
+    };
+    T tmax = T(0);
+    terms([&](T t) { tmax = t > tmax ? t : tmax; });
+    const T M = block_max_nonneg<T, 256>(tmax, red);
+    T S = T(0);
+    if (M > T(0)) {
+        const T per_unit = T(kSumUnits) / M;
+        unsigned long long units = 0;
+        terms([&](T t) { units += sum_units(t, per_unit); });
+        S = T(double(block_sum_u64<256>(units, redi)) * (double(M) / kSumUnits));
     }
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-    __syncthreads();
-    const T S = red[0] + red[1] + red[2] + red[3];
     const T sc = S > T(0) ? T(Acc::kOne) / S : T(0);
     // pass 2: spread in fixed point
     if (S > T(0)) {
@@ -707,6 +751,7 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_tile_kernel(const float*
                                                                     TileShape ts, cplx<float>* __restrict__ fine) {
     __shared__ int lre[kLineLds], lim[kLineLds];
     __shared__ float red[kLineBlock / 64];
+    __shared__ unsigned long long redi[kLineBlock / 64];
     const int nbins = ts.nty * ts.ntz;
     const int tile = int(blockIdx.x), rot = int(blockIdx.y);
     const int tby = tile % ts.nty, tbz = tile / ts.nty;
@@ -725,25 +770,30 @@ __global__ __launch_bounds__(kLineBlock) void nfft_line_tile_kernel(const float*
     }
     // y / z offset of a sample's first window row from the tile, in (-nf/2, nf/2]
     auto rel = [&](float v, int org) { return ((first_node(v, half) - org + nf / 2) & msk) - nf / 2; };
-    float part = 0.f;
+    auto terms = [&](auto&& take) __attribute__((always_inline)) {
 #pragma unroll
-    for (int nb = 0; nb < 4; ++nb) {
-        for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
-            const int64_t at = int64_t(bstart[nb]) + p;
-            const float* vp = vbuf + 4 * at;
-            const int oy = rel(vp[1], y0), oz = rel(vp[2], z0);
-            if (oy > -W && oy < kLineRows && oz > -W && oz < kLineRows) {
-                const cplx<float> ck = cbuf[at];
-                part += fmaxf(fabsf(ck.re), fabsf(ck.im));
+        for (int nb = 0; nb < 4; ++nb) {
+            for (int p = int(threadIdx.x); p < bcount[nb]; p += kLineBlock) {
+                const int64_t at = int64_t(bstart[nb]) + p;
+                const float* vp = vbuf + 4 * at;
+                const int oy = rel(vp[1], y0), oz = rel(vp[2], z0);
+                if (oy > -W && oy < kLineRows && oz > -W && oz < kLineRows) {
+                    const cplx<float> ck = cbuf[at];
+                    take(fmaxf(fabsf(ck.re), fabsf(ck.im)));
+                }
             }
         }
-    }
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-    __syncthreads();
+    };
+    float tmax = 0.f;
+    terms([&](float t) { tmax = fmaxf(tmax, t); });
+    const float M = block_max_nonneg<float, kLineBlock>(tmax, red);
     float S = 0.f;
-#pragma unroll
-    for (int i = 0; i < kLineBlock / 64; ++i) S += red[i];
+    if (M > 0.f) {
+        const float per_unit = float(kSumUnits) / M;
+        unsigned long long units = 0;
+        terms([&](float t) { units += sum_units(t, per_unit); });
+        S = float(double(block_sum_u64<kLineBlock>(units, redi)) * (double(M) / kSumUnits));
+    }
     cplx<float>* g = fine + int64_t(rot) * nf * nf * nf;
     const int sh = __ffs(nf) - 1;  // nf is a power of two
     if (!(S > 0.f)) {  // no sample reaches the tile: store zeros, skip the LDS work
@@ -854,6 +904,7 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
     __shared__ __align__(16) int acc[2 * kFusedLds];
     __shared__ cplx<float> tw[NF];
     __shared__ float red[BS / 64];
+    __shared__ unsigned long long redi[BS / 64];
     // counting sort of the touching candidates by (z, y) row offset: oy in
     // (-W, 8), oz in (-W, 4), W <= 8
     constexpr int KEYS = 15 * 11;
@@ -865,7 +916,7 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
     __shared__ int s_nsorted;
     // two blocks share a compute unit's 160 KiB only while one stays within 80 KiB
     static_assert(sizeof(int) * (2 * kFusedLds + KEYS + KC * BS + 1) + sizeof(cplx<float>) * NF +
-                          sizeof(float) * (BS / 64) <= 80 * 1024,
+                          (sizeof(float) + sizeof(unsigned long long)) * (BS / 64) <= 80 * 1024,
                   "the fused line tile must fit two blocks per compute unit");
     int* lre = acc;
     int* lim = acc + kFusedLds;
@@ -932,25 +983,32 @@ __global__ __launch_bounds__(kFusedBlock) void nfft_line_fft_kernel(const float*
             cck[k] = cbuf[at];
         }
     }
-    float part = 0.f;
+    // S, order-free: the largest term, then the sum in its units (the first
+    // KC candidates of each thread from registers, the rest reloaded)
+    auto terms = [&](auto&& take) __attribute__((always_inline)) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k) {
-        const int i = int(threadIdx.x) + k * BS;
-        if (i < total && touches(rel(cvy[k], y0), rel(cvz[k], z0))) part += fmaxf(fabsf(cck[k].re), fabsf(cck[k].im));
-    }
-    for (int i = int(threadIdx.x) + KC * BS; i < total; i += BS) {
-        const int64_t at = slot(i);
-        if (touches(rel(vbuf[4 * at + 1], y0), rel(vbuf[4 * at + 2], z0))) {
-            const cplx<float> ck = cbuf[at];
-            part += fmaxf(fabsf(ck.re), fabsf(ck.im));
+        for (int k = 0; k < KC; ++k) {
+            const int i = int(threadIdx.x) + k * BS;
+            if (i < total && touches(rel(cvy[k], y0), rel(cvz[k], z0))) take(fmaxf(fabsf(cck[k].re), fabsf(cck[k].im)));
         }
-    }
-    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
-    __syncthreads();
+        for (int i = int(threadIdx.x) + KC * BS; i < total; i += BS) {
+            const int64_t at = slot(i);
+            if (touches(rel(vbuf[4 * at + 1], y0), rel(vbuf[4 * at + 2], z0))) {
+                const cplx<float> ck = cbuf[at];
+                take(fmaxf(fabsf(ck.re), fabsf(ck.im)));
+            }
+        }
+    };
+    float tmax = 0.f;
+    terms([&](float t) { tmax = fmaxf(tmax, t); });
+    const float M = block_max_nonneg<float, BS>(tmax, red);
     float S = 0.f;
-#pragma unroll
-    for (int i = 0; i < BS / 64; ++i) S += red[i];
+    if (M > 0.f) {
+        const float per_unit = float(kSumUnits) / M;
+        unsigned long long units = 0;
+        terms([&](float t) { units += sum_units(t, per_unit); });
+        S = float(double(block_sum_u64<BS>(units, redi)) * (double(M) / kSumUnits));
+    }
     // x-pruned rows of this tile: row r = iz * 8 + iy at [b][z0 + iz][y0 + iy][0 .. N)
     cplx<float>* hb = half_buf + int64_t(rot) * NF * NF * N;
     auto hrow = [=](int r) __attribute__((always_inline)) {

@@ -329,6 +329,35 @@ def test_nfft_peaks_fp32_through_folded_inverse(ctxs, n, nrot):
         assert np.max(np.abs(ref_t[r] - op.subvoxel(nb0, tuple(t[r])))) <= 1e-3
 
 
+@pytest.mark.parametrize("dtype,planar,n", [("f32", False, 64), ("f64", False, 32), ("f32", True, 64)])
+def test_nfft_repeats_bit_for_bit(ctxs, dtype, planar, n):
+    """The bins list their samples in arrival order, which varies from run to
+    run; each tile's fixed-point scale is an order-free sum, so repeated
+    calls give identical volumes and peaks (FP32 line tiles with a tile
+    crowded past the sorted candidates, FP64 general tiles, planar tiles)."""
+    ctx = ctxs[dtype]
+    rng = np.random.default_rng(800 + n + (1 if planar else 0))
+    rho_f = smooth_field(rng, n, planar, damping=0.06 * n * n).astype(CPLX[dtype])
+    dim = 2 if planar else 3
+    centre = rng.uniform(-0.2 * n, 0.2 * n, dim)
+    pts = np.concatenate([centre + rng.normal(scale=0.7, size=(2600, dim)),
+                          rng.uniform(-0.45 * n, 0.45 * n, (900, dim))])
+    if planar:
+        pts = np.concatenate([pts, np.zeros((len(pts), 1))], axis=1)
+    pos = pts.astype(REAL[dtype])
+    coef = (rng.normal(size=len(pos)) + 1j * rng.normal(size=len(pos))).astype(CPLX[dtype])
+    gf = grid_spec(n, planar)
+    spec = ctx.spectrum(rho_f, gf)
+    quats = planar_quats(3, 17) if planar else wr.uniform_quaternions(3, 900 + n)
+    flush_print("nfft repeat", dtype, "planar" if planar else "3D", n)
+    vols = [to_np(ctx.score_volume_nfft(spec, gf, pos, coef, quats, width=6)) for _ in range(3)]
+    assert all(np.array_equal(vols[0], v) for v in vols[1:])
+    outs = [ctx.score_rotations_nfft(spec, gf, pos, coef, quats, width=6) for _ in range(3)]
+    for key in ("score", "t", "nbhd", "refined"):
+        ref = to_np(outs[0][key])
+        assert all(np.array_equal(ref, to_np(o[key])) for o in outs[1:]), key
+
+
 def test_nfft_without_samples_scores_zero(ctxs):
     ctx = ctxs["f32"]
     gf = grid_spec(16, False)
