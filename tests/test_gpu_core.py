@@ -536,6 +536,25 @@ def _phi_sum(rho_f, nm, poses, gs):
     return acc
 
 
+@pytest.mark.parametrize("n,nm", [(16, 6), (24, 8)])
+def test_score_grad_repeats_bit_for_bit(ctxs, n, nm):
+    """Pose gradients and the moving coefficients' cotangent reduce in fixed
+    trees (no floating-point atomics), so repeated calls agree bit for bit on
+    the tile kernel (N = 16) and the LDS-box kernel (N = 24)."""
+    ctx = ctxs["f32"]
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, False, 500 + n)
+    rng = np.random.default_rng(5 + n)
+    B = 37
+    poses = np.concatenate([rng.uniform(-n, 2 * n, size=(B, 3)), wr.uniform_quaternions(B, 60 + n)], axis=1)
+    gs = rng.normal(size=B)
+    flush_print("score_grad repeat", n, nm)
+    runs = [[to_np(x) for x in ctx.score_grad(rho_f, gf, rho_m, w, gm, poses, want_pose=True)[:2]] for _ in range(3)]
+    assert all(np.array_equal(runs[0][i], r[i]) for r in runs[1:] for i in range(2))
+    coefs = [to_np(ctx.score_grad_coef(rho_f, gf, rho_m, w, gm, poses, want_w=True, grad_scale=gs)[2])
+             for _ in range(3)]
+    assert all(np.array_equal(coefs[0], c) for c in coefs[1:])
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
 @pytest.mark.parametrize("n,nm", [(16, 6), (24, 8)])
 def test_score_grad_coef_matches_oracle(ctxs, dtype, n, nm):
