@@ -310,12 +310,12 @@ def sdf_build_counts(ctx, part, params, build_ms):
     ctx.set_option("sdf_stats", 0)
     dense = float(part.samples.count) * part.grid.size
     sec = build_ms * 1e-3
-    # VALU issue bound: the FP32 kernel's inner loops issue about 10 VALU
-    # instructions per pass-1 pair (FP64 distance and compares), 10 per pass-2
-    # pair (distance and ball test) and 19 more per pair inside the ball; the
+    # VALU issue bound: the FP32 kernel's inner loops issue about 8 VALU
+    # instructions per pass-1 pair (FP64 distance and compares), 9 per pass-2
+    # pair (distance and ball test) and 18 more per pair inside the ball; the
     # chip issues 256 CUs x 64 lanes x 2.4 GHz lane instructions per second
     lanes_per_s = 256 * 64 * 2.4e9
-    bound_ms = 1e3 * (10.0 * c["nearest"] + 10.0 * c["sum"] + 19.0 * c["in_ball"]) / lanes_per_s
+    bound_ms = 1e3 * (8.0 * c["nearest"] + 9.0 * c["sum"] + 18.0 * c["in_ball"]) / lanes_per_s
     return {"build_ms": round(build_ms, 3), "samples": part.samples.count, "nodes": part.grid.size,
             "pairs_nearest": c["nearest"], "pairs_sum": c["sum"], "pairs_in_ball": c["in_ball"],
             "frac_of_dense": {k: round(v / dense, 4) for k, v in c.items()},

@@ -78,6 +78,16 @@ struct Brick {
 };
 __host__ __device__ inline Brick brick_shape(int nz) { return nz == 1 ? Brick{16, 16, 1} : Brick{8, 8, 4}; }
 
+// A zero the compiler cannot see through: LDS addresses offset by it stay in
+// a vector register across a loop, so the broadcast reads of the sample
+// tiles use immediate offsets from it instead of re-copying a scalar base
+// into a vector register for every read.
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+v"(z));
+    return z;
+}
+
 // Samples in Morton order with per-tile bounding boxes.
 struct SampleTiles {
     const double* qs;   // positions, n x 3
@@ -151,12 +161,15 @@ __device__ __forceinline__ void nearest_pass(const SampleTiles& st, int64_t ns, 
                 sidx[a] = st.js[s];
             }
             __syncthreads();
+            const int z0 = opaque_zero();
+            const v4<double>* sqb = sq + z0;
+            const int* sib = sidx + z0;
 #pragma unroll 4
             for (int a = 0; a < cnt; ++a) {
-                const v4<double> s = sq[a];
+                const v4<double> s = sqb[a];
                 const double dx = px - s.x, dy = py - s.y, dz = pz - s.z;
                 const double d2 = dx * dx + dy * dy + dz * dz;
-                const int jj = sidx[a];
+                const int jj = sib[a];
                 if (d2 < best || (d2 == best && jj < jbest)) {
                     best = d2;
                     jbest = jj;
@@ -262,9 +275,12 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                 }
                 __syncthreads();
                 if (live) {
+                    const int z0 = opaque_zero();
+                    const v4<T>* sqb = sq2 + z0;
+                    const v4<T>* snb = sn2 + z0;
 #pragma unroll 4
                     for (int a = 0; a < cnt; ++a) {
-                        const v4<T> s = sq2[a];
+                        const v4<T> s = sqb[a];
                         const T dx = prx - s.x, dy = pry - s.y, dz = prz - s.z;
                         const T d2 = dx * dx + dy * dy + dz * dz;
                         bool in = d2 <= r2lo;
@@ -276,7 +292,7 @@ __global__ __launch_bounds__(kSdfBlock) void sdf_build_kernel(const double* __re
                         }
                         if (in) {
                             if (STATS) ++inball;
-                            const v4<T> nv = sn2[a];
+                            const v4<T> nv = snb[a];
                             const T inv_eta = fast_rsqrt(d2);
                             const T eta = d2 * inv_eta;
                             const T r = eta * inv_xi;
