@@ -328,6 +328,39 @@ def test_score_rotations_peaks_f32(ctxs, path, n, nm, planar, nrot, batch):
         ctx.set_option("pencil_group", 2)
 
 
+def test_score_rotations_n64_many_items_per_block(ctxs):
+    """At N = 64 the spread and inverse slab kernels run several 512-thread
+    blocks per compute unit from the occupancy query; 96 rotations in one
+    launch give every block several work items.  Sampled rotations against
+    the oracle, every rotation against the plain multi-pass path."""
+    ctx = ctxs["f32"]
+    n, nm, nrot = 64, 24, 96
+    gf, gm, rho_f, rho_m, w = small_case(n, nm, False, 4242)
+    quats = wr.uniform_quaternions(nrot, 77)
+    spec = ctx.spectrum(rho_f, gf)
+    ctx.set_option("batch", nrot)
+    try:
+        flush_print("score_rotations n64 many items", nrot)
+        out = ctx.score_rotations(spec, gf, rho_m, w, gm, quats)
+        s, t = to_np(out["score"]), to_np(out["t"])
+        ctx.set_option("path", 1)
+        ref = ctx.score_rotations(spec, gf, rho_m, w, gm, quats)
+        s1, t1 = to_np(ref["score"]), to_np(ref["t"])
+    finally:
+        ctx.set_option("path", 0)
+        ctx.set_option("batch", 64)
+    scale = np.abs(s1).max()
+    assert np.max(np.abs(s - s1)) <= 2e-5 * scale
+    c = oc.moving_coefficients(rho_m, w)
+    for r in range(0, nrot, 8):
+        vol = oc.score_volume(rho_f, c, quats[r], nm, False)
+        s0, _, t0 = op.peak(vol)
+        vscale = np.abs(vol).max()
+        assert abs(s[r] - s0) <= 2e-5 * vscale, (r, s[r], s0)
+        if tuple(t[r]) != t0:
+            assert abs(vol[t[r][2], t[r][1], t[r][0]] - s0) <= 2e-5 * vscale, (r, t[r], t0)
+
+
 @pytest.mark.parametrize("n,nm,planar,nrot", [(16, 6, False, 3), (32, 19, True, 4)])
 def test_score_rotations_f64_exact_peaks(ctxs, n, nm, planar, nrot):
     ctx = ctxs["f64"]
