@@ -182,28 +182,28 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 }
 
 // ------------------------------------------------------------------ K1
-// Slab layouts.  Generic sizes keep the interleaved complex N x N slab and
-// two N x N integer planes over the same bytes, with periodic wrap of the
-// stencil.  N = 64 and 128 use a padded row layout: row y holds the re plane
-// (N ints), the im plane (N ints) and 24 pad ints, so consecutive rows start
-// 24 banks apart (unpadded rows put every row on the same banks and double
-// the scatter's conflict stalls).  The
-// complex row that replaces it after conversion has N + 8 entries, entry e
-// at e + e / 16, so that the radix-16 pass along x, which writes 16
-// consecutive entries per lane, does not put the 8 lanes of a row on the
-// same banks.  Positions are stored shifted by N / 2 in x and y,
-// which the fitting rule for the rotated body box keeps inside [0, N), so no
-// index wraps and the 16 stencil addresses of a sample are one base plus
-// constant offsets.  The shift multiplies the slab's 2D DFT by (-1)^(kx+ky),
-// removed when the slab is written.
+// Slab layout.  The scatter accumulates into padded integer rows: row y
+// holds the re plane (N ints), the im plane (N ints) and 24 pad ints, so
+// consecutive rows start 24 banks apart (unpadded rows put every row on the
+// same banks and double the scatter's conflict stalls).  Positions are stored
+// shifted by N / 2 in x and y, which the fitting rule for the rotated body box
+// (checked by the ABI for every size) keeps inside [0, N), so no index wraps
+// and the 16 stencil addresses of a sample are one base plus constant
+// offsets.  The shift multiplies the slab's 2D DFT by (-1)^(kx+ky), removed
+// when the slab is written (or folded into the pair-grouped spectrum).  At
+// N = 64 and 128 (kFast) the complex row that replaces a row after
+// conversion has N + 8 entries, entry e at e + e / 16, so that the radix-16
+// pass along x, which writes 16 consecutive entries per lane, does not put
+// the 8 lanes of a row on the same banks; the other sizes convert to an
+// interleaved complex N x N slab for the generic transforms.
 template <int N>
 struct SlabLayout {
     static constexpr bool kFast = N == 64 || N == 128;
-    static constexpr int kRowInts = kFast ? 2 * N + 24 : N;  // ints per accumulation row
-    static constexpr int kImOff = kFast ? N : N * N;          // im plane offset (ints)
-    static constexpr int kInts = kFast ? N * kRowInts : 2 * N * N;
-    static constexpr int kRowCf = kRowInts / 2;                // complex stride after conversion (fast)
-    static constexpr int kShift = kFast ? N / 2 : 0;
+    static constexpr int kRowInts = 2 * N + 24;      // ints per accumulation row
+    static constexpr int kImOff = N;                 // im plane offset in a row (ints)
+    static constexpr int kInts = N * kRowInts;       // >= 2 N N: room for the complex slab
+    static constexpr int kRowCf = kRowInts / 2;      // complex stride after conversion (fast)
+    static constexpr int kShift = N / 2;
 };
 
 __device__ __forceinline__ int fixed_rpi(float v) {
@@ -219,28 +219,13 @@ template <int N>
 __device__ __forceinline__ void flush_stencil(int* __restrict__ acc, int ix, int iy, const int vr[16],
                                               const int vi[16]) {
     using L = SlabLayout<N>;
-    if constexpr (L::kFast) {
-        const int base = int(__umul24(unsigned(iy + L::kShift), unsigned(L::kRowInts))) + ix + L::kShift;
+    const int base = int(__umul24(unsigned(iy + L::kShift), unsigned(L::kRowInts))) + ix + L::kShift;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < 4; ++b) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                atomicAdd(acc + base + b * L::kRowInts + a, vr[4 * b + a]);
-                atomicAdd(acc + base + b * L::kRowInts + L::kImOff + a, vi[4 * b + a]);
-            }
-        }
-    } else {
-        int col[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) col[a] = wrap(ix + a, N);
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int row = wrap(iy + b, N) * N;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                atomicAdd(acc + row + col[a], vr[4 * b + a]);
-                atomicAdd(acc + L::kImOff + row + col[a], vi[4 * b + a]);
-            }
+        for (int a = 0; a < 4; ++a) {
+            atomicAdd(acc + base + b * L::kRowInts + a, vr[4 * b + a]);
+            atomicAdd(acc + base + b * L::kRowInts + L::kImOff + a, vi[4 * b + a]);
         }
     }
 }
@@ -572,14 +557,17 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
             // 3D grids: the rotation's column tiles; planar: the slab
             slab_fft_store_fast<N>(acc, tw, inv, planar ? out : slabs + int64_t(rot) * nz * N * N, planar == 0, z);
         } else {
-            // planes -> interleaved complex, in place: read everything, then write
+            // padded planes -> interleaved complex, in place: read everything, then write
             cf* slab = reinterpret_cast<cf*>(acc);
             constexpr int PER = (N * N + B - 1) / B;
             cf v[PER];
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
                 const int i = threadIdx.x + p * B;
-                if ((N * N) % B == 0 || i < N * N) v[p] = mk(float(acc[i]) * inv, float(acc[N * N + i]) * inv);
+                if ((N * N) % B == 0 || i < N * N) {
+                    const int row = (i / N) * L::kRowInts + i % N;
+                    v[p] = mk(float(acc[row]) * inv, float(acc[row + L::kImOff]) * inv);
+                }
             }
             __syncthreads();
 #pragma unroll
@@ -590,7 +578,11 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
             __syncthreads();
             lds_fft_lines<float, N, -1, false, Plan>(slab, 1, N, N, tw);  // along x
             lds_fft_lines<float, N, -1, true, Plan>(slab, N, 1, N, tw);   // along y
-            for (int i = threadIdx.x; i < N * N; i += B) out[i] = slab[i];
+            // the (-1)^(kx + ky) of the N / 2 shift
+            for (int i = threadIdx.x; i < N * N; i += B) {
+                const cf v = slab[i];
+                out[i] = ((i % N + i / N) & 1) ? mk(-v.re, -v.im) : v;
+            }
         }
     }
 }
