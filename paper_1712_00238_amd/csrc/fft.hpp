@@ -198,10 +198,11 @@ __device__ __forceinline__ void stockham_run(cplx<T>* line_base, int es, int t, 
 // element stride es.  LINES_FAST selects the lane mapping: consecutive lanes
 // take consecutive lines (for element-strided, line-contiguous layouts) or
 // consecutive elements of one line (for line-strided, element-contiguous
-// layouts).  All threads of the block must call this.
-template <typename T, int N, int S, bool LINES_FAST, typename Plan = typename DefaultPlan<N>::type>
+// layouts).  TPL threads work on one line (fewer than N / 8 give each thread
+// several butterflies per pass).  All threads of the block must call this.
+template <typename T, int N, int S, bool LINES_FAST, typename Plan = typename DefaultPlan<N>::type,
+          int TPL = FFTShape<N>::TPL>
 __device__ __forceinline__ void lds_fft_lines(cplx<T>* buf, int es, int ls, int nlines, const cplx<T>* tw) {
-    constexpr int TPL = FFTShape<N>::TPL;
     const int conc = blockDim.x / TPL;
     const int tid = threadIdx.x;
     int ll, t;

@@ -59,6 +59,26 @@ constexpr int kSlabBlock = 1024;
 // partial per wave and (rotation, slab).
 constexpr int slab_block(int N) { return N == 64 ? 512 : kSlabBlock; }
 constexpr int islab_waves(int N) { return slab_block(N) / 64; }
+// Threads per line when a block of BLOCK threads transforms LINES lines of
+// NZ points (generic sizes): NZ / 8, or else the largest power of two below
+// it that lets every line run at once (96 lines of 12 threads exceed 1024
+// threads, and a second round of 11 lines leaves most of the block idle).
+template <int NZ, int LINES, int BLOCK>
+constexpr int fft_tpl() {
+    const int t = NZ / 8 < 1 ? 1 : NZ / 8;
+    if (LINES * t <= BLOCK) return t;
+    int p = 1;
+    while (2 * p <= t && LINES * 2 * p <= BLOCK) p *= 2;
+    return p;
+}
+static_assert(fft_tpl<96, 96, 1024>() == 8 && fft_tpl<32, 32, 1024>() == 4, "threads per line");
+// Slab transforms of the generic sizes (8, 16, 32, 96): threads per line, and
+// the complex row pitch, padded so that the lines one wave transforms along x
+// start on different LDS banks.
+template <int N>
+constexpr int slab_tpl() { return fft_tpl<N, N, slab_block(N)>(); }
+template <int N>
+constexpr int slab_pitch() { return N + (slab_tpl<N>() < 2 ? 2 : slab_tpl<N>()); }
 constexpr int kPencilBlock = 512;
 constexpr int kFinishBlock = 256;
 constexpr int kPrepBlocks = 64;
@@ -92,10 +112,13 @@ template <> struct FusedRadix<128, 0> { using type = Radices<8, 4, 4>; };
 template <> struct FusedRadix<128, 1> { using type = Radices<4, 4, 8>; };
 template <> struct FusedRadix<128, 2> { using type = Radices<2, 8, 8>; };
 
-// Copy COUNT 16-byte words from global memory to LDS: every thread issues
-// all of its loads before its first LDS write, so the loads overlap.
-template <int COUNT, int BLOCK>
-__device__ __forceinline__ void stage_to_lds(float4* __restrict__ lds, const float4* __restrict__ g) {
+// Copy a row-major N x N complex slab from global memory to LDS rows of
+// pitch RS, two entries per 16-byte word: every thread issues all of its
+// loads before its first LDS write, so the loads overlap.
+template <int N, int RS, int BLOCK>
+__device__ __forceinline__ void stage_rows_to_lds(float4* __restrict__ lds, const float4* __restrict__ g) {
+    static_assert(N % 2 == 0 && RS % 2 == 0, "two complex entries per 16-byte word");
+    constexpr int COUNT = N * N / 2;
     constexpr int PER = (COUNT + BLOCK - 1) / BLOCK;
     float4 r[PER];
 #pragma unroll
@@ -106,7 +129,7 @@ __device__ __forceinline__ void stage_to_lds(float4* __restrict__ lds, const flo
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
         const int i = threadIdx.x + p * BLOCK;
-        if (COUNT % BLOCK == 0 || i < COUNT) lds[i] = r[p];
+        if (COUNT % BLOCK == 0 || i < COUNT) lds[((2 * i / N) * RS + 2 * i % N) / 2] = r[p];
     }
 }
 
@@ -557,7 +580,9 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
             // 3D grids: the rotation's column tiles; planar: the slab
             slab_fft_store_fast<N>(acc, tw, inv, planar ? out : slabs + int64_t(rot) * nz * N * N, planar == 0, z);
         } else {
-            // padded planes -> interleaved complex, in place: read everything, then write
+            // padded planes -> padded complex rows, in place: read everything, then write
+            constexpr int TPL = slab_tpl<N>(), RS = slab_pitch<N>();
+            static_assert(2 * N * RS <= L::kInts, "the complex slab must fit the integer planes");
             cf* slab = reinterpret_cast<cf*>(acc);
             constexpr int PER = (N * N + B - 1) / B;
             cf v[PER];
@@ -573,14 +598,14 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
                 const int i = threadIdx.x + p * B;
-                if ((N * N) % B == 0 || i < N * N) slab[i] = v[p];
+                if ((N * N) % B == 0 || i < N * N) slab[(i / N) * RS + i % N] = v[p];
             }
             __syncthreads();
-            lds_fft_lines<float, N, -1, false, Plan>(slab, 1, N, N, tw);  // along x
-            lds_fft_lines<float, N, -1, true, Plan>(slab, N, 1, N, tw);   // along y
+            lds_fft_lines<float, N, -1, false, Plan, TPL>(slab, 1, RS, N, tw);  // along x
+            lds_fft_lines<float, N, -1, true, Plan, TPL>(slab, RS, 1, N, tw);   // along y
             // the (-1)^(kx + ky) of the N / 2 shift
             for (int i = threadIdx.x; i < N * N; i += B) {
-                const cf v = slab[i];
+                const cf v = slab[(i / N) * RS + i % N];
                 out[i] = ((i % N + i / N) & 1) ? mk(-v.re, -v.im) : v;
             }
         }
@@ -1286,7 +1311,8 @@ __global__ __launch_bounds__(slab_block(N)) void islab_peak_kernel(const cf* __r
     constexpr int B = slab_block(N), NW = islab_waves(N);
     using Plan = typename FusedRadix<N, P>::type;
     constexpr bool kFast = SlabLayout<N>::kFast;
-    __shared__ cf slab[kFast ? N * (N + N / 16 + 4) : N * N];
+    constexpr int TPL = slab_tpl<N>(), RS = slab_pitch<N>();  // generic sizes
+    __shared__ cf slab[kFast ? N * (N + N / 16 + 4) : N * RS];
     __shared__ cf tw[N];
     fill_twiddles<float, N>(tw);
     const int npair = (n_rot + 1) / 2;
@@ -1315,12 +1341,12 @@ __global__ __launch_bounds__(slab_block(N)) void islab_peak_kernel(const cf* __r
             islab_fft_argmax_fast<N>(pre, nx < items ? src_of(nx) : nullptr, slab, tw, zoff, va, ia, vb, ib,
                                      grouped);
         } else {
-            stage_to_lds<N * N / 2, B>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
+            stage_rows_to_lds<N, RS, B>(reinterpret_cast<float4*>(slab), reinterpret_cast<const float4*>(src));
             __syncthreads();
-            lds_fft_lines<float, N, 1, true, Plan>(slab, N, 1, N, tw);   // along y
-            lds_fft_lines<float, N, 1, false, Plan>(slab, 1, N, N, tw);  // along x
+            lds_fft_lines<float, N, 1, true, Plan, TPL>(slab, RS, 1, N, tw);   // along y
+            lds_fft_lines<float, N, 1, false, Plan, TPL>(slab, 1, RS, N, tw);  // along x
             for (int i = threadIdx.x; i < N * N; i += B) {
-                const cf v = slab[i];
+                const cf v = slab[(i / N) * RS + i % N];
                 take(v.re, zoff + i, va, ia);
                 take(v.im, zoff + i, vb, ib);
             }
