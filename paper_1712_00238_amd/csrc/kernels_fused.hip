@@ -205,10 +205,12 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 }
 
 // ------------------------------------------------------------------ K1
-// Slab layout.  The scatter accumulates into padded integer rows: row y
-// holds the re plane (N ints), the im plane (N ints) and 24 pad ints, so
-// consecutive rows start 24 banks apart (unpadded rows put every row on the
-// same banks and double the scatter's conflict stalls).  Positions are stored
+// Slab layout.  The scatter accumulates into padded rows of 64-bit words:
+// row y holds one word per node x, im 2^32 + re of the node's two
+// fixed-point sums (one 64-bit LDS add per node instead of two 32-bit ones),
+// and 8 pad words, so consecutive rows start 16 banks apart (unpadded rows
+// put every row on the same banks and double the scatter's conflict stalls;
+// of the pads tried, 8 words was fastest at N = 128).  Positions are stored
 // shifted by N / 2 in x and y, which the fitting rule for the rotated body box
 // (checked by the ABI for every size) keeps inside [0, N), so no index wraps
 // and the 16 stencil addresses of a sample are one base plus constant
@@ -222,11 +224,11 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 template <int N>
 struct SlabLayout {
     static constexpr bool kFast = N == 64 || N == 128;
-    static constexpr int kRowInts = 2 * N + 24;      // ints per accumulation row
-    static constexpr int kImOff = N;                 // im plane offset in a row (ints)
+    static constexpr int kRowInts = 2 * N + 16;      // 32-bit words per accumulation row
     static constexpr int kInts = N * kRowInts;       // >= 2 N N: room for the complex slab
-    static constexpr int kRowCf = kRowInts / 2;      // complex stride after conversion (fast)
+    static constexpr int kRowCf = kRowInts / 2;      // 64-bit node words per row = complex stride (fast)
     static constexpr int kShift = N / 2;
+    static_assert(!kFast || kRowCf >= N + N / 16, "a converted row (N entries and N / 16 gaps) fits its row");
 };
 
 __device__ __forceinline__ int fixed_rpi(float v) {
@@ -237,23 +239,36 @@ __device__ __forceinline__ int fixed_rpi(float v) {
 }
 
 // Add a 4 x 4 stencil of fixed-point values (re in vr, im in vi, index
-// 4 b + a for node (ix + a, iy + b)) to the slab planes.
+// 4 b + a for node (ix + a, iy + b)) to the slab's node words.  A word gets
+// im 2^32 + re with re sign-extended: its high half is im minus the borrow
+// of a negative re.
 template <int N>
 __device__ __forceinline__ void flush_stencil(int* __restrict__ acc, int ix, int iy, const int vr[16],
                                               const int vi[16]) {
     using L = SlabLayout<N>;
-    const int base = int(__umul24(unsigned(iy + L::kShift), unsigned(L::kRowInts))) + ix + L::kShift;
+    unsigned long long* acc64 = reinterpret_cast<unsigned long long*>(acc);
+    const int base = int(__umul24(unsigned(iy + L::kShift), unsigned(L::kRowCf))) + ix + L::kShift;
 #pragma unroll
     for (int b = 0; b < 4; ++b) {
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-            atomicAdd(acc + base + b * L::kRowInts + a, vr[4 * b + a]);
-            atomicAdd(acc + base + b * L::kRowInts + L::kImOff + a, vi[4 * b + a]);
+            const int re = vr[4 * b + a], im = vi[4 * b + a];
+            const unsigned long long v =
+                (static_cast<unsigned long long>(unsigned(im + (re >> 31))) << 32) | unsigned(re);
+            atomicAdd(acc64 + base + b * L::kRowCf + a, v);
         }
     }
 }
 
-// Spread the samples of one (rotation, z-slab) item into the integer planes.
+// The (re, im) sums of a node from its 64-bit word: the word holds
+// im 2^32 + re exactly (modulo 2^64), so with both sums in int32 range the
+// low half is re and the high half is im minus the borrow of a negative re.
+__device__ __forceinline__ void unpack_node(unsigned long long s, int& re, int& im) {
+    re = int(unsigned(s));
+    im = int(unsigned(s >> 32)) - (re >> 31);
+}
+
+// Spread the samples of one (rotation, z-slab) item into the slab's node words.
 // lines of a (rotation, slab) item compacted per round; the list of their
 // runs lives in LDS next to the slab
 constexpr int kLineChunk = 4096;
@@ -437,7 +452,7 @@ __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory")
 // Along x, 8 consecutive lanes own one row for both passes (radix R1, then
 // radix 8 with twiddles), so the x transform needs no block barrier: one
 // wave's LDS operations complete in issue order.  The first pass reads the
-// integer planes and converts.  Along y, pass C (radix R1) is split by a
+// node words and converts.  Along y, pass C (radix R1) is split by a
 // barrier between its reads and writes; pass D (radix 8) reads, writes the
 // result to global memory with the (-1)^(kx+ky) shift correction, and
 // clears the LDS words it read for the next item.
@@ -463,7 +478,8 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
 #pragma unroll
             for (int r = 0; r < R1; ++r) {
                 const int x = j + 8 * r;
-                const int a = acc[y * L::kRowInts + x], b = acc[y * L::kRowInts + L::kImOff + x];
+                int a, b;
+                unpack_node(reinterpret_cast<const unsigned long long*>(acc)[y * L::kRowCf + x], a, b);
                 any |= a | b;
                 v[r] = mk(float(a) * inv, float(b) * inv);
             }
@@ -544,7 +560,7 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
     constexpr int B = slab_block(N);
     using L = SlabLayout<N>;
     using Plan = typename FusedRadix<N, P>::type;
-    __shared__ int acc[L::kInts];
+    __shared__ __align__(16) int acc[L::kInts];
     __shared__ cf tw[N];
     __shared__ int list[kLineChunk];  // packed (i1, i2, lo, hi) of the lines that reach the slab
     __shared__ int nlist;
@@ -580,9 +596,9 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
             // 3D grids: the rotation's column tiles; planar: the slab
             slab_fft_store_fast<N>(acc, tw, inv, planar ? out : slabs + int64_t(rot) * nz * N * N, planar == 0, z);
         } else {
-            // padded planes -> padded complex rows, in place: read everything, then write
+            // node words -> padded complex rows, in place: read everything, then write
             constexpr int TPL = slab_tpl<N>(), RS = slab_pitch<N>();
-            static_assert(2 * N * RS <= L::kInts, "the complex slab must fit the integer planes");
+            static_assert(2 * N * RS <= L::kInts, "the complex slab must fit the node words");
             cf* slab = reinterpret_cast<cf*>(acc);
             constexpr int PER = (N * N + B - 1) / B;
             cf v[PER];
@@ -590,8 +606,9 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
             for (int p = 0; p < PER; ++p) {
                 const int i = threadIdx.x + p * B;
                 if ((N * N) % B == 0 || i < N * N) {
-                    const int row = (i / N) * L::kRowInts + i % N;
-                    v[p] = mk(float(acc[row]) * inv, float(acc[row + L::kImOff]) * inv);
+                    int a, b;
+                    unpack_node(reinterpret_cast<const unsigned long long*>(acc)[(i / N) * L::kRowCf + i % N], a, b);
+                    v[p] = mk(float(a) * inv, float(b) * inv);
                 }
             }
             __syncthreads();
