@@ -989,6 +989,9 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
     constexpr int NL = 2 * W * GR;  // lines: (rotation, tile, column)
     constexpr bool kFast = NZ == N && SlabLayout<N>::kFast;
     __shared__ cf buf[kFast ? NZ * (NL + 8) : NZ * NL];
+    // generic sizes: the item's values of the group's first fixed spectrum,
+    // loaded with the slab tiles so that the product does not wait on them
+    __shared__ cf sbuf[kFast ? 1 : 2 * NZ * W];
     __shared__ cf tw[NZ > 1 ? NZ : 1];
     __shared__ const cf* spec_of[GR];
     __shared__ int zr_of[GR][2];  // slab range [zlo, zhi] of each rotation of the group
@@ -1051,10 +1054,13 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
             continue;
         }
         // load both tiles of every rotation of the group (zeros for missing
-        // rotations); all loads of a thread are issued before its LDS writes
+        // rotations) and the first rotation's spectrum values; all loads of a
+        // thread are issued before its LDS writes
         {
             constexpr int TOT = GR * 2 * NZ * W;
             constexpr int PER = (TOT + kPencilBlock - 1) / kPencilBlock;
+            constexpr int STOT = 2 * NZ * W;
+            constexpr int SPER = (STOT + kPencilBlock - 1) / kPencilBlock;
             cf v[PER];
 #pragma unroll
             for (int p = 0; p < PER; ++p) {
@@ -1081,6 +1087,23 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
                     buf[kz * NL + line_of(r, t, cc)] = v[p];
                 }
             }
+            const cf* sp0 = spec_of[0];  // the group's first rotation exists
+            cf sv[SPER];
+#pragma unroll
+            for (int p = 0; p < SPER; ++p) {
+                const int i = threadIdx.x + p * kPencilBlock;
+                if (STOT % kPencilBlock == 0 || i < STOT) {
+                    const int cc = i % W;
+                    const int kz = (i / W) % NZ;
+                    const int t = i / (W * NZ);
+                    sv[p] = sp0[(int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc)];
+                }
+            }
+#pragma unroll
+            for (int p = 0; p < SPER; ++p) {
+                const int i = threadIdx.x + p * kPencilBlock;
+                if (STOT % kPencilBlock == 0 || i < STOT) sbuf[i] = sv[p];
+            }
         }
         __syncthreads();
         if constexpr (NZ > 1) lds_fft_lines<float, NZ, -1, true, Plan>(buf, NL, 1, NL, tw);
@@ -1090,8 +1113,8 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
             const int kz = (i / W) % NZ;
             const int t = i / (W * NZ);
             const int64_t off = (int64_t(kz) * N + kyt[t]) * N + kx_of(t, cc);
-            const cf* prev = nullptr;
-            cf sv = mk(0.f, 0.f);
+            const cf* prev = spec_of[0];
+            cf sv = sbuf[i];
 #pragma unroll
             for (int r = 0; r < GR; ++r) {
                 const cf* sp = spec_of[r];
