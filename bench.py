@@ -36,10 +36,16 @@ KERNEL_SOURCES = ["paper_1712_00238_amd/csrc/kernels_fused.hip", "paper_1712_002
 
 
 def sources_sha() -> str:
+    """Hash of the kernel sources' code: line comments and blank space are
+    dropped first, so an edit of a comment keeps the stored counters valid
+    while any change to the code itself invalidates them."""
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            for line in f:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

@@ -7,10 +7,11 @@
 //                   within the B-spline support of this slab, forward 2D
 //                   FFT over (x, y) in LDS, one coalesced write of the slab.
 //                   The scatter accumulates 32-bit fixed-point values with
-//                   LDS integer atomics: on gfx950 these run several times
-//                   faster than LDS float atomics, and integer sums do not
-//                   depend on the order of the additions, so the spread is
-//                   bitwise deterministic.  The scale leaves 8x headroom over
+//                   LDS integer atomics (a node's re and im in one 64-bit
+//                   word, one add per node): on gfx950 these run several
+//                   times faster than LDS float atomics, and integer sums do
+//                   not depend on the order of the additions, so the spread
+//                   is bitwise deterministic.  The scale leaves 8x headroom over
 //                   max |c_k| (the B-spline weights of a unit-density lattice
 //                   sum to about one at every node); two's-complement
 //                   wrap-around of partial sums cancels as long as the final
