@@ -121,12 +121,39 @@ __device__ __forceinline__ void dft16(cplx<T>* v) {
         for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
     }
 }
+// 12 = 4 x 3: DFT4 over n1 of x[3 n1 + n2], twiddle by w12^(n2 k1), DFT3
+// over n2; output k1 + 4 k2
+template <typename T, int S>
+__device__ __forceinline__ void dft12(cplx<T>* v) {
+    const T h = T(0.86602540378443864676), q = T(0.5);  // cos 30 deg, sin 30 deg
+    cplx<T> a[3][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[3 * n1 + n2];
+        dft4<T, S>(a[n2]);
+    }
+    a[1][1] = rot_by<T, S>(a[1][1], h, q);   // w^1
+    a[1][2] = rot_by<T, S>(a[1][2], q, h);   // w^2
+    a[1][3] = mul_i<T, S>(a[1][3]);          // w^3
+    a[2][1] = rot_by<T, S>(a[2][1], q, h);   // w^2
+    a[2][2] = rot_by<T, S>(a[2][2], -q, h);  // w^4
+    a[2][3] = mk(-a[2][3].re, -a[2][3].im);  // w^6
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cplx<T> b[3] = {a[0][k1], a[1][k1], a[2][k1]};
+        dft3<T, S>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < 3; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+}
 template <typename T, int S, int R>
 __device__ __forceinline__ void dftR(cplx<T>* v) {
     if constexpr (R == 2) dft2<T, S>(v);
     else if constexpr (R == 3) dft3<T, S>(v);
     else if constexpr (R == 4) dft4<T, S>(v);
     else if constexpr (R == 8) dft8<T, S>(v);
+    else if constexpr (R == 12) dft12<T, S>(v);
     else if constexpr (R == 16) dft16<T, S>(v);
 }
 

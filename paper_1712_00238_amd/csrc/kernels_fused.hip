@@ -225,11 +225,14 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 template <int N>
 struct SlabLayout {
     static constexpr bool kFast = N == 64 || N == 128;
+    // the spread kernel's register-resident slab transform (8 lanes per
+    // row): the fast sizes and N = 96 (radix 12 x 8, row-major store)
+    static constexpr bool kRowFft = kFast || N == 96;
     static constexpr int kRowInts = 2 * N + 16;      // 32-bit words per accumulation row
     static constexpr int kInts = N * kRowInts;       // >= 2 N N: room for the complex slab
     static constexpr int kRowCf = kRowInts / 2;      // 64-bit node words per row = complex stride (fast)
     static constexpr int kShift = N / 2;
-    static_assert(!kFast || kRowCf >= N + N / 16, "a converted row (N entries and N / 16 gaps) fits its row");
+    static_assert(!kRowFft || kRowCf >= N + N / 16, "a converted row (N entries and N / 16 gaps) fits its row");
 };
 
 __device__ __forceinline__ int fixed_rpi(float v) {
@@ -449,7 +452,7 @@ __device__ __forceinline__ void spread_item(int* __restrict__ acc, const FusedRo
 
 __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
 
-// Forward 2D DFT of the padded slab (N = 8 R1, R1 = 8 or 16) and its store.
+// Forward 2D DFT of the padded slab (N = 8 R1, R1 = 8, 12 or 16) and its store.
 // Along x, 8 consecutive lanes own one row for both passes (radix R1, then
 // radix 8 with twiddles), so the x transform needs no block barrier: one
 // wave's LDS operations complete in issue order.  The first pass reads the
@@ -495,8 +498,9 @@ __device__ __forceinline__ void slab_fft_store_fast(int* __restrict__ acc, const
             for (int r = 0; r < R1; ++r) slab[y * RS + px(j * R1 + r)] = v[r];
             compiler_fence();
 #pragma unroll
-            for (int m = 0; m < NB / 8; ++m) {
+            for (int m = 0; m < (NB + 7) / 8; ++m) {
                 const int jj = j + 8 * m;  // k = jj
+                if (NB % 8 != 0 && jj >= NB) break;  // R1 = 12: lanes 0-3 take a second butterfly
                 cf u[8];
 #pragma unroll
                 for (int r = 0; r < 8; ++r) u[r] = slab[y * RS + px(jj + NB * r)];
@@ -528,8 +532,9 @@ x_done:
     }
     if (on) {
 #pragma unroll
-        for (int m = 0; m < NB / 8; ++m) {
+        for (int m = 0; m < (NB + 7) / 8; ++m) {
             const int jj = jb + 8 * m;
+            if (NB % 8 != 0 && jj >= NB) break;
             cf u[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + px(x)];
@@ -570,7 +575,7 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
     fill_twiddles<float, N>(tw);
     const int nz = planar ? 1 : N;
     const int items = nz * n_rot;
-    if constexpr (L::kFast) {
+    if constexpr (L::kRowFft) {
         for (int i = threadIdx.x; i < L::kInts; i += B) acc[i] = 0;  // later items clear as they store
     }
     for (int item = blockIdx.x; item < items; item += gridDim.x) {
@@ -585,7 +590,7 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
         if (nz > 1 && (zc < fr.zlo || zc > fr.zhi)) continue;  // uniform: the slab is zero and is not written
         const FusedJob jb = jobs[fr.job];
         __syncthreads();  // previous item done with the slab
-        if constexpr (!L::kFast) {
+        if constexpr (!L::kRowFft) {
             for (int i = threadIdx.x; i < L::kInts; i += B) acc[i] = 0;
             __syncthreads();
         }
@@ -596,6 +601,8 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
         if constexpr (L::kFast) {
             // 3D grids: the rotation's column tiles; planar: the slab
             slab_fft_store_fast<N>(acc, tw, inv, planar ? out : slabs + int64_t(rot) * nz * N * N, planar == 0, z);
+        } else if constexpr (L::kRowFft) {
+            slab_fft_store_fast<N>(acc, tw, inv, out, false, z);  // row-major slab
         } else {
             // node words -> padded complex rows, in place: read everything, then write
             constexpr int TPL = slab_tpl<N>(), RS = slab_pitch<N>();
@@ -1256,7 +1263,7 @@ __device__ __forceinline__ void take(float v, int i, float& bv, int& bi) {
     }
 }
 
-// Inverse 2D DFT of one folded slab (N = 8 R1, R1 = 8 or 16) with the
+// Inverse 2D DFT of one folded slab (N = 8 R1, R1 = 8, 12 or 16) with the
 // per-thread argmax of its real (rotation A) and imaginary (rotation B)
 // parts.  Pass A (radix R1 along y) takes its inputs from registers loaded
 // from global memory one item ahead; pass B (radix 8) runs in place; along x,
@@ -1287,8 +1294,9 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
     __syncthreads();
     if (on) {
 #pragma unroll
-        for (int m = 0; m < NB / 8; ++m) {
+        for (int m = 0; m < (NB + 7) / 8; ++m) {
             const int jj = jb + 8 * m;
+            if (NB % 8 != 0 && jj >= NB) break;  // R1 = 12: lanes 0-3 take a second butterfly
             cf u[8];
 #pragma unroll
             for (int r = 0; r < 8; ++r) u[r] = slab[(jj + NB * r) * RS + px(x)];
@@ -1315,33 +1323,38 @@ __device__ __forceinline__ void islab_fft_argmax_fast(cf* pre, const cf* __restr
 #pragma unroll
         for (int r = 0; r < R1; ++r) slab[y * RS + px(j * R1 + r)] = v[r];
         compiler_fence();
-        cf u[NB / 8][8];
+        constexpr int MB = (NB + 7) / 8;  // butterflies per lane (lanes 0-3 of N = 96 take 2, 4-7 take 1)
+        const bool two = NB % 8 == 0 || j + 8 * (MB - 1) < NB;
+        cf u[MB][8];
 #pragma unroll
-        for (int m = 0; m < NB / 8; ++m) {
+        for (int m = 0; m < MB; ++m) {
             const int jj = j + 8 * m;
+            if (NB % 8 != 0 && m == MB - 1 && !two) break;
 #pragma unroll
             for (int r = 0; r < 8; ++r) u[m][r] = slab[y * RS + px(jj + NB * r)];
 #pragma unroll
             for (int r = 1; r < 8; ++r) u[m][r] = u[m][r] * conj(tw[r * jj]);
             dft8<float, 1>(u[m]);
         }
-        // visit the outputs in increasing index (x = j + 8 m + NB r = j + 8 s
-        // with slot s = m + (NB / 8) r): a strict comparison then keeps the
-        // lowest index among equal values; the slot is turned into the flat
-        // index once
+        // visit the outputs in increasing index (x = j + 8 m + NB r): a
+        // strict comparison then keeps the lowest index among equal values;
+        // the slot (x - j) / 8 when NB is a multiple of 8, else x - j, is
+        // turned into the flat index once
+        constexpr int SU = NB % 8 == 0 ? 8 : 1;  // index units per slot
         int sa = -1, sb = -1;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
 #pragma unroll
-            for (int m = 0; m < NB / 8; ++m) {
-                const int slot = m + (NB / 8) * r;
+            for (int m = 0; m < MB; ++m) {
+                if (NB % 8 != 0 && m == MB - 1 && !two) continue;
+                const int slot = (8 * m + NB * r) / SU;
                 if (u[m][r].re > va) { va = u[m][r].re; sa = slot; }
                 if (u[m][r].im > vb) { vb = u[m][r].im; sb = slot; }
             }
         }
         const int row = zoff + y * N + j;
-        if (sa >= 0) ia = row + 8 * sa;
-        if (sb >= 0) ib = row + 8 * sb;
+        if (sa >= 0) ia = row + SU * sa;
+        if (sb >= 0) ib = row + SU * sb;
     }
 }
 
@@ -1351,14 +1364,16 @@ __global__ __launch_bounds__(slab_block(N)) void islab_peak_kernel(const cf* __r
                                                                     float* __restrict__ pval, int* __restrict__ pidx) {
     constexpr int B = slab_block(N), NW = islab_waves(N);
     using Plan = typename FusedRadix<N, P>::type;
-    constexpr bool kFast = SlabLayout<N>::kFast;
+    // register-resident transform: the fast sizes (pair-grouped columns in
+    // 3D) and N = 96 (radix 12 x 8, row-major slabs)
+    constexpr bool kFast = SlabLayout<N>::kRowFft;
     constexpr int TPL = slab_tpl<N>(), RS = slab_pitch<N>();  // generic sizes
     __shared__ cf slab[kFast ? N * (N + N / 16 + 4) : N * RS];
     __shared__ cf tw[N];
     fill_twiddles<float, N>(tw);
     const int npair = (n_rot + 1) / 2;
     const int items = nz * npair;
-    const bool grouped = nz == N;
+    const bool grouped = nz == N && SlabLayout<N>::kFast;
     auto src_of = [&](int item) { return packed + (int64_t(item / nz) * nz + item % nz) * N * N; };
     cf pre[kFast ? N / 8 : 1];
     if constexpr (kFast) {
