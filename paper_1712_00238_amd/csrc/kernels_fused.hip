@@ -638,6 +638,47 @@ __global__ __launch_bounds__(slab_block(N)) void spread_slab_kernel(const FusedR
 }
 
 // ------------------------------------------------------------------ K2
+// z transform of LINES lines of NZ = 8 R1 points held at buf[kz * NL + l]
+// (generic pencils; R1 = 12): thread (l, jb), jb < 8, takes the points
+// kz = jb + 8 r into registers for a radix-R1 DFT, then runs radix 8 with
+// twiddles on rows jj + R1 r (jj = jb, and jb + 8 while below R1), which no
+// other thread touches; natural order out.  Two barriers instead of the
+// Stockham passes' six per round.  Every thread of the block calls it.
+template <int NZ, int S, int NL, int LINES, int BLOCK>
+__device__ __forceinline__ void zfft_lines_r8(cf* __restrict__ buf, const cf* __restrict__ tw) {
+    constexpr int R1 = NZ / 8, NB = NZ / 8;
+    static_assert(NZ % 8 == 0 && LINES <= NL && NL * 8 <= BLOCK, "one thread per (line, jb)");
+    const int l = int(threadIdx.x) % NL, jb = int(threadIdx.x) / NL;
+    const bool on = l < LINES && jb < 8;
+    cf v[R1];
+    if (on) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = buf[(jb + 8 * r) * NL + l];
+        dftR<float, S, R1>(v);
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) buf[(jb * R1 + r) * NL + l] = v[r];
+    }
+    __syncthreads();
+    if (on) {
+#pragma unroll
+        for (int m = 0; m < (NB + 7) / 8; ++m) {
+            const int jj = jb + 8 * m;
+            if (NB % 8 != 0 && jj >= NB) break;
+            cf u[8];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) u[r] = buf[(jj + NB * r) * NL + l];
+#pragma unroll
+            for (int r = 1; r < 8; ++r) u[r] = u[r] * (S < 0 ? tw[r * jj] : conj(tw[r * jj]));
+            dft8<float, S>(u);
+#pragma unroll
+            for (int r = 0; r < 8; ++r) buf[(jj + NB * r) * NL + l] = u[r];
+        }
+    }
+    __syncthreads();
+}
 struct PencilJob {
     int ky, x0;
 };
@@ -1114,7 +1155,10 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
             }
         }
         __syncthreads();
-        if constexpr (NZ > 1) lds_fft_lines<float, NZ, -1, true, Plan>(buf, NL, 1, NL, tw);
+        if constexpr (NZ == 96 && NL * 8 <= kPencilBlock)
+            zfft_lines_r8<NZ, -1, NL, NL, kPencilBlock>(buf, tw);
+        else if constexpr (NZ > 1)
+            lds_fft_lines<float, NZ, -1, true, Plan>(buf, NL, 1, NL, tw);
         // product with each rotation's fixed spectrum (shared spectra hit in cache)
         for (int i = threadIdx.x; i < 2 * NZ * W; i += kPencilBlock) {
             const int cc = i % W;
@@ -1152,7 +1196,10 @@ __global__ __launch_bounds__(kPencilBlock, 4) void pencil_kernel(const FusedRot*
             buf[mkz * NL + a1] = mk(ha.re + hb.im, hb.re - ha.im);
         }
         __syncthreads();
-        if constexpr (NZ > 1) lds_fft_lines<float, NZ, 1, true, Plan>(buf, NL, 1, GR * W, tw);
+        if constexpr (NZ == 96 && NL * 8 <= kPencilBlock)
+            zfft_lines_r8<NZ, 1, NL, GR * W, kPencilBlock>(buf, tw);
+        else if constexpr (NZ > 1)
+            lds_fft_lines<float, NZ, 1, true, Plan>(buf, NL, 1, GR * W, tw);
         // write the folded pencils of each pair
         const int pair0 = g0 / 2;
         for (int i = threadIdx.x; i < (GR / 2) * 2 * NZ * W; i += kPencilBlock) {
