@@ -297,7 +297,11 @@ def test_score_volume_direct_sum_tiny(ctxs):
                                                     # edge of the unwrapped slab; 71 is odd: generic lane map)
                                                     (64, 34, False, 3, 2), (128, 71, False, 2, 2),
                                                     # four rotations per pencil item (group 4) at the two-pass sizes
-                                                    (64, 24, False, 7, -8), (128, 40, False, 5, -4)])
+                                                    (64, 24, False, 7, -8), (128, 40, False, 5, -4),
+                                                    # N = 96 (radix 12 x 8 slab and z transforms): the largest box
+                                                    # the fitting rule admits (odd), group 4, planar
+                                                    (96, 53, False, 3, 2), (96, 40, False, 5, -4),
+                                                    (96, 40, True, 5, 4)])
 def test_score_rotations_peaks_f32(ctxs, path, n, nm, planar, nrot, batch):
     # batch < 0: batch |batch| with pencil groups of 4 rotations
     ctx = ctxs["f32"]
@@ -567,6 +571,26 @@ def _phi_sum(rho_f, nm, poses, gs):
         val, _ = og.phi_and_grad(rho_f, y, want_grad=False)
         acc += gs[b] * val
     return acc
+
+
+@pytest.mark.parametrize("n,nm", [(64, 32), (96, 48), (128, 40)])
+def test_fused_search_repeats_bit_for_bit(ctxs, n, nm):
+    """The fused search accumulates its spread in integers and reduces its
+    peaks in fixed orders, so repeated calls (with the batch split into
+    several launches) agree bit for bit at the sizes with register-resident
+    slab transforms."""
+    ctx = ctxs["f32"]
+    ctx.set_option("batch", 4)
+    try:
+        gf, gm, rho_f, rho_m, w = small_case(n, nm, False, 900 + n)
+        quats = wr.uniform_quaternions(9, 70 + n)
+        spec = ctx.spectrum(rho_f, gf)
+        flush_print("fused repeat", n, nm)
+        runs = [{k: to_np(v) for k, v in ctx.score_rotations(spec, gf, rho_m, w, gm, quats).items() if v is not None}
+                for _ in range(3)]
+        assert all(np.array_equal(runs[0][k], r[k]) for r in runs[1:] for k in runs[0])
+    finally:
+        ctx.set_option("batch", 64)
 
 
 @pytest.mark.parametrize("n,nm", [(16, 6), (24, 8)])
