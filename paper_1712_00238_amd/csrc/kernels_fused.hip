@@ -217,11 +217,11 @@ __global__ void cmax_final_kernel(const FusedJob* __restrict__ jobs, const float
 // and the 16 stencil addresses of a sample are one base plus constant
 // offsets.  The shift multiplies the slab's 2D DFT by (-1)^(kx+ky), removed
 // when the slab is written (or folded into the pair-grouped spectrum).  At
-// N = 64 and 128 (kFast) the complex row that replaces a row after
-// conversion has N + 8 entries, entry e at e + e / 16, so that the radix-16
-// pass along x, which writes 16 consecutive entries per lane, does not put
-// the 8 lanes of a row on the same banks; the other sizes convert to an
-// interleaved complex N x N slab for the generic transforms.
+// N = 64, 96 and 128 (kRowFft) the complex row that replaces a row after
+// conversion keeps entry e at e + e / 16, so that the radix-16 (12) pass
+// along x, which writes consecutive entries per lane, does not put the 8
+// lanes of a row on the same banks; the other sizes convert to complex rows
+// of pitch slab_pitch for the generic transforms.
 template <int N>
 struct SlabLayout {
     static constexpr bool kFast = N == 64 || N == 128;
