@@ -1500,10 +1500,28 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
     float bv = -INFINITY;
     int bi = 0x7fffffff;
     constexpr int NW = islab_waves(N);
-    for (int i = threadIdx.x; i < nz * NW; i += kFinishBlock) {
-        const float v = pval[int64_t(rot) * nz * NW + i];
-        const int id = pidx[int64_t(rot) * nz * NW + i];
-        if (better(v, id, bv, bi)) { bv = v; bi = id; }
+    {
+        // every partial of the thread loaded before the first comparison (the
+        // (value, lowest index) order is total, so the visiting order does
+        // not matter); nz is N or 1
+        constexpr int PB = (N * NW + kFinishBlock - 1) / kFinishBlock;
+        const float* pv = pval + int64_t(rot) * nz * NW;
+        const int* pi = pidx + int64_t(rot) * nz * NW;
+        float vv[PB];
+        int ii[PB];
+#pragma unroll
+        for (int p = 0; p < PB; ++p) {
+            const int i = int(threadIdx.x) + p * kFinishBlock;
+            vv[p] = -INFINITY;
+            ii[p] = 0x7fffffff;
+            if (i < nz * NW) {
+                vv[p] = pv[i];
+                ii[p] = pi[i];
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < PB; ++p)
+            if (better(vv[p], ii[p], bv, bi)) { bv = vv[p]; bi = ii[p]; }
     }
     sv[threadIdx.x] = bv;
     si[threadIdx.x] = bi;
@@ -1526,18 +1544,28 @@ __global__ __launch_bounds__(kFinishBlock) void finish_slab_kernel(const cf* __r
     // inner sums along x: two threads per row ky, each half of the row's
     // stored positions
     const bool grouped = nz == N && (N == 64 || N == 128);
+    // (the loads of HB positions are issued together: one at a time, each
+    // waited on before the next, the loop ran at cache latency)
+    constexpr int HB = N / 2 >= 16 ? 16 : N / 2;
+    static_assert((N / 2) % HB == 0, "whole batches of positions");
     for (int w = threadIdx.x; w < 2 * N; w += kFinishBlock) {
         const int ky = w >> 1, half = w & 1;
         double ar[3] = {0, 0, 0}, ai[3] = {0, 0, 0};
-        for (int px = half * (N / 2); px < (half + 1) * (N / 2); ++px) {
-            const cf v = sl[ky * N + px];
-            const int kx = grouped ? col_kx<N>(px) : px;
-            const double vr = v.re, vi = v.im;
+        for (int p0 = half * (N / 2); p0 < (half + 1) * (N / 2); p0 += HB) {
+            cf vb[HB];
 #pragma unroll
-            for (int j = 0; j < 3; ++j) {
-                const int m = (kx * xs[j]) % N;
-                ar[j] += vr * twr[m] - vi * twi[m];
-                ai[j] += vr * twi[m] + vi * twr[m];
+            for (int q = 0; q < HB; ++q) vb[q] = sl[ky * N + p0 + q];
+#pragma unroll
+            for (int q = 0; q < HB; ++q) {
+                const int px = p0 + q;
+                const int kx = grouped ? col_kx<N>(px) : px;
+                const double vr = vb[q].re, vi = vb[q].im;
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    const int m = (kx * xs[j]) % N;
+                    ar[j] += vr * twr[m] - vi * twi[m];
+                    ai[j] += vr * twi[m] + vi * twr[m];
+                }
             }
         }
 #pragma unroll
